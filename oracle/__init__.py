@@ -1,0 +1,211 @@
+"""Stark CPU oracle -- test infrastructure only.
+
+Plain FP64 CPU statements of what the Strassen hot path computes (Algorithm 1,
+Section III-A; divide / leaf / combine phases of Section III-C).  The C code in
+``oracle.c`` does the arithmetic; this module only builds it with gcc and
+marshals numpy arrays.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The GPU library (``paper_1811_07325_amd``) never imports it, and
+this package never imports that one.
+
+Pins (tests/test_oracle.py): brute force on small integers for every n <= 16
+and every depth, the 2x2 worked example of Algorithm 1, exact identities
+(A*I, I*B, 0*B, sign and power-of-two scaling), the structural counts of
+Section III-C-1 (7^k leaves, 18 additions per node, 4/2/2/4 quadrant uses) and
+the double-precision classical loop against numpy's BLAS matmul.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain IEEE, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Counts(ctypes.Structure):
+    """Structural counters of one Strassen run (see oracle.c)."""
+    _fields_ = [
+        ("leaf_products", ctypes.c_int64),
+        ("internal_nodes", ctypes.c_int64),
+        ("block_additions", ctypes.c_int64),
+        ("uses_a", ctypes.c_int64 * 4),
+        ("uses_b", ctypes.c_int64 * 4),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    lib.oracle_gemm_f64.argtypes = [P, P, P, I64]
+    lib.oracle_gemm_i64.argtypes = [P, P, P, I64]
+    lib.oracle_rows_f64.argtypes = [P, P, I64, P, I64, P]
+    lib.oracle_gemv_f64.argtypes = [P, P, P, I64]
+    lib.oracle_strassen_f64.argtypes = [P, P, P, I64, ctypes.c_int, I64, ctypes.POINTER(Counts)]
+    lib.oracle_strassen_f64.restype = ctypes.c_int
+    lib.oracle_divide_f32.argtypes = [P, I64, P, I64, I64, P, P]
+    lib.oracle_combine_f32.argtypes = [P, I64, P, I64]
+    lib.oracle_split_bf16.argtypes = [P, I64, ctypes.c_int, P]
+    lib.oracle_set_mutation.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _f64(a) -> np.ndarray:
+    """Exact widening of a float32 (or any real) array to contiguous float64."""
+    return np.ascontiguousarray(np.asarray(a), dtype=np.float64)
+
+
+def gemm_f64(A, B) -> np.ndarray:
+    """Classical product in FP64: C[i][j] = sum_t A[i][t] B[t][j]."""
+    A, B = _f64(A), _f64(B)
+    n = A.shape[0]
+    assert A.shape == (n, n) and B.shape == (n, n)
+    C = np.empty((n, n), dtype=np.float64)
+    _load().oracle_gemm_f64(_ptr(A), _ptr(B), _ptr(C), n)
+    return C
+
+
+def gemm_i64(A, B) -> np.ndarray:
+    """Classical product in exact 64-bit integer arithmetic (brute force)."""
+    A = np.ascontiguousarray(A, dtype=np.int64)
+    B = np.ascontiguousarray(B, dtype=np.int64)
+    n = A.shape[0]
+    C = np.empty((n, n), dtype=np.int64)
+    _load().oracle_gemm_i64(_ptr(A), _ptr(B), _ptr(C), n)
+    return C
+
+
+def rows_f64(A, B, rows) -> np.ndarray:
+    """Rows `rows` of the classical FP64 product (same loop order as gemm_f64)."""
+    A, B = _f64(A), _f64(B)
+    n = A.shape[0]
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    assert rows.min() >= 0 and rows.max() < n
+    out = np.empty((rows.size, n), dtype=np.float64)
+    _load().oracle_rows_f64(_ptr(A), _ptr(B), n, _ptr(rows), rows.size, _ptr(out))
+    return out
+
+
+def gemv_f64(M, x) -> np.ndarray:
+    """y = M x in FP64."""
+    M, x = _f64(M), _f64(x)
+    n = M.shape[0]
+    y = np.empty(n, dtype=np.float64)
+    _load().oracle_gemv_f64(_ptr(M), _ptr(x), _ptr(y), n)
+    return y
+
+
+def padded_size(n: int, depth: int, granule: int = 1) -> int:
+    """Smallest multiple of 2^depth * granule that is >= n."""
+    q = (1 << depth) * granule
+    return -(-n // q) * q
+
+
+def strassen_f64(A, B, depth: int, n_pad: int | None = None, with_counts: bool = False):
+    """C = A B by `depth` levels of Algorithm 1 on zero-padded operands, FP64."""
+    A, B = _f64(A), _f64(B)
+    n = A.shape[0]
+    assert A.shape == (n, n) and B.shape == (n, n)
+    if n_pad is None:
+        n_pad = padded_size(n, depth)
+    C = np.empty((n, n), dtype=np.float64)
+    cnt = Counts()
+    rc = _load().oracle_strassen_f64(_ptr(A), _ptr(B), _ptr(C), n, depth, n_pad, ctypes.byref(cnt))
+    if rc != 0:
+        raise ValueError(f"oracle_strassen_f64: bad arguments n={n} depth={depth} n_pad={n_pad}")
+    if with_counts:
+        return C, cnt
+    return C
+
+
+def divide_f32(X, Y):
+    """Operand pairs (S_i, T_i), i = 1..7, of one node in binary32 -> (7,h,h) x2."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    m = X.shape[0]
+    assert X.shape == (m, m) and Y.shape == (m, m) and m % 2 == 0
+    h = m // 2
+    S = np.empty((7, h, h), dtype=np.float32)
+    T = np.empty((7, h, h), dtype=np.float32)
+    _load().oracle_divide_f32(_ptr(X), m, _ptr(Y), m, m, _ptr(S), _ptr(T))
+    return S, T
+
+
+def combine_f32(M) -> np.ndarray:
+    """C (2h x 2h) from the seven products M (7,h,h) in binary32."""
+    M = np.ascontiguousarray(M, dtype=np.float32)
+    assert M.ndim == 3 and M.shape[0] == 7 and M.shape[1] == M.shape[2]
+    h = M.shape[1]
+    C = np.empty((2 * h, 2 * h), dtype=np.float32)
+    _load().oracle_combine_f32(_ptr(M), h, _ptr(C), 2 * h)
+    return C
+
+
+def split_bf16(x, terms: int = 2) -> np.ndarray:
+    """bfloat16 split planes (terms, *x.shape) as uint16 bit patterns (RNE)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    assert terms in (2, 3)
+    out = np.empty((terms,) + x.shape, dtype=np.uint16)
+    _load().oracle_split_bf16(_ptr(x), x.size, terms, _ptr(out))
+    return out
+
+
+def bf16_bits_to_f32(b) -> np.ndarray:
+    """Exact value of bfloat16 bit patterns as float32."""
+    return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+def set_mutation(m: int) -> None:
+    """Test hook: plant a known mistake in the oracle (0 = none)."""
+    _load().oracle_set_mutation(int(m))
+
+
+def rel_frobenius(C, ref) -> float:
+    """||C - ref||_F / ||ref||_F in FP64."""
+    C, ref = _f64(C), _f64(ref)
+    d = C - ref
+    return float(np.sqrt(np.sum(d * d)) / np.sqrt(np.sum(ref * ref)))
+
+
+def max_abs(C, ref) -> float:
+    return float(np.max(np.abs(_f64(C) - _f64(ref))))
+
+
+def freivalds_rel(A, B, C, x) -> float:
+    """||C x - A (B x)|| / ||A (B x)|| in FP64 (Freivalds 1977, Gaussian x).
+
+    For Gaussian x, E||E x||^2 = ||E||_F^2, so this estimates the relative
+    Frobenius error of C."""
+    Bx = gemv_f64(B, x)
+    ABx = gemv_f64(A, Bx)
+    Cx = gemv_f64(C, x)
+    return float(np.linalg.norm(Cx - ABx) / np.linalg.norm(ABx))

@@ -1,0 +1,353 @@
+/*
+ * Stark CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU statement of what the Strassen hot path
+ * computes.  Only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark may load this file; the GPU library never does, and the two
+ * share no code, headers or tables.
+ *
+ * Every floating-point routine works in IEEE binary64 on inputs that were
+ * converted exactly from binary32 (the paper computes in double precision
+ * throughout, Section V-A "Test Setup").  The FP32 step routines
+ * (oracle_divide_f32 / oracle_combine_f32) exist so the GPU's divide and
+ * combine kernels can be checked bit for bit: a single binary32 addition is
+ * correctly rounded on both sides, and the order of the additions is fixed
+ * below.
+ *
+ * Pins (what keeps this file honest; all run on the CPU):
+ *   - brute force: on small-integer inputs the Strassen recursion, the
+ *     classical triple loop, the int64 triple loop and numpy's integer matmul
+ *     agree exactly, for every n <= 16 and every depth (odd n padded);
+ *   - the 2x2 worked example of Algorithm 1 (golden file);
+ *   - identities A*I = A, I*B = B, 0*B = 0, (-A)*B = -(A*B),
+ *     (2^a A)(2^b B) = 2^(a+b) AB, which hold bit for bit;
+ *   - structure: 7^k leaf products, 18 block additions per internal node,
+ *     and each quadrant of A and B used 4/2/2/4 times per node (Section
+ *     III-C-1, Fig. 3);
+ *   - the classical loop against numpy/BLAS double matmul (library routine).
+ *
+ * Readings of the paper taken here (the paper is silent or misprinted):
+ *   - Algorithm 1 prints C22 = M1 - M2 - M3 + M6; the product it must equal
+ *     has +M3 (worked 2x2 example: the printed form gives 54, the product is
+ *     50).  The oracle uses C22 = M1 - M2 + M3 + M6.
+ *   - Algorithm 2 recurses on (A, B); the recursion must act on the divided
+ *     pairs D.  The oracle recurses on the seven (S_i, T_i) pairs.
+ *   - The base case "n = threshold" / "n = 1 block" is read as: recurse
+ *     exactly `depth` times; the leaf size is n_pad / 2^depth.
+ *   - Sizes that are not 2^p (the paper defers to partitioning) are
+ *     zero-padded to n_pad, a multiple of 2^depth, and the product cropped.
+ *     Padding is exact: the extra rows/columns contribute only zeros.
+ *   - The order of the combine additions is left to right as printed:
+ *     C11 = ((M1 + M4) - M5) + M7, C22 = ((M1 - M2) + M3) + M6.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math:
+ * every operation below is a plain IEEE operation in the written order).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Structural counters (pins for Algorithm 1 / Section III-C-1).            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t leaf_products;   /* base-case multiplications performed         */
+    int64_t internal_nodes;  /* recursion nodes that divided                */
+    int64_t block_additions; /* h x h additions/subtractions (divide+combine)*/
+    int64_t uses_a[4];       /* uses of A11, A12, A21, A22 by the 7 products */
+    int64_t uses_b[4];       /* uses of B11, B12, B21, B22                   */
+} oracle_counts;
+
+/* Deliberate-mistake switch, used only by the tests that prove the pins
+ * catch plausible errors.  0 = the oracle as specified.  Never set by any
+ * product path. */
+static int g_mutation = 0;
+void oracle_set_mutation(int m) { g_mutation = m; }
+
+/* ------------------------------------------------------------------------ */
+/* Classical product, the plain definition C[i][j] = sum_t A[i][t] B[t][j]. */
+/* i-t-j loop order; rows are independent and split over OpenMP threads.    */
+/* ------------------------------------------------------------------------ */
+static void classical_f64(const double* A, int64_t lda, const double* B, int64_t ldb,
+                          double* C, int64_t ldc, int64_t m, int parallel)
+{
+#pragma omp parallel for schedule(static) if (parallel)
+    for (int64_t i = 0; i < m; ++i) {
+        double* c = C + i * ldc;
+        for (int64_t j = 0; j < m; ++j) c[j] = 0.0;
+        for (int64_t t = 0; t < m; ++t) {
+            const double a = A[i * lda + t];
+            const double* b = B + t * ldb;
+            for (int64_t j = 0; j < m; ++j) c[j] += a * b[j];
+        }
+    }
+}
+
+void oracle_gemm_f64(const double* A, const double* B, double* C, int64_t n)
+{
+    classical_f64(A, n, B, n, C, n, n, 1);
+}
+
+void oracle_gemm_i64(const int64_t* A, const int64_t* B, int64_t* C, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t s = 0;
+            for (int64_t t = 0; t < n; ++t) s += A[i * n + t] * B[t * n + j];
+            C[i * n + j] = s;
+        }
+}
+
+/* Selected rows of the classical product: out[r][:] = A[rows[r]][:] * B,
+ * in the same i-t-j order as classical_f64 (so a sampled row is bit-identical
+ * to that row of the full product). */
+void oracle_rows_f64(const double* A, const double* B, int64_t n,
+                     const int64_t* rows, int64_t nrows, double* out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t i = rows[r];
+        double* c = out + r * n;
+        for (int64_t j = 0; j < n; ++j) c[j] = 0.0;
+        for (int64_t t = 0; t < n; ++t) {
+            const double a = A[i * n + t];
+            const double* b = B + t * n;
+            for (int64_t j = 0; j < n; ++j) c[j] += a * b[j];
+        }
+    }
+}
+
+/* y = M x in double (Freivalds' check: ||C x - A (B x)||, Freivalds 1977). */
+void oracle_gemv_f64(const double* M, const double* x, double* y, int64_t n)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) s += M[i * n + j] * x[j];
+        y[i] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Strassen recursion, Algorithm 1 (Section III-A), depth-limited.          */
+/* ------------------------------------------------------------------------ */
+
+/* out = P + sign*Q on h x h blocks (out contiguous, ld = h). */
+static void block_addsub(double* out, const double* P, int64_t ldp, const double* Q, int64_t ldq,
+                         double sign, int64_t h)
+{
+    for (int64_t i = 0; i < h; ++i)
+        for (int64_t j = 0; j < h; ++j)
+            out[i * h + j] = (sign > 0) ? P[i * ldp + j] + Q[i * ldq + j]
+                                        : P[i * ldp + j] - Q[i * ldq + j];
+}
+
+static void block_copy(double* out, const double* P, int64_t ldp, int64_t h)
+{
+    for (int64_t i = 0; i < h; ++i) memcpy(out + i * h, P + i * ldp, (size_t)h * sizeof(double));
+}
+
+static void strassen_rec(const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                         double* Z, int64_t ldz, int64_t m, int levels, int top,
+                         oracle_counts* cnt)
+{
+    if (levels == 0) {
+        /* Base case: "multiply A and B using naive approach". */
+        classical_f64(X, ldx, Y, ldy, Z, ldz, m, top);
+        cnt->leaf_products += 1;
+        return;
+    }
+    const int64_t h = m / 2;
+    const size_t hh = (size_t)h * (size_t)h;
+    /* Quadrants of the operands ("Compute A11, B11, ..., A22, B22"). */
+    const double *A11 = X, *A12 = X + h, *A21 = X + h * ldx, *A22 = X + h * ldx + h;
+    const double *B11 = Y, *B12 = Y + h, *B21 = Y + h * ldy, *B22 = Y + h * ldy + h;
+
+    /* Two operand scratch blocks and the seven products M1..M7. */
+    double* s = (double*)malloc(hh * sizeof(double));
+    double* t = (double*)malloc(hh * sizeof(double));
+    double* M = (double*)malloc(7 * hh * sizeof(double));
+    double *M1 = M, *M2 = M + hh, *M3 = M + 2 * hh, *M4 = M + 3 * hh,
+           *M5 = M + 4 * hh, *M6 = M + 5 * hh, *M7 = M + 6 * hh;
+    const int lv = levels - 1;
+
+    cnt->internal_nodes += 1;
+
+    /* M1 = (A11 + A22)(B11 + B22) */
+    block_addsub(s, A11, ldx, A22, ldx, +1, h);
+    block_addsub(t, B11, ldy, B22, ldy, +1, h);
+    cnt->uses_a[0]++; cnt->uses_a[3]++; cnt->uses_b[0]++; cnt->uses_b[3]++;
+    strassen_rec(s, h, t, h, M1, h, h, lv, 0, cnt);
+
+    /* M2 = (A21 + A22) B11 */
+    block_addsub(s, A21, ldx, A22, ldx, +1, h);
+    cnt->uses_a[2]++; cnt->uses_a[3]++; cnt->uses_b[0]++;
+    strassen_rec(s, h, B11, ldy, M2, h, h, lv, 0, cnt);
+
+    /* M3 = A11 (B12 - B22) */
+    block_addsub(t, B12, ldy, B22, ldy, -1, h);
+    cnt->uses_a[0]++; cnt->uses_b[1]++; cnt->uses_b[3]++;
+    if (g_mutation == 2) /* mistake: operands of M3 exchanged */
+        strassen_rec(t, h, A11, ldx, M3, h, h, lv, 0, cnt);
+    else
+        strassen_rec(A11, ldx, t, h, M3, h, h, lv, 0, cnt);
+
+    /* M4 = A22 (B21 - B11) */
+    block_addsub(t, B21, ldy, B11, ldy, -1, h);
+    cnt->uses_a[3]++; cnt->uses_b[2]++; cnt->uses_b[0]++;
+    strassen_rec(A22, ldx, t, h, M4, h, h, lv, 0, cnt);
+
+    /* M5 = (A11 + A12) B22 */
+    if (g_mutation == 3) /* mistake: A21 taken for A12 */
+        block_addsub(s, A11, ldx, A21, ldx, +1, h);
+    else
+        block_addsub(s, A11, ldx, A12, ldx, +1, h);
+    cnt->uses_a[0]++; cnt->uses_a[1]++; cnt->uses_b[3]++;
+    strassen_rec(s, h, B22, ldy, M5, h, h, lv, 0, cnt);
+
+    /* M6 = (A21 - A11)(B11 + B12) */
+    block_addsub(s, A21, ldx, A11, ldx, -1, h);
+    block_addsub(t, B11, ldy, B12, ldy, +1, h);
+    cnt->uses_a[2]++; cnt->uses_a[0]++; cnt->uses_b[0]++; cnt->uses_b[1]++;
+    strassen_rec(s, h, t, h, M6, h, h, lv, 0, cnt);
+
+    /* M7 = (A12 - A22)(B21 + B22) */
+    block_addsub(s, A12, ldx, A22, ldx, -1, h);
+    block_addsub(t, B21, ldy, B22, ldy, +1, h);
+    cnt->uses_a[1]++; cnt->uses_a[3]++; cnt->uses_b[2]++; cnt->uses_b[3]++;
+    strassen_rec(s, h, t, h, M7, h, h, lv, 0, cnt);
+
+    /* 10 operand additions above, 8 below: 18 per node. */
+    cnt->block_additions += 18;
+
+    /* Combine, left to right as printed (C22 with +M3, see header). */
+    double *C11 = Z, *C12 = Z + h, *C21 = Z + h * ldz, *C22 = Z + h * ldz + h;
+    for (int64_t i = 0; i < h; ++i) {
+        for (int64_t j = 0; j < h; ++j) {
+            const size_t q = (size_t)i * h + j;
+            double c11 = ((M1[q] + M4[q]) - M5[q]);
+            if (g_mutation != 4) c11 = c11 + M7[q]; /* mistake 4: M7 dropped */
+            C11[i * ldz + j] = c11;
+            C12[i * ldz + j] = M3[q] + M5[q];
+            C21[i * ldz + j] = M2[q] + M4[q];
+            if (g_mutation == 1) /* mistake 1: C22 sign exactly as printed */
+                C22[i * ldz + j] = ((M1[q] - M2[q]) - M3[q]) + M6[q];
+            else
+                C22[i * ldz + j] = ((M1[q] - M2[q]) + M3[q]) + M6[q];
+        }
+    }
+    free(s); free(t); free(M);
+}
+
+/* C (n x n) = A (n x n) * B (n x n) by `depth` levels of Strassen on the
+ * zero-padded n_pad x n_pad operands; n_pad must be >= n and a multiple of
+ * 2^depth.  Returns 0, or -1 on bad arguments.  cnt may be NULL. */
+int oracle_strassen_f64(const double* A, const double* B, double* C, int64_t n,
+                        int depth, int64_t n_pad, oracle_counts* cnt)
+{
+    oracle_counts local;
+    if (!cnt) cnt = &local;
+    memset(cnt, 0, sizeof(*cnt));
+    if (n <= 0 || depth < 0 || depth > 20 || n_pad < n || (n_pad % ((int64_t)1 << depth)) != 0)
+        return -1;
+    const size_t N = (size_t)n_pad * (size_t)n_pad;
+    double* Ap = (double*)calloc(N, sizeof(double));
+    double* Bp = (double*)calloc(N, sizeof(double));
+    double* Cp = (double*)calloc(N, sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        memcpy(Ap + i * n_pad, A + i * n, (size_t)n * sizeof(double));
+        memcpy(Bp + i * n_pad, B + i * n, (size_t)n * sizeof(double));
+    }
+    strassen_rec(Ap, n_pad, Bp, n_pad, Cp, n_pad, n_pad, depth, 1, cnt);
+    for (int64_t i = 0; i < n; ++i) memcpy(C + i * n, Cp + i * n_pad, (size_t)n * sizeof(double));
+    free(Ap); free(Bp); free(Cp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One divide step and one combine step in binary32, for bit-exact checks    */
+/* of the GPU's per-level kernels.                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Operand pairs of the seven products of one node (Algorithm 1; replication
+ * map of Section III-C-1 / Fig. 3).  X, Y: m x m with leading dims ldx, ldy.
+ * S, T: 7 contiguous h x h blocks each (h = m/2), S[i], T[i] the operands of
+ * M_{i+1}; the pass-through operands (S3 = A11, S4 = A22, T2 = B11, T5 = B22)
+ * are copied so that every block is explicit. */
+void oracle_divide_f32(const float* X, int64_t ldx, const float* Y, int64_t ldy, int64_t m,
+                       float* S, float* T)
+{
+    const int64_t h = m / 2;
+    const size_t hh = (size_t)h * (size_t)h;
+    for (int64_t i = 0; i < h; ++i) {
+        for (int64_t j = 0; j < h; ++j) {
+            const float a11 = X[i * ldx + j], a12 = X[i * ldx + j + h];
+            const float a21 = X[(i + h) * ldx + j], a22 = X[(i + h) * ldx + j + h];
+            const float b11 = Y[i * ldy + j], b12 = Y[i * ldy + j + h];
+            const float b21 = Y[(i + h) * ldy + j], b22 = Y[(i + h) * ldy + j + h];
+            const size_t q = (size_t)i * h + j;
+            S[0 * hh + q] = a11 + a22;  T[0 * hh + q] = b11 + b22;  /* M1 */
+            S[1 * hh + q] = a21 + a22;  T[1 * hh + q] = b11;        /* M2 */
+            S[2 * hh + q] = a11;        T[2 * hh + q] = b12 - b22;  /* M3 */
+            S[3 * hh + q] = a22;        T[3 * hh + q] = b21 - b11;  /* M4 */
+            S[4 * hh + q] = a11 + a12;  T[4 * hh + q] = b22;        /* M5 */
+            S[5 * hh + q] = a21 - a11;  T[5 * hh + q] = b11 + b12;  /* M6 */
+            S[6 * hh + q] = a12 - a22;  T[6 * hh + q] = b21 + b22;  /* M7 */
+        }
+    }
+}
+
+/* C (m x m, leading dim ldc) from the seven h x h products M[0..6] = M1..M7
+ * (Algorithm 1, C22 with +M3), additions left to right in binary32. */
+void oracle_combine_f32(const float* M, int64_t h, float* C, int64_t ldc)
+{
+    const size_t hh = (size_t)h * (size_t)h;
+    for (int64_t i = 0; i < h; ++i) {
+        for (int64_t j = 0; j < h; ++j) {
+            const size_t q = (size_t)i * h + j;
+            const float m1 = M[q], m2 = M[hh + q], m3 = M[2 * hh + q], m4 = M[3 * hh + q];
+            const float m5 = M[4 * hh + q], m6 = M[5 * hh + q], m7 = M[6 * hh + q];
+            C[i * ldc + j] = ((m1 + m4) - m5) + m7;
+            C[i * ldc + j + h] = m3 + m5;
+            C[(i + h) * ldc + j] = m2 + m4;
+            C[(i + h) * ldc + j + h] = ((m1 - m2) + m3) + m6;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* bfloat16 split (not in the paper: the leaf-precision scheme of the GPU    */
+/* path).  bfloat16 = the upper 16 bits of a binary32; rounding to nearest,  */
+/* ties to even, on the 16 discarded bits.  Finite inputs only.             */
+/* ------------------------------------------------------------------------ */
+static uint16_t bf16_rne(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+static float bf16_to_f32(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float x;
+    memcpy(&x, &u, 4);
+    return x;
+}
+
+/* x ~= hi + mid + lo with each term bfloat16: hi = rne(x), mid = rne(x - hi),
+ * lo = rne(x - hi - mid).  The differences are exact in binary32. `terms` is
+ * 2 (hi, mid) or 3; out has `terms` planes of count values each. */
+void oracle_split_bf16(const float* x, int64_t count, int terms, uint16_t* out)
+{
+    for (int64_t i = 0; i < count; ++i) {
+        float r = x[i];
+        for (int p = 0; p < terms; ++p) {
+            const uint16_t b = bf16_rne(r);
+            out[(size_t)p * (size_t)count + (size_t)i] = b;
+            r = r - bf16_to_f32(b);
+        }
+    }
+}
