@@ -1,0 +1,317 @@
+"""Benchmark of the Strassen hot path on one MI355X.
+
+Default workload (one "step" = one full multiply: divide levels, split,
+grouped leaf GEMM, combine levels): C = A B at n = 16384, A and B i.i.d.
+normal(0, 1) in binary32, leaf products in BF16x3 (bf16 matrix cores, binary32
+accumulation), recursion depth chosen by the autotuner among 2..4.  Inputs are
+resident in HBM before the timed region; the timed region is K back-to-back
+multiplies on one stream, bracketed by device synchronisation.
+
+Reported beside it, on the same GPU and inputs: the plain binary32 Strassen
+path (autotuned depth), the classical product (depth 0, binary32 leaves) and
+BF16x6; the error of the headline result against the FP64 oracle on 256
+sampled rows and Freivalds' check; the leaf GEMM's roofline; the oracle's own
+speed on the host (sampled rows); and a serving run (Poisson stream of
+requests of mixed sizes and precisions) with p50/p99 latency.
+
+Prints ONE JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "hbm": 8.0e12}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--n", type=int, default=16384)
+    p.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "bf16x6"])
+    p.add_argument("--min-depth", type=int, default=2)
+    p.add_argument("--max-depth", type=int, default=4)
+    p.add_argument("--depth", type=int, default=None, help="fixed depth (skips the autotuner)")
+    p.add_argument("--no-compare", action="store_true", help="skip the FP32 / classical / BF16x6 legs")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-serving", action="store_true")
+    p.add_argument("--serving-requests", type=int, default=2000)
+    p.add_argument("--rows", type=int, default=256, help="sampled rows for the error check")
+    p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "leaf_gemm_traffic.json"),
+                   help="HBM traffic of the leaf GEMM measured by rocprofv3 counters (JSON), if present")
+    return p.parse_args()
+
+
+def run_serving(S, count: int, seed: int = 5, budget: int = 96 << 30, slots: int = 8) -> dict:
+    """Poisson stream of `count` requests, n log-uniform in [128, 8192], 70 %
+    BF16x3 / 30 % FP32, operands normal(0,1) generated on the device from
+    per-request seeds.  The arrival rate is 0.7 x the saturation throughput
+    measured first with a closed burst of requests from the same mix."""
+    rng = np.random.default_rng(seed)
+
+    def draw(k):
+        ns = np.exp(rng.uniform(math.log(128), math.log(8192), k)).astype(np.int64)
+        ps = np.where(rng.uniform(size=k) < 0.7, S.STARK_BF16X3, S.STARK_FP32)
+        return ns, ps
+
+    def drain(ctx, tickets):
+        pending = list(tickets)
+        while pending:
+            pending = [t for t in pending if S.stark_poll(ctx, t) is None]
+            if pending:
+                time.sleep(0.0005)
+
+    # saturation: a closed burst
+    ctx = S.stark_create(0, hbm_budget_bytes=budget, max_slots=slots)
+    ns, ps = draw(min(400, count))
+    t0 = time.perf_counter()
+    tickets = [S.stark_submit(ctx, int(n_), int(p_), S.STARK_DEPTH_AUTO, seed=20000 + i, tag=i)
+               for i, (n_, p_) in enumerate(zip(ns, ps))]
+    drain(ctx, tickets)
+    burst_s = time.perf_counter() - t0
+    sat = len(ns) / burst_s
+    sat_tf = float(np.sum(2.0 * ns.astype(np.float64) ** 3)) / burst_s * 1e-12
+    S.stark_destroy(ctx)
+    log(f"serving: saturation {sat:.0f} req/s ({sat_tf:.1f} TF/s) from a burst of {len(ns)}")
+
+    lam = 0.7 * sat
+    ns, ps = draw(count)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, count))
+    ctx = S.stark_create(0, hbm_budget_bytes=budget, max_slots=slots)
+    tickets = []
+    t0 = time.perf_counter()
+    for i in range(count):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        tickets.append(S.stark_submit(ctx, int(ns[i]), int(ps[i]), S.STARK_DEPTH_AUTO, seed=10000 + i, tag=i))
+    drain(ctx, tickets)
+    wall = time.perf_counter() - t0
+    stt = S.stark_stats(ctx)
+    S.stark_destroy(ctx)
+    out = {"requests": count, "rate_req_s": lam, "saturation_req_s": sat, "p50_ms": stt.p50_ms,
+           "p99_ms": stt.p99_ms, "throughput_tflops": stt.throughput_tflops, "completed": int(stt.completed),
+           "failed": int(stt.failed), "max_concurrent": stt.max_concurrent,
+           "max_inflight_gb": stt.max_inflight_bytes / 1e9, "wall_s": wall, "slots": slots,
+           "budget_gb": budget / 2 ** 30}
+    log(f"serving: {count} requests at {lam:.0f} req/s: p50 {stt.p50_ms:.2f} ms, p99 {stt.p99_ms:.2f} ms, "
+        f"{stt.throughput_tflops:.1f} TF/s, max concurrent {stt.max_concurrent}")
+    return out
+
+
+def main() -> int:
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        return 2
+    import torch
+
+    from paper_1811_07325_amd import inputs
+    from paper_1811_07325_amd import stark as S
+
+    n = args.n
+    dev = torch.device("cuda", 0)
+    st = torch.cuda.Stream(device=dev)
+    prec = S.PRECISIONS[args.precision]
+
+    log(f"generating inputs n={n}")
+    A = torch.from_numpy(inputs.normal(n, 0)).to(dev)
+    B = torch.from_numpy(inputs.normal(n, 1)).to(dev)
+    C = torch.empty((n, n), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    ctx = S.stark_create(0)
+
+    def timed(depth: int, precision: int, steps: int, warmup: int) -> float:
+        """ms per multiply over `steps` back-to-back calls."""
+        for _ in range(warmup):
+            S.stark_gemm(ctx, A, B, C, n, depth, precision, st)
+        st.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(steps):
+            S.stark_gemm(ctx, A, B, C, n, depth, precision, st)
+        e1.record(st)
+        e1.synchronize()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    # -- autotune the headline configuration ---------------------------------
+    tune_pts = []
+    if args.depth is None:
+        log(f"autotuning {args.precision} depth in [{args.min_depth}, {args.max_depth}]")
+        tune_pts = S.stark_tune(ctx, A, B, C, n, prec, args.min_depth, args.max_depth, 1e-5, st)
+        ok = [p for p in tune_pts if p[2] <= 1e-5]
+        depth = min(ok, key=lambda p: p[1])[0] if ok else min(tune_pts, key=lambda p: p[2])[0]
+        for p in tune_pts:
+            log(f"  depth {p[0]}: {p[1]:.3f} ms, freivalds {p[2]:.2e}")
+    else:
+        depth = args.depth
+
+    # -- timed region -----------------------------------------------------------
+    log(f"timing {args.precision} depth {depth}: warmup {args.warmup}, steps {args.steps}")
+    ms = timed(depth, prec, args.steps, args.warmup)
+    eff = 2.0 * n ** 3 / (ms * 1e-3) * 1e-12
+    log(f"  {ms:.3f} ms/step, {eff:.1f} effective TFLOP/s")
+
+    # -- error of the headline result (C holds it) ------------------------------
+    import oracle
+    S.stark_gemm(ctx, A, B, C, n, depth, prec, st)
+    st.synchronize()
+    rows = inputs.sample_rows(n, args.rows, 2)
+    Ah = A.cpu().numpy()
+    Bh = B.cpu().numpy()
+    log(f"oracle: {rows.size} sampled rows (FP64) on {oracle.threads()} host threads")
+    t0 = time.perf_counter()
+    ref = oracle.rows_f64(Ah, Bh, rows)
+    t_rows = time.perf_counter() - t0
+    Ch = C[torch.from_numpy(rows).to(dev)].cpu().numpy().astype(np.float64)
+    d = Ch - ref
+    rel_rows = float(np.sqrt(np.sum(d * d) / np.sum(ref * ref)))
+    max_abs = float(np.max(np.abs(d)))
+    x = torch.from_numpy(inputs.gaussian_vector(n, 3)).to(dev)
+    y = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
+    S.stark_matvec_f64(B, x, y[0], n, st)
+    S.stark_matvec_f64(A, y[0], y[1], n, st)
+    S.stark_matvec_f64(C, x, y[2], n, st)
+    st.synchronize()
+    freiv = float(torch.linalg.norm(y[2] - y[1]) / torch.linalg.norm(y[1]))
+    log(f"  error: rel_frob(rows)={rel_rows:.3e} max_abs={max_abs:.3e} freivalds={freiv:.3e}")
+
+    # -- roofline of the dominant kernel (leaf GEMM), timed live --------------
+    plan = S.stark_plan_info(n, depth, prec)
+    S.stark_gemm_phases(ctx, A, B, C, n, depth, prec, S.STARK_PHASE_DIVIDE, st)
+    reps = 5
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    e[0].record(st)
+    for _ in range(reps):
+        S.stark_gemm_phases(ctx, A, B, C, n, depth, prec, S.STARK_PHASE_DIVIDE, st)
+    e[1].record(st)
+    for _ in range(reps):
+        S.stark_gemm_phases(ctx, A, B, C, n, depth, prec, S.STARK_PHASE_LEAF, st)
+    e[2].record(st)
+    for _ in range(reps):
+        S.stark_gemm_phases(ctx, A, B, C, n, depth, prec, S.STARK_PHASE_COMBINE, st)
+    e[3].record(st)
+    e[3].synchronize()
+    t_div = e[0].elapsed_time(e[1]) / reps
+    t_leaf = e[1].elapsed_time(e[2]) / reps
+    t_comb = e[2].elapsed_time(e[3]) / reps
+    planes = plan.planes
+    L = plan.leaf
+    nleaf = 7 ** depth
+    prods = {0: 1, 2: 3, 3: 6}[planes]
+    leaf_flops = 2.0 * L ** 3 * nleaf * prods        # matrix-core work of one launch
+    unit_peak = PEAK["fp32"] if planes == 0 else PEAK["bf16"]
+    achieved = leaf_flops / (t_leaf * 1e-3)
+    traffic = None
+    if os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            tr = json.load(f)
+        key = f"n{n}_d{depth}_{args.precision}"
+        if key in tr:
+            traffic = tr[key]
+    # divide (+ split) and combine: algorithmic bytes, see the planner
+    Np = plan.n_pad ** 2
+    div_bytes = split_bytes = comb_bytes = 0.0
+    fp32_levels = depth if planes == 0 else max(depth - 1, 0)
+    for l in range(fp32_levels):
+        h = (plan.n_pad >> l) / 2
+        div_bytes += 2 * 7 ** l * (4 + plan.div_slots[l]) * h * h * 4
+    if planes:
+        nodes = 7 ** (depth - 1) if depth else 1
+        ib, ob = (4, 7) if depth else (1, 1)
+        split_bytes = 2 * nodes * (ib * L * L * 4 + ob * planes * L * L * 2)
+    for l in range(depth):
+        h = (plan.n_pad >> l) / 2
+        comb_bytes += 7 ** l * 11 * h * h * 4
+    phases = {
+        "divide_ms": t_div, "divide_gbs": (div_bytes + split_bytes) / (t_div * 1e-3) * 1e-9,
+        "leaf_ms": t_leaf, "leaf_tflops": achieved * 1e-12,
+        "combine_ms": t_comb, "combine_gbs": comb_bytes / (t_comb * 1e-3) * 1e-9 if t_comb > 0 else None,
+    }
+    log(f"  phases: divide {t_div:.3f} ms ({phases['divide_gbs']:.0f} GB/s), leaf {t_leaf:.3f} ms "
+        f"({achieved * 1e-12:.1f} TF/s of {unit_peak * 1e-12:.0f}), combine {t_comb:.3f} ms")
+    roofline = {"bound": "mfma", "achieved": achieved * 1e-12, "peak": unit_peak * 1e-12, "unit": "TFLOP/s",
+                "frac": achieved / unit_peak, "traffic": traffic,
+                "kernel": "k_gemm_bf16" if planes else "k_gemm_f32",
+                "work_per_launch": f"{nleaf} leaves x {prods} x 2*{L}^3 flops"}
+
+    # -- comparisons on the same GPU ----------------------------------------------
+    compare = {}
+    if not args.no_compare:
+        for name, p_, dmin, dmax in (("fp32_strassen", S.STARK_FP32, 1, 4), ("fp32_classical", S.STARK_FP32, 0, 0),
+                                     ("bf16x6_strassen", S.STARK_BF16X6, 1, 4),
+                                     ("bf16x3_classical", S.STARK_BF16X3, 0, 0)):
+            if dmin == dmax:
+                d_ = dmin
+                pts = []
+            else:
+                pts = S.stark_tune(ctx, A, B, C, n, p_, dmin, dmax, 1e-5, st)
+                okp = [p for p in pts if p[2] <= 1e-5]
+                d_ = min(okp, key=lambda p: p[1])[0] if okp else min(pts, key=lambda p: p[2])[0]
+            m_ = timed(d_, p_, max(3, args.steps // 2), 1)
+            compare[name] = {"depth": d_, "ms": m_, "tflops": 2.0 * n ** 3 / (m_ * 1e-3) * 1e-12,
+                             "tune": [{"depth": a, "ms": b, "err": c} for a, b, c in pts]}
+            log(f"  {name}: depth {d_}, {m_:.3f} ms, {compare[name]['tflops']:.1f} TF/s")
+        tt = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(st):
+            for _ in range(2):
+                torch.matmul(A, B, out=C)
+            tt[0].record(st)
+            for _ in range(3):
+                torch.matmul(A, B, out=C)
+            tt[1].record(st)
+        tt[1].synchronize()
+        m_ = tt[0].elapsed_time(tt[1]) / 3
+        compare["torch_matmul_fp32_external"] = {"ms": m_, "tflops": 2.0 * n ** 3 / (m_ * 1e-3) * 1e-12}
+
+    # -- CPU baseline: the oracle on the sampled rows ---------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        flops = 2.0 * rows.size * n * n
+        cpu = {"value": flops / t_rows * 1e-12, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"classical FP64 triple loop, {rows.size} sampled rows of the n={n} product "
+                         f"({flops:.3g} flops, {t_rows:.1f} s)"}
+
+    # -- serving -----------------------------------------------------------------
+    serving = None
+    if not args.no_serving:
+        serving = run_serving(S, count=args.serving_requests)
+
+    S.stark_destroy(ctx)
+    out = {
+        "metric": "effective TFLOP/s (2n^3/t) at n=16384, BF16x3 Strassen",
+        "value": eff, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if planes else "fp32", "data": "synthetic",
+        "config": {"workload": f"strassen C=AB n={n} normal(0,1) {args.precision} depth={depth}"
+                               f" (autotuned in [{args.min_depth},{args.max_depth}])" if args.depth is None else
+                               f"strassen C=AB n={n} normal(0,1) {args.precision} depth={depth}",
+                   "n": n, "depth": depth, "precision": args.precision, "leaf": L, "n_pad": plan.n_pad},
+        "error": {"rel_frob_sampled_rows": rel_rows, "max_abs_sampled_rows": max_abs, "freivalds": freiv,
+                  "rows": int(rows.size), "target": 1e-5, "meets_target": rel_rows <= 1e-5},
+        "tune": [{"depth": a, "ms": b, "err": c} for a, b, c in tune_pts],
+        "phases": phases, "roofline": roofline, "cpu_baseline": cpu, "compare": compare, "serving": serving,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,244 @@
+/*
+ * stark.h -- C ABI of the MI355X (gfx950) Strassen hot path.
+ *
+ * The library computes C = A * B for square dense binary32 matrices with
+ * `depth` levels of Strassen's seven-product recursion (Algorithm 1,
+ * Section III-A of Misra, Bhattacharya and Ghosh, "Stark: Fast and Scalable
+ * Strassen's Matrix Multiplication using Apache Spark").  The three phases of
+ * the paper's distributed method (Section III-C) become GPU launches:
+ *   divide   (Section III-C-1, Algorithms 2-3): one launch per recursion level
+ *            forms the operand sums S_i, T_i of every node of that level;
+ *   leaf     (Section III-C-2, Algorithm 4): one grouped launch multiplies all
+ *            7^depth leaf pairs;
+ *   combine  (Section III-C-3, Algorithm 5): one launch per level folds
+ *            M1..M7 of every node back into its four quadrants.
+ * Sizes that are not a multiple of 2^depth * 64 are zero-padded (the paper
+ * treats n = 2^p and defers other sizes to partitioning, Section III-A).
+ *
+ * Conventions for every call:
+ *   - Matrices are device pointers to row-major binary32 with leading
+ *     dimension n (n x n, contiguous).  The caller owns them; the library
+ *     never frees caller memory.  A, B, C must stay valid until the work
+ *     enqueued on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work and return; they do not synchronise.
+ *   - Status codes are returned; no exception crosses the ABI.  On failure
+ *     stark_last_error() returns a message (thread-local, valid until the
+ *     next failing call on that thread).
+ */
+#ifndef STARK_H
+#define STARK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int stark_status;
+#define STARK_OK 0
+#define STARK_PENDING 1          /* stark_poll: request not finished yet      */
+#define STARK_EINVAL (-1)        /* bad argument                              */
+#define STARK_ENOMEM (-2)        /* workspace or HBM budget too small         */
+#define STARK_EDEVICE (-3)       /* a HIP call failed (message kept)          */
+#define STARK_EBUSY (-4)         /* serving queue full                        */
+#define STARK_ENOTFOUND (-5)     /* unknown ticket                            */
+#define STARK_EUNSUPPORTED (-6)  /* valid but not supported (e.g. precision)  */
+
+/* Arithmetic of the leaf products.  Divide and combine are binary32 in all
+ * modes.  BF16X3: each leaf operand x is split as hi = bf16(x),
+ * lo = bf16(x - hi) (round to nearest even) and the product is formed from
+ * hi*hi + hi*lo + lo*hi on bf16 matrix cores with binary32 accumulation.
+ * BF16X6: three terms (hi, mid, lo) and the six products whose order of
+ * magnitude is at least 2^-16 of hi*hi. */
+typedef enum {
+    STARK_FP32 = 0,
+    STARK_BF16X3 = 1,
+    STARK_BF16X6 = 2
+} stark_precision;
+
+#define STARK_DEPTH_AUTO (-1)    /* let the autotuner choose the depth        */
+#define STARK_MAX_DEPTH 8
+
+typedef struct stark_ctx stark_ctx;
+
+typedef struct {
+    int device;               /* HIP device ordinal                               */
+    void* workspace;          /* optional caller-owned device buffer lent to the
+                                 context until stark_destroy; NULL = the library
+                                 allocates (and grows) its own                    */
+    size_t workspace_bytes;   /* size of `workspace`                              */
+    size_t hbm_budget_bytes;  /* serving: device bytes the engine may hold
+                                 (0 = 3/4 of free memory at create time)          */
+    int max_slots;            /* serving: concurrent requests (0 = 4)             */
+    const char* tuner_cache;  /* autotuner cache file (NULL = none)               */
+} stark_config;
+
+/* Create a context on cfg->device.  cfg may be NULL (device 0, library-owned
+ * workspace).  *out receives the context.  Errors: EINVAL, EDEVICE. */
+stark_status stark_create(stark_ctx** out, const stark_config* cfg);
+
+/* Wait for work the context enqueued (serving included) and free everything
+ * the context owns.  NULL is accepted. */
+stark_status stark_destroy(stark_ctx* ctx);
+
+/* Bytes of workspace one multiply of size n needs at this depth and
+ * precision (pure function, no context).  depth must be >= 0. */
+stark_status stark_workspace_size(int64_t n, int depth, stark_precision p, size_t* bytes);
+
+/* Largest depth usable for n (leaf size >= 64 after padding). */
+int stark_max_depth(int64_t n);
+
+/* C = A * B with `depth` Strassen levels (Algorithm 1; depth 0 is the
+ * classical product on the same leaf kernels).  depth = STARK_DEPTH_AUTO asks
+ * the autotuner (which may also run measurements on `stream` the first time a
+ * size is seen).  C must not overlap A or B.  Errors: EINVAL (null pointer,
+ * n <= 0, depth out of range, overlap), ENOMEM (caller workspace too small),
+ * EUNSUPPORTED, EDEVICE. */
+stark_status stark_gemm(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n,
+                        int depth, stark_precision p, void* stream);
+
+/* One measured point of the autotuner: depth, median time of three runs
+ * (ms) and the relative error estimated by Freivalds' check in binary64. */
+typedef struct {
+    int depth;
+    double ms;
+    double err;
+} stark_tune_point;
+
+/* Autotune the depth for (n, p): run every depth in [min_depth, max_depth]
+ * (clamped to stark_max_depth(n)) on the caller's A and B (C is overwritten),
+ * time each after a warm-up, estimate its error as
+ * ||C x - A (B x)|| / ||A (B x)|| for a Gaussian x, and record the fastest
+ * depth whose error is <= tol (tol <= 0: 1e-5 or STARK_TUNE_TOL), else the
+ * most accurate.  Later calls with depth = STARK_DEPTH_AUTO use the record.
+ * Up to `cap` points are written to `points` (may be NULL) and their number
+ * to *count (may be NULL).  Synchronises `stream`. */
+stark_status stark_tune(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n,
+                        stark_precision p, int min_depth, int max_depth, double tol,
+                        stark_tune_point* points, int cap, int* count, void* stream);
+
+/* `count` independent products C[i] = A[i] * B[i] of sizes n[i] (host arrays
+ * of device pointers / sizes), all at the same depth (clamped per problem to
+ * stark_max_depth) and precision.  Every recursion level of every problem is
+ * one launch, and all leaf products of all problems form one grouped launch;
+ * the sequence is captured once into a hipGraph and replayed.
+ * Errors as stark_gemm. */
+stark_status stark_gemm_batched(stark_ctx* ctx, int count, const float* const* A,
+                                const float* const* B, float* const* C, const int64_t* n,
+                                int depth, stark_precision p, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of independent multiply requests.           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;                /* matrix size                                       */
+    stark_precision precision;
+    int depth;                /* >= 0, or STARK_DEPTH_AUTO                         */
+    const float* A;           /* device operands owned by the caller, or NULL to  */
+    const float* B;           /* have the engine generate them on the device from */
+    float* C;                 /* `seed` (normal(0,1), see stark_generate_normal); */
+    uint64_t seed;            /* C NULL = library-owned result (freed at poll)    */
+    uint64_t tag;             /* caller's tag, returned by poll                    */
+} stark_request;
+
+typedef struct {
+    uint64_t tag;
+    int depth;                /* depth actually used                               */
+    stark_status status;
+    double t_submit_us;       /* host steady-clock timestamps (microseconds)       */
+    double t_admit_us;
+    double t_done_us;         /* completion as observed by the engine              */
+    double gpu_ms;            /* device time between the request's own events      */
+    double checksum;          /* sum of the result in binary64 (library-owned C)   */
+} stark_result;
+
+/* Enqueue a request; returns at once with a ticket.  Thread-safe.
+ * Errors: EINVAL, EBUSY (queue full), ENOMEM (request alone exceeds the HBM
+ * budget). */
+stark_status stark_submit(stark_ctx* ctx, const stark_request* r, uint64_t* ticket);
+
+/* STARK_PENDING while the request runs; STARK_OK (out filled, ticket
+ * retired) or the request's error once done; ENOTFOUND for an unknown or
+ * retired ticket.  Thread-safe. */
+stark_status stark_poll(stark_ctx* ctx, uint64_t ticket, stark_result* out);
+
+typedef struct {
+    uint64_t completed;
+    uint64_t failed;
+    double throughput_tflops; /* effective 2n^3/t over the engine's busy span     */
+    double p50_ms;            /* latency submit -> done                            */
+    double p99_ms;
+    double max_inflight_bytes;
+    int max_concurrent;       /* most requests on the device at once               */
+} stark_stats_t;
+
+stark_status stark_stats(stark_ctx* ctx, stark_stats_t* out);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* stark_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Measurement helpers (binary64 on the GPU, used by tests and benchmarks).  */
+/* ------------------------------------------------------------------------ */
+
+/* y = M x in binary64 for a device binary32 M (n x n, row-major) and device
+ * binary64 x, y.  Freivalds' check (1977) compares C x with A (B x), both
+ * formed with this call. */
+stark_status stark_matvec_f64(const float* M, const double* x, double* y, int64_t n, void* stream);
+
+/* Sums over the sampled rows: out[0] = max |C[r][j] - ref[i][j]|,
+ * out[1] = sum (C - ref)^2, out[2] = sum ref^2, where r = rows[i]; rows is a
+ * device int64 array, ref a device binary64 array (nrows x n), out a device
+ * binary64 array of 3. */
+stark_status stark_row_errors(const float* C, int64_t n, const int64_t* rows, int64_t nrows,
+                              const double* ref, double* out, void* stream);
+
+/* Fill X (n x n binary32, device) with normal(0,1) values from `seed`:
+ * Philox4x32-10 (Salmon et al., SC'11) counter stream, each value the sum of
+ * twelve 24-bit uniforms minus 6 (Irwin-Hall, mean 0, variance 1), exactly
+ * reproducible on any host. */
+stark_status stark_generate_normal(float* X, int64_t n, uint64_t seed, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Introspection for tests and profiling.                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n, n_pad, leaf;   /* user size, padded size, leaf size n_pad/2^depth   */
+    int depth, precision, planes;
+    int64_t div_a[STARK_MAX_DEPTH], div_b[STARK_MAX_DEPTH]; /* byte offsets of the
+                                 binary32 divide outputs of level l (-1 = none)    */
+    int div_slots[STARK_MAX_DEPTH]; /* blocks per node written at level l (5 or 7) */
+    int64_t leaf_a, leaf_b;   /* byte offsets of the split bf16 leaf operands (-1) */
+    int64_t leaf_m;           /* byte offset of the 7^depth leaf products (-1 when
+                                 depth 0 writes C directly)                        */
+    int64_t comb[STARK_MAX_DEPTH]; /* byte offset of level-l combine output (l>=1) */
+    int64_t pad_a, pad_b;     /* byte offsets of padded copies (depth-0 FP32 only) */
+    size_t bytes;             /* total workspace                                   */
+} stark_plan_desc;
+
+stark_status stark_plan_info(int64_t n, int depth, stark_precision p, stark_plan_desc* out);
+
+/* Phases for stark_gemm_phases. */
+#define STARK_PHASE_DIVIDE 1u   /* pad, divide levels and the bf16 split          */
+#define STARK_PHASE_LEAF 2u     /* grouped leaf products                          */
+#define STARK_PHASE_COMBINE 4u  /* combine levels (level 0 writes C)              */
+#define STARK_PHASE_ALL 7u
+
+/* As stark_gemm at a fixed depth, but only the phases in `mask` are launched
+ * (eagerly, no graph); the workspace keeps its contents between calls, so a
+ * test can run the phases one by one and inspect the regions described by
+ * stark_plan_info. */
+stark_status stark_gemm_phases(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n,
+                               int depth, stark_precision p, unsigned mask, void* stream);
+
+/* Device address of the context's workspace (NULL before first use) and its
+ * size; lets tests read the regions of stark_plan_info. */
+stark_status stark_workspace(stark_ctx* ctx, void** ptr, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STARK_H */

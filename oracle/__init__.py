@@ -71,6 +71,9 @@ def _load():
     lib.oracle_combine_f32.argtypes = [P, I64, P, I64]
     lib.oracle_split_bf16.argtypes = [P, I64, ctypes.c_int, P]
     lib.oracle_set_mutation.argtypes = [ctypes.c_int]
+    lib.oracle_strassen_model_f32.argtypes = [P, P, P, I64, ctypes.c_int, I64, ctypes.c_int]
+    lib.oracle_strassen_model_f32.restype = ctypes.c_int
+    lib.oracle_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -182,6 +185,30 @@ def split_bf16(x, terms: int = 2) -> np.ndarray:
 def bf16_bits_to_f32(b) -> np.ndarray:
     """Exact value of bfloat16 bit patterns as float32."""
     return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+MODEL_MODES = {"fp32": 0, "bf16x3": 2, "bf16x6": 3}
+
+
+def strassen_model_f32(A, B, depth: int, mode: str, n_pad: int | None = None) -> np.ndarray:
+    """Arithmetic model of the GPU path: binary32 divide/combine, leaf products
+    exact in binary64 from the leaf operands as seen by `mode` ("fp32",
+    "bf16x3", "bf16x6"), rounded to binary32.  Returns float32 n x n."""
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    n = A.shape[0]
+    if n_pad is None:
+        n_pad = padded_size(n, depth)
+    C = np.empty((n, n), dtype=np.float32)
+    rc = _load().oracle_strassen_model_f32(_ptr(A), _ptr(B), _ptr(C), n, depth, n_pad, MODEL_MODES[mode])
+    if rc != 0:
+        raise ValueError("oracle_strassen_model_f32: bad arguments")
+    return C
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().oracle_threads())
 
 
 def set_mutation(m: int) -> None:

@@ -351,3 +351,112 @@ void oracle_split_bf16(const float* x, int64_t count, int terms, uint16_t* out)
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Arithmetic model of the GPU path (error-model tool).                      */
+/*                                                                            */
+/* The same recursion as oracle_strassen_f64, but every operand sum and every */
+/* combine addition is a binary32 operation (oracle_divide_f32 /              */
+/* oracle_combine_f32 order), and each leaf product is formed exactly in     */
+/* binary64 from the leaf operands as the leaf arithmetic sees them, then    */
+/* rounded once to binary32:                                                  */
+/*   mode 0 (FP32):   x*y                                                     */
+/*   mode 2 (BF16X3): xh*yh + xh*yl + xl*yh           (2-term split)          */
+/*   mode 3 (BF16X6): + xh*ym.. the six cross terms of the 3-term split whose */
+/*                    plane indices sum to at most 2                          */
+/* The GPU accumulates the leaf sums in binary32 instead; the difference is  */
+/* that accumulation's rounding only, so GPU results sit within a few units  */
+/* of accumulation error of this model at any depth.                         */
+/* ------------------------------------------------------------------------ */
+static void leaf_model(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* Z, int64_t ldz,
+                       int64_t m, int mode)
+{
+    const int terms = mode == 0 ? 1 : mode == 2 ? 2 : 3;
+    const size_t mm = (size_t)m * (size_t)m;
+    /* planes of X and Y as doubles (mode 0: the values themselves) */
+    double* xp = (double*)malloc((size_t)terms * mm * sizeof(double));
+    double* yp = (double*)malloc((size_t)terms * mm * sizeof(double));
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < m; ++j) {
+            float rx = X[i * ldx + j], ry = Y[i * ldy + j];
+            for (int p = 0; p < terms; ++p) {
+                float hx = rx, hy = ry;
+                if (mode != 0) { hx = bf16_to_f32(bf16_rne(rx)); hy = bf16_to_f32(bf16_rne(ry)); }
+                xp[(size_t)p * mm + (size_t)i * m + j] = hx;
+                yp[(size_t)p * mm + (size_t)i * m + j] = hy;
+                rx = rx - hx;
+                ry = ry - hy;
+            }
+        }
+    double* acc = (double*)calloc(mm, sizeof(double));
+    for (int pa = 0; pa < terms; ++pa)
+        for (int pb = 0; pb < terms; ++pb) {
+            if (pa + pb > terms - 1) continue;   /* keep hi*hi (+ hi*lo, lo*hi (+ ...)) */
+            const double* xa = xp + (size_t)pa * mm;
+            const double* yb = yp + (size_t)pb * mm;
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < m; ++i)
+                for (int64_t t = 0; t < m; ++t) {
+                    const double a = xa[(size_t)i * m + t];
+                    const double* y = yb + (size_t)t * m;
+                    double* c = acc + (size_t)i * m;
+                    for (int64_t j = 0; j < m; ++j) c[j] += a * y[j];
+                }
+        }
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < m; ++j) Z[i * ldz + j] = (float)acc[(size_t)i * m + j];
+    free(xp); free(yp); free(acc);
+}
+
+static void model_rec(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* Z, int64_t ldz,
+                      int64_t m, int levels, int mode)
+{
+    if (levels == 0) {
+        leaf_model(X, ldx, Y, ldy, Z, ldz, m, mode);
+        return;
+    }
+    const int64_t h = m / 2;
+    const size_t hh = (size_t)h * (size_t)h;
+    float* S = (float*)malloc(7 * hh * sizeof(float));
+    float* T = (float*)malloc(7 * hh * sizeof(float));
+    float* M = (float*)malloc(7 * hh * sizeof(float));
+    oracle_divide_f32(X, ldx, Y, ldy, m, S, T);
+    for (int i = 0; i < 7; ++i) model_rec(S + i * hh, h, T + i * hh, h, M + i * hh, h, h, levels - 1, mode);
+    oracle_combine_f32(M, h, Z, ldz);
+    free(S); free(T); free(M);
+}
+
+/* C (n x n, binary32) from binary32 A, B: zero-pad to n_pad, `depth` levels,
+ * leaf arithmetic `mode` (0, 2, 3), crop.  Returns 0 or -1. */
+int oracle_strassen_model_f32(const float* A, const float* B, float* C, int64_t n, int depth, int64_t n_pad,
+                              int mode)
+{
+    if (n <= 0 || depth < 0 || depth > 20 || n_pad < n || (n_pad % ((int64_t)1 << depth)) != 0 ||
+        (mode != 0 && mode != 2 && mode != 3))
+        return -1;
+    const size_t N = (size_t)n_pad * (size_t)n_pad;
+    float* Ap = (float*)calloc(N, sizeof(float));
+    float* Bp = (float*)calloc(N, sizeof(float));
+    float* Cp = (float*)calloc(N, sizeof(float));
+    for (int64_t i = 0; i < n; ++i) {
+        memcpy(Ap + i * n_pad, A + i * n, (size_t)n * sizeof(float));
+        memcpy(Bp + i * n_pad, B + i * n, (size_t)n * sizeof(float));
+    }
+    model_rec(Ap, n_pad, Bp, n_pad, Cp, n_pad, n_pad, depth, mode);
+    for (int64_t i = 0; i < n; ++i) memcpy(C + i * n, Cp + i * n_pad, (size_t)n * sizeof(float));
+    free(Ap); free(Bp); free(Cp);
+    return 0;
+}
+
+/* Threads the OpenMP loops above use (for reporting CPU timings). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,196 @@
+// Batched multiplies: many independent problems of uneven sizes share every
+// launch.  Level l of the divide covers the level-l nodes of every problem
+// deep enough to have them; one grouped persistent launch per leaf-tile class
+// (128- or 64-wide tiles) multiplies every leaf of every problem; the combine
+// levels mirror the divide.  The problem table and the per-launch block
+// prefixes live in a small device buffer owned by the cache entry, and the
+// launch sequence is captured into a hipGraph the second time the same batch
+// (pointers, sizes, depth, precision, stream) is seen.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "ctx.hpp"
+#include "launch.hpp"
+
+namespace stk {
+
+namespace {
+
+enum LaunchKind { kPad, kDivide, kSplit, kGemm, kCombine };
+
+struct BatchLaunch {
+    LaunchKind kind;
+    int level;      // divide / combine level
+    int tile;       // gemm tile class
+    int64_t total;  // blocks (or tiles for the gemm)
+    size_t prefix;  // index of the prefix array in the device buffer (in int64 units)
+};
+
+struct BatchEntry {
+    void* dev = nullptr;           // ProbDesc[count] followed by prefix arrays
+    int count = 0;
+    int planes = 0;
+    std::vector<BatchLaunch> launches;
+    hipGraphExec_t exec = nullptr;
+    int uses = 0;
+};
+
+struct BatchKey {
+    std::vector<const void*> ptrs;
+    std::vector<int64_t> sizes;
+    int depth, precision;
+    const void* ws;
+    hipStream_t stream;
+    bool operator<(const BatchKey& o) const {
+        return std::tie(ptrs, sizes, depth, precision, ws, stream) <
+               std::tie(o.ptrs, o.sizes, o.depth, o.precision, o.ws, o.stream);
+    }
+};
+
+std::mutex g_batch_mu;
+std::map<std::pair<stark_ctx*, BatchKey>, BatchEntry> g_batches;
+
+stark_status enqueue(stark_ctx* ctx, const BatchEntry& e, hipStream_t st) {
+    const ProbDesc* table = static_cast<const ProbDesc*>(e.dev);
+    const int64_t* pre = reinterpret_cast<const int64_t*>(static_cast<const char*>(e.dev) +
+                                                          sizeof(ProbDesc) * e.count);
+    for (const BatchLaunch& l : e.launches) {
+        const TableProb src{table, pre + l.prefix, e.count};
+        switch (l.kind) {
+            case kPad: STK_HIP(launch_pad(src, l.total, st)); break;
+            case kDivide: STK_HIP(launch_divide(src, l.level, l.total, st)); break;
+            case kSplit: STK_HIP(launch_split(src, e.planes, l.total, st)); break;
+            case kGemm:
+                STK_HIP(launch_gemm(src, e.planes, l.tile, l.total, gemm_grid(ctx, e.planes, l.tile, l.total), st));
+                break;
+            case kCombine: STK_HIP(launch_combine(src, l.level, l.total, st)); break;
+        }
+    }
+    return STARK_OK;
+}
+
+}  // namespace
+
+stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, const float* const* B, float* const* C,
+                          const int64_t* n, int depth, int precision, hipStream_t st) {
+    std::vector<Plan> plans(count);
+    std::vector<size_t> off(count);
+    size_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        const int d = std::min(depth, max_depth_for(n[i]));
+        const std::string why = make_plan(n[i], d, precision, plans[i]);
+        if (!why.empty()) { set_error("problem %d: %s", i, why.c_str()); return STARK_EINVAL; }
+        off[i] = total;
+        total += (plans[i].bytes + 255) / 256 * 256;
+    }
+    stark_status rc = ensure_workspace(ctx, total);
+    if (rc != STARK_OK) return rc;
+
+    BatchKey key;
+    key.depth = depth;
+    key.precision = precision;
+    key.ws = ctx->ws;
+    key.stream = st ? st : ctx->side_stream;
+    for (int i = 0; i < count; ++i) {
+        key.ptrs.push_back(A[i]);
+        key.ptrs.push_back(B[i]);
+        key.ptrs.push_back(C[i]);
+        key.sizes.push_back(n[i]);
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto it = g_batches.find({ctx, key});
+    if (it == g_batches.end()) {
+        BatchEntry e;
+        e.count = count;
+        e.planes = plans[0].planes;
+        std::vector<ProbDesc> descs(count);
+        for (int i = 0; i < count; ++i)
+            descs[i] = make_desc(plans[i], A[i], B[i], C[i], static_cast<char*>(ctx->ws) + off[i]);
+        std::vector<int64_t> pre;
+        auto add_launch = [&](LaunchKind kind, int level, int tile, auto blocks_of) {
+            BatchLaunch l{kind, level, tile, 0, pre.size()};
+            int64_t acc = 0;
+            for (int i = 0; i < count; ++i) {
+                pre.push_back(acc);
+                acc += blocks_of(i);
+            }
+            pre.push_back(acc);
+            l.total = acc;
+            if (acc > 0) e.launches.push_back(l);
+        };
+        int max_fp32 = 0, max_depth = 0;
+        for (const Plan& p : plans) {
+            max_fp32 = std::max(max_fp32, p.fp32_levels);
+            max_depth = std::max(max_depth, p.depth);
+        }
+        add_launch(kPad, 0, 0, [&](int i) { return plans[i].pad_a >= 0 ? blocks_pad(descs[i]) : 0; });
+        for (int l = 0; l < max_fp32; ++l)
+            add_launch(kDivide, l, 0, [&](int i) { return plans[i].fp32_levels > l ? blocks_divide(descs[i], l) : 0; });
+        if (e.planes > 0) add_launch(kSplit, 0, 0, [&](int i) { return blocks_split(descs[i]); });
+        for (int tile : {128, 64})
+            add_launch(kGemm, 0, tile, [&](int i) {
+                const Plan& p = plans[i];
+                return p.tile == tile ? pow7(p.depth) * (p.leaf / tile) * (p.leaf / tile) : (int64_t)0;
+            });
+        for (int l = max_depth - 1; l >= 0; --l)
+            add_launch(kCombine, l, 0, [&](int i) { return plans[i].depth > l ? blocks_combine(descs[i], l) : 0; });
+        const size_t bytes = sizeof(ProbDesc) * count + sizeof(int64_t) * pre.size();
+        STK_HIP(hipMalloc(&e.dev, bytes));
+        std::vector<char> host(bytes);
+        std::memcpy(host.data(), descs.data(), sizeof(ProbDesc) * count);
+        std::memcpy(host.data() + sizeof(ProbDesc) * count, pre.data(), sizeof(int64_t) * pre.size());
+        STK_HIP(hipMemcpy(e.dev, host.data(), bytes, hipMemcpyHostToDevice));
+        it = g_batches.emplace(std::make_pair(ctx, key), std::move(e)).first;
+    }
+    BatchEntry& e = it->second;
+    hipStream_t gs = key.stream;
+    e.uses++;
+    if (e.uses == 1) return enqueue(ctx, e, st);
+    if (!e.exec) {
+        hipGraph_t g = nullptr;
+        STK_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+        const stark_status rs = enqueue(ctx, e, gs);
+        const hipError_t ec = hipStreamEndCapture(gs, &g);
+        if (rs != STARK_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rs;
+        }
+        STK_HIP(ec);
+        const hipError_t ei = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        STK_HIP(ei);
+    }
+    if (!st) {
+        STK_HIP(hipEventRecord(ctx->ev_in, nullptr));
+        STK_HIP(hipStreamWaitEvent(gs, ctx->ev_in, 0));
+        STK_HIP(hipGraphLaunch(e.exec, gs));
+        STK_HIP(hipEventRecord(ctx->ev_out, gs));
+        STK_HIP(hipStreamWaitEvent(nullptr, ctx->ev_out, 0));
+    } else {
+        STK_HIP(hipGraphLaunch(e.exec, gs));
+    }
+    return STARK_OK;
+}
+
+// Release the batch entries of a context (called from stark_destroy after the
+// device is idle).
+void batched_release(stark_ctx* ctx) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (auto it = g_batches.begin(); it != g_batches.end();) {
+        if (it->first.first == ctx) {
+            if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+            if (it->second.dev) (void)hipFree(it->second.dev);
+            it = g_batches.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+}  // namespace stk

@@ -1,0 +1,112 @@
+// Serving engine: continuous batching of independent multiply requests.
+//
+// Requests arrive through stark_submit (any thread) into a queue.  An engine
+// thread admits them in arrival order whenever a slot (a HIP stream of its
+// own) is free and the request's device footprint fits the remaining HBM
+// budget; a request that does not fit lets at most kMaxBypass later, smaller
+// requests go first, so nothing starves.  Admitted requests run concurrently
+// on their slot streams; completion is observed with HIP events and frees the
+// slot and the memory for the next arrivals.  Each request's kernels and
+// their order are fixed by its plan, so its result does not depend on what
+// else is running.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/stark.h"
+#include "plan.hpp"
+
+struct stark_ctx;
+
+namespace stk {
+
+// First-fit allocator over [0, size) with coalescing of freed ranges.
+class Arena {
+public:
+    explicit Arena(size_t size = 0) { reset(size); }
+    void reset(size_t size);
+    bool alloc(size_t bytes, size_t* off);
+    void free(size_t off, size_t bytes);
+    size_t used() const { return used_; }
+    size_t size() const { return size_; }
+    size_t largest_free() const;
+
+private:
+    std::map<size_t, size_t> free_;  // offset -> length
+    size_t size_ = 0, used_ = 0;
+};
+
+// Depth used for a request when it asks for STARK_DEPTH_AUTO and the
+// autotuner has no record for its size.
+int default_serving_depth(int64_t n, int precision);
+
+// Device bytes a request holds while it runs.
+size_t request_footprint(const Plan& p, bool gen_operands, bool own_c);
+
+class Engine {
+public:
+    static constexpr int kMaxBypass = 8;
+    static constexpr size_t kMaxQueue = 1 << 16;
+
+    Engine(stark_ctx* ctx, size_t budget, int slots, hipError_t* err);
+    ~Engine();
+
+    stark_status submit(const stark_request& r, uint64_t* ticket);
+    stark_status poll(uint64_t ticket, stark_result* out);
+    stark_status stats(stark_stats_t* out);
+
+private:
+    struct Req {
+        uint64_t ticket = 0;
+        stark_request r{};
+        Plan plan;
+        size_t bytes = 0, off = 0;
+        bool gen = false, own_c = false;
+        int slot = -1;
+        double t_submit = 0, t_admit = 0, t_done = 0;
+        stark_status status = STARK_OK;
+        double checksum = 0;
+        float gpu_ms = 0;
+    };
+    struct Slot {
+        hipStream_t stream = nullptr;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        double* partials = nullptr;   // device, checksum reduction
+        bool busy = false;
+        Req* req = nullptr;
+    };
+
+    void loop();
+    bool admit(Req* q, int slot);
+    void finish(int slot);
+
+    stark_ctx* ctx_;
+    void* base_ = nullptr;        // device arena
+    double* host_sums_ = nullptr; // pinned, one per slot
+    Arena arena_;
+    std::vector<Slot> slots_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::deque<Req*> arrivals_, waiting_;
+    std::map<uint64_t, Req*> live_;     // submitted, not yet polled
+    uint64_t next_ticket_ = 1;
+    bool stop_ = false;
+    std::thread thread_;
+    // statistics
+    std::vector<double> lat_ms_;
+    uint64_t completed_ = 0, failed_ = 0;
+    double flops_ = 0, first_admit_ = -1, last_done_ = 0;
+    size_t max_bytes_ = 0;
+    int inflight_ = 0, max_inflight_ = 0;
+    int64_t fault_tag_ = -1;   // STARK_FAULT_INJECT: tag of a request made to fail
+};
+
+double now_us();
+
+}  // namespace stk

@@ -1,0 +1,152 @@
+// Measurement-side kernels: the only binary64 arithmetic on the GPU (error
+// checks; no Strassen step needs it), and the seeded operand generator of the
+// serving path.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace stk {
+
+// y = M x, M binary32 (n x n row-major), x and y binary64.  One block per
+// row; fixed per-thread strides and a fixed reduction tree (deterministic).
+__global__ __launch_bounds__(256) void k_matvec_f64(const float* __restrict__ M, const double* __restrict__ x,
+                                                    double* __restrict__ y, int64_t n) {
+    __shared__ double part[256];
+    const int64_t i = blockIdx.x;
+    const float* row = M + i * n;
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += 256) s += (double)row[j] * x[j];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) y[i] = part[0];
+}
+
+// Errors of sampled rows against a binary64 reference: max |d|, sum d^2,
+// sum ref^2.  A single block of 1024 threads (deterministic reduction).
+__global__ __launch_bounds__(1024) void k_row_errors(const float* __restrict__ C, int64_t n,
+                                                     const int64_t* __restrict__ rows, int64_t nrows,
+                                                     const double* __restrict__ ref, double* __restrict__ out) {
+    __shared__ double smax[1024], sd2[1024], sr2[1024];
+    double mx = 0.0, d2 = 0.0, r2 = 0.0;
+    const int64_t total = nrows * n;
+    for (int64_t f = threadIdx.x; f < total; f += 1024) {
+        const int64_t i = f / n, j = f - i * n;
+        const double rv = ref[f];
+        const double dv = (double)C[rows[i] * n + j] - rv;
+        mx = fmax(mx, fabs(dv));
+        d2 += dv * dv;
+        r2 += rv * rv;
+    }
+    smax[threadIdx.x] = mx;
+    sd2[threadIdx.x] = d2;
+    sr2[threadIdx.x] = r2;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+            sd2[threadIdx.x] += sd2[threadIdx.x + w];
+            sr2[threadIdx.x] += sr2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = smax[0];
+        out[1] = sd2[0];
+        out[2] = sr2[0];
+    }
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+// as 1, 2, 3", SC'11): ten rounds of the 4x32 bijection with the published
+// multipliers and Weyl key increments.
+struct Philox4 {
+    uint32_t v[4];
+};
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                  uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    return Philox4{{c0, c1, c2, c3}};
+}
+
+// Element e: twelve 24-bit uniforms from counters (e_lo, e_hi, j, 0), j=0..2,
+// key (seed_lo, seed_hi); value = (sum - 6*2^24) * 2^-24 (Irwin-Hall, mean 0,
+// variance 1).  The integer sum is exact and its conversion rounds to nearest
+// even, so any host reproduces the value bit for bit.
+__global__ __launch_bounds__(256) void k_generate_normal(float* __restrict__ X, int64_t count, uint64_t seed) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count) return;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    int32_t s = 0;
+    for (uint32_t j = 0; j < 3; ++j) {
+        const Philox4 r = philox4x32_10((uint32_t)e, (uint32_t)((uint64_t)e >> 32), j, 0u, k0, k1);
+        s += (int32_t)(r.v[0] >> 8) + (int32_t)(r.v[1] >> 8) + (int32_t)(r.v[2] >> 8) + (int32_t)(r.v[3] >> 8);
+    }
+    X[e] = (float)(s - 6 * (1 << 24)) * (1.0f / 16777216.0f);
+}
+
+// Deterministic binary64 sum of X: kSumBlocks blocks sum contiguous chunks
+// with a fixed tree into partials, then one block sums the partials.
+constexpr int kSumBlocks = 256;
+__global__ __launch_bounds__(256) void k_sum_stage1(const float* __restrict__ X, int64_t count,
+                                                    double* __restrict__ partials) {
+    __shared__ double part[256];
+    const int64_t chunk = (count + kSumBlocks - 1) / kSumBlocks;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < count ? lo + chunk : count;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += (double)X[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = part[0];
+}
+__global__ __launch_bounds__(256) void k_sum_stage2(const double* __restrict__ partials, double* __restrict__ out) {
+    __shared__ double part[256];
+    part[threadIdx.x] = partials[threadIdx.x];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = part[0];
+}
+
+hipError_t launch_sum_f64(const float* X, int64_t count, double* partials, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_stage1, dim3(kSumBlocks), dim3(256), 0, st, X, count, partials);
+    hipLaunchKernelGGL(k_sum_stage2, dim3(1), dim3(256), 0, st, partials, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec_f64(const float* M, const double* x, double* y, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_matvec_f64, dim3((unsigned)n), dim3(256), 0, st, M, x, y, n);
+    return hipGetLastError();
+}
+hipError_t launch_row_errors(const float* C, int64_t n, const int64_t* rows, int64_t nrows, const double* ref,
+                             double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_row_errors, dim3(1), dim3(1024), 0, st, C, n, rows, nrows, ref, out);
+    return hipGetLastError();
+}
+hipError_t launch_generate_normal(float* X, int64_t count, uint64_t seed, hipStream_t st) {
+    const int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(k_generate_normal, dim3((unsigned)blocks), dim3(256), 0, st, X, count, seed);
+    return hipGetLastError();
+}
+
+}  // namespace stk

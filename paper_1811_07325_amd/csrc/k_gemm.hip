@@ -1,0 +1,369 @@
+// Leaf products of the Strassen recursion (Section III-C-2, Algorithm 4):
+// one persistent, grouped launch multiplies every leaf pair M_id = S_id T_id
+// (7^depth of them per problem, all problems of a batch) on the matrix cores.
+//
+//  k_gemm_f32   binary32 operands read in place (views included), MFMA
+//               v_mfma_f32_16x16x4_f32, binary32 accumulation.
+//  k_gemm_bf16  operands pre-split into P bf16 planes (A row-major, B
+//               transposed so both are k-contiguous), MFMA
+//               v_mfma_f32_16x16x32_bf16 over the cross products of the
+//               planes whose magnitude matters, binary32 accumulation.
+//
+// Both: 256 threads = 4 waves in a 2 x 2 arrangement, each wave a
+// (BM/2) x (BN/2) sub-tile of 16 x 16 MFMA blocks; K advances in steps of 32
+// through a double-buffered LDS tile fed from registers, so the global loads
+// of step k+1 are in flight while step k runs on the matrix cores.
+// Tile order is static (no atomics, no split-K): tile t of the grid-stride
+// loop is remapped so that the blocks of one XCD (blockIdx mod 8) work on
+// consecutive tiles, and tiles inside a leaf are visited in groups of 8 tile
+// rows so the A and B panels in flight are shared through that XCD's L2.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace stk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kGemmThreads = 256;
+constexpr int kGroupRows = 8;
+
+// Tile coordinates of logical tile `r` of a leaf with tm_cnt x tn_cnt tiles,
+// visiting groups of kGroupRows tile rows column by column.
+__device__ __forceinline__ void tile_coords(int64_t r, int64_t tm_cnt, int64_t tn_cnt, int64_t& tm,
+                                            int64_t& tn) {
+    const int64_t per_group = (int64_t)kGroupRows * tn_cnt;
+    const int64_t g = r / per_group;
+    const int64_t first = g * kGroupRows;
+    const int64_t rows = (tm_cnt - first) < kGroupRows ? (tm_cnt - first) : kGroupRows;
+    const int64_t in = r - g * per_group;
+    tm = first + in % rows;
+    tn = in / rows;
+}
+
+// Block b of a G-block grid (G a multiple of 8) -> its logical slot, so the
+// G/8 blocks of XCD x take slots [x*G/8, (x+1)*G/8).
+__device__ __forceinline__ int64_t xcd_slot(int64_t b, int64_t G) {
+    if (G % 8) return b;
+    return (b % 8) * (G / 8) + b / 8;
+}
+
+// ---------------------------------------------------------------------------
+// binary32 leaf GEMM.
+// ---------------------------------------------------------------------------
+template <class Src, int BM, int BN>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm_f32(Src src, int64_t total_tiles) {
+    constexpr int BK = 32;
+    constexpr int LDA = BK + 4;          // As[m][k], k contiguous (row 144 B)
+    constexpr int LDB = BN + 4;          // Bs[k][n], n contiguous
+    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+    constexpr int A_LD = BM * BK / 4 / kGemmThreads;   // float4 loads per thread
+    constexpr int B_LD = BK * BN / 4 / kGemmThreads;
+    __shared__ __attribute__((aligned(16))) float As[2][BM * LDA];
+    __shared__ __attribute__((aligned(16))) float Bs[2][BK * LDB];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t G = gridDim.x;
+    const int64_t slot = xcd_slot(blockIdx.x, G);
+
+    for (int64_t t = slot; t < total_tiles; t += G) {
+        int64_t local;
+        const ProbDesc& d = src.get(src.locate(t, local));
+        const int64_t L = d.leaf;
+        const int64_t tm_cnt = L / BM, tn_cnt = L / BN, tpl = tm_cnt * tn_cnt;
+        const int64_t leaf = local / tpl;
+        int64_t tm, tn;
+        tile_coords(local - leaf * tpl, tm_cnt, tn_cnt, tm, tn);
+        const float *Ap, *Bp;
+        int64_t lda, ldb;
+        resolve(d, 0, d.depth, leaf, Ap, lda);
+        resolve(d, 1, d.depth, leaf, Bp, ldb);
+        float* Cp;
+        int64_t ldc;
+        if (d.depth == 0) { Cp = d.C; ldc = d.n; }
+        else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * L * L; ldc = L; }
+        const bool crop = d.depth == 0 && d.bounded0;   // depth 0 writes C directly
+        const int64_t m0 = tm * BM, n0 = tn * BN;
+
+        f32x4 acc[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        float4 ra[A_LD], rb[B_LD];
+        auto gload = [&](int64_t k0) {
+#pragma unroll
+            for (int i = 0; i < A_LD; ++i) {
+                const int idx = tid + kGemmThreads * i;
+                const int row = idx / (BK / 4), kq = idx % (BK / 4);
+                ra[i] = *reinterpret_cast<const float4*>(Ap + (m0 + row) * lda + k0 + 4 * kq);
+            }
+#pragma unroll
+            for (int i = 0; i < B_LD; ++i) {
+                const int idx = tid + kGemmThreads * i;
+                const int kr = idx / (BN / 4), nq = idx % (BN / 4);
+                rb[i] = *reinterpret_cast<const float4*>(Bp + (k0 + kr) * ldb + n0 + 4 * nq);
+            }
+        };
+        auto sstore = [&](int buf) {
+#pragma unroll
+            for (int i = 0; i < A_LD; ++i) {
+                const int idx = tid + kGemmThreads * i;
+                const int row = idx / (BK / 4), kq = idx % (BK / 4);
+                *reinterpret_cast<float4*>(&As[buf][row * LDA + 4 * kq]) = ra[i];
+            }
+#pragma unroll
+            for (int i = 0; i < B_LD; ++i) {
+                const int idx = tid + kGemmThreads * i;
+                const int kr = idx / (BN / 4), nq = idx % (BN / 4);
+                *reinterpret_cast<float4*>(&Bs[buf][kr * LDB + 4 * nq]) = rb[i];
+            }
+        };
+
+        const int64_t KT = L / BK;
+        gload(0);
+        sstore(0);
+        __syncthreads();
+        for (int64_t kt = 0; kt < KT; ++kt) {
+            const int buf = (int)(kt & 1);
+            if (kt + 1 < KT) gload((kt + 1) * BK);
+            const float* as = As[buf];
+            const float* bs = Bs[buf];
+#pragma unroll
+            for (int ks = 0; ks < BK / 16; ++ks) {
+                // MFMA s of this step takes k = 16ks + 4g + s from lane group g.
+                float4 a[TM];
+                float b[TN][4];
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    a[i] = *reinterpret_cast<const float4*>(&as[(wm * WM + 16 * i + li) * LDA + 16 * ks + 4 * lg]);
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        b[j][s] = bs[(16 * ks + 4 * lg + s) * LDB + wn * WN + 16 * j + li];
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) {
+                        const float av = s == 0 ? a[i].x : s == 1 ? a[i].y : s == 2 ? a[i].z : a[i].w;
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[j][s], acc[i][j], 0, 0, 0);
+                    }
+            }
+            if (kt + 1 < KT) sstore(buf ^ 1);
+            __syncthreads();
+        }
+
+        // D layout of a 16x16 MFMA block: lane (li, lg), element r -> row 4lg + r, column li.
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
+                    const int64_t col = n0 + wn * WN + 16 * j + li;
+                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r];
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bf16-split leaf GEMM.  Planes p = 0 (hi), 1 (mid), 2 (lo).  The products
+// kept are those of magnitude >= 2^-16 relative to hi*hi; they are issued
+// smallest first into one binary32 accumulator.
+// ---------------------------------------------------------------------------
+template <int P>
+struct SplitProducts;
+template <>
+struct SplitProducts<2> {
+    static constexpr int count = 3;
+    __device__ static constexpr int a(int q) { return q == 0 ? 1 : 0; }
+    __device__ static constexpr int b(int q) { return q == 1 ? 1 : 0; }
+};
+template <>
+struct SplitProducts<3> {
+    // (mid,mid), (lo,hi), (hi,lo), (mid,hi), (hi,mid), (hi,hi)
+    static constexpr int count = 6;
+    __device__ static constexpr int a(int q) {
+        return q == 0 ? 1 : q == 1 ? 2 : q == 2 ? 0 : q == 3 ? 1 : 0;
+    }
+    __device__ static constexpr int b(int q) {
+        return q == 0 ? 1 : q == 1 ? 0 : q == 2 ? 2 : q == 3 ? 0 : q == 4 ? 1 : 0;
+    }
+};
+
+template <class Src, int BM, int BN, int P>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t total_tiles) {
+    constexpr int BK = 32;
+    constexpr int LDK = BK + 8;                   // uint16 per LDS row (80 B)
+    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+    constexpr int A_LD = BM * (BK / 8) / kGemmThreads;  // 16-byte loads per plane
+    constexpr int B_LD = BN * (BK / 8) / kGemmThreads;
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][P][BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][P][BN * LDK];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t G = gridDim.x;
+    const int64_t slot = xcd_slot(blockIdx.x, G);
+
+    for (int64_t t = slot; t < total_tiles; t += G) {
+        int64_t local;
+        const ProbDesc& d = src.get(src.locate(t, local));
+        const int64_t L = d.leaf, LL = L * L;
+        const int64_t tm_cnt = L / BM, tn_cnt = L / BN, tpl = tm_cnt * tn_cnt;
+        const int64_t leaf = local / tpl;
+        int64_t tm, tn;
+        tile_coords(local - leaf * tpl, tm_cnt, tn_cnt, tm, tn);
+        const uint16_t* Ah = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_a + leaf * P * LL;
+        const uint16_t* Bh = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_b + leaf * P * LL;
+        float* Cp;
+        int64_t ldc;
+        if (d.depth == 0) { Cp = d.C; ldc = d.n; }
+        else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
+        const bool crop = d.depth == 0 && d.bounded0;
+        const int64_t m0 = tm * BM, n0 = tn * BN;
+
+        f32x4 acc[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        uint4 ra[P][A_LD], rb[P][B_LD];
+        auto gload = [&](int64_t k0) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int i = 0; i < A_LD; ++i) {
+                    const int idx = tid + kGemmThreads * i;
+                    const int row = idx >> 2, q = idx & 3;
+                    ra[p][i] = *reinterpret_cast<const uint4*>(Ah + p * LL + (m0 + row) * L + k0 + 8 * q);
+                }
+#pragma unroll
+                for (int i = 0; i < B_LD; ++i) {
+                    const int idx = tid + kGemmThreads * i;
+                    const int row = idx >> 2, q = idx & 3;
+                    rb[p][i] = *reinterpret_cast<const uint4*>(Bh + p * LL + (n0 + row) * L + k0 + 8 * q);
+                }
+            }
+        };
+        auto sstore = [&](int buf) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int i = 0; i < A_LD; ++i) {
+                    const int idx = tid + kGemmThreads * i;
+                    const int row = idx >> 2, q = idx & 3;
+                    *reinterpret_cast<uint4*>(&As[buf][p][row * LDK + 8 * q]) = ra[p][i];
+                }
+#pragma unroll
+                for (int i = 0; i < B_LD; ++i) {
+                    const int idx = tid + kGemmThreads * i;
+                    const int row = idx >> 2, q = idx & 3;
+                    *reinterpret_cast<uint4*>(&Bs[buf][p][row * LDK + 8 * q]) = rb[p][i];
+                }
+            }
+        };
+
+        const int64_t KT = L / BK;
+        gload(0);
+        sstore(0);
+        __syncthreads();
+        for (int64_t kt = 0; kt < KT; ++kt) {
+            const int buf = (int)(kt & 1);
+            if (kt + 1 < KT) gload((kt + 1) * BK);
+            bf16x8 a[P][TM], b[P][TN];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    a[p][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                                                             &As[buf][p][(wm * WM + 16 * i + li) * LDK + 8 * lg]));
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    b[p][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                                                             &Bs[buf][p][(wn * WN + 16 * j + li) * LDK + 8 * lg]));
+            }
+#pragma unroll
+            for (int q = 0; q < SplitProducts<P>::count; ++q)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            a[SplitProducts<P>::a(q)][i], b[SplitProducts<P>::b(q)][j], acc[i][j], 0, 0, 0);
+            if (kt + 1 < KT) sstore(buf ^ 1);
+            __syncthreads();
+        }
+
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
+                    const int64_t col = n0 + wn * WN + 16 * j + li;
+                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r];
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+template <class Src, int BM, int BN>
+static hipError_t launch_f32_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_gemm_f32<Src, BM, BN>), dim3(grid), dim3(kGemmThreads), 0, st, s, tiles);
+    return hipGetLastError();
+}
+template <class Src, int BM, int BN, int P>
+static hipError_t launch_bf16_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_gemm_bf16<Src, BM, BN, P>), dim3(grid), dim3(kGemmThreads), 0, st, s, tiles);
+    return hipGetLastError();
+}
+
+template <int BM, int BN>
+static int occ_f32() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_f32<OneProb, BM, BN>, kGemmThreads, 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+template <int BM, int BN, int P>
+static int occ_bf16() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<OneProb, BM, BN, P>, kGemmThreads, 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+int gemm_blocks_per_cu(int planes, int tile) {
+    // Occupancy does not depend on the descriptor source.
+    if (planes == 0) return tile == 128 ? occ_f32<128, 128>() : occ_f32<64, 64>();
+    if (planes == 2) return tile == 128 ? occ_bf16<128, 128, 2>() : occ_bf16<64, 64, 2>();
+    return tile == 128 ? occ_bf16<128, 128, 3>() : occ_bf16<64, 64, 3>();
+}
+
+template <class Src>
+hipError_t launch_gemm(const Src& s, int planes, int tile, int64_t tiles, int grid, hipStream_t st) {
+    if (planes == 0) return tile == 128 ? launch_f32_t<Src, 128, 128>(s, tiles, grid, st)
+                                        : launch_f32_t<Src, 64, 64>(s, tiles, grid, st);
+    if (planes == 2) return tile == 128 ? launch_bf16_t<Src, 128, 128, 2>(s, tiles, grid, st)
+                                        : launch_bf16_t<Src, 64, 64, 2>(s, tiles, grid, st);
+    return tile == 128 ? launch_bf16_t<Src, 128, 128, 3>(s, tiles, grid, st)
+                       : launch_bf16_t<Src, 64, 64, 3>(s, tiles, grid, st);
+}
+
+template hipError_t launch_gemm<OneProb>(const OneProb&, int, int, int64_t, int, hipStream_t);
+template hipError_t launch_gemm<TableProb>(const TableProb&, int, int, int64_t, int, hipStream_t);
+
+}  // namespace stk

@@ -1,0 +1,381 @@
+// HBM-streaming kernels of the Strassen hot path (gfx950):
+//   k_pad      zero-padded copy of A and B (classical product of a padded size)
+//   k_divide   one recursion level of the divide step: the operand sums of
+//              all 7^l nodes of level l (Algorithm 1; Section III-C-1)
+//   k_split    last divide level of the bf16 paths: the seven operand pairs of
+//              every level-(k-1) node, split into bf16 planes; B-side planes
+//              are written transposed (k contiguous) for the leaf products
+//   k_combine  one recursion level of the combine step (Algorithm 1;
+//              Section III-C-3): C11..C22 of every node from M1..M7
+//
+// All are memory-bound streams: each thread moves 16-byte vectors, issues all
+// of its loads before any store, and the block -> (node, chunk) map keeps a
+// block inside one node so the walk that finds the node's operands runs once
+// per block.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace stk {
+
+constexpr int kStreamThreads = 256;
+constexpr int kStreamUnroll = 4;                          // float4 positions per thread
+constexpr int kStreamPerBlock = kStreamThreads * kStreamUnroll;
+
+__device__ __forceinline__ float4 f4add(float4 a, float4 b) {
+    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ float4 f4sub(float4 a, float4 b) {
+    return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+}
+
+// Four consecutive elements of row r, columns c..c+3 of an n x n row-major
+// matrix, zero outside (used only where the source is the unpadded user
+// matrix, whose rows need not be 16-byte aligned).
+__device__ __forceinline__ float4 load4_bounded(const float* X, int64_t n, int64_t r, int64_t c) {
+    float v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (r < n && c + e < n) ? X[r * n + c + e] : 0.0f;
+    return make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Zero-padded copies A -> pad_a, B -> pad_b (np x np).  grid.y = side.
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(kStreamThreads) void k_pad(Src src) {
+    int64_t local;
+    const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
+    const int side = blockIdx.y;
+    const float* X = side ? d.B : d.A;
+    float4* out = reinterpret_cast<float4*>(reinterpret_cast<float*>(d.ws) + (side ? d.pad_b : d.pad_a));
+    const int64_t rq = d.np / 4;
+    const int64_t total = d.np * rq;
+#pragma unroll
+    for (int u = 0; u < kStreamUnroll; ++u) {
+        const int64_t f = local * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
+        if (f < total) {
+            const int64_t r = f / rq, c = (f - r * rq) * 4;
+            out[f] = load4_bounded(X, d.n, r, c);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Divide, level l: for every node of the level, read its four quadrants once
+// and write the materialised operand blocks (5 per side, or all 7 when the
+// level-0 source is the unpadded user matrix, read with bounds so the padding
+// is formed on the fly).  grid.y = side (0: A, 1: B).
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(kStreamThreads) void k_divide(Src src, int level) {
+    int64_t local;
+    const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
+    const int side = blockIdx.y;
+    const bool bounded = (level == 0) && d.bounded0;
+    const int64_t m = d.np >> level, h = m >> 1;
+    const int64_t hq = h >> 2;               // float4 per quadrant row
+    const int64_t q4 = h * hq;               // float4 per quadrant
+    const int64_t bpn = (q4 + kStreamPerBlock - 1) / kStreamPerBlock;
+    const int64_t node = local / bpn, chunk = local - node * bpn;
+
+    const float* X;
+    int64_t ld;
+    resolve(d, side, level, node, X, ld);
+    const int slots = d.div_slots[level];
+    float4* out = reinterpret_cast<float4*>(reinterpret_cast<float*>(d.ws) +
+                                            (side ? d.div_b[level] : d.div_a[level]) +
+                                            node * slots * h * h);
+
+    float4 q11[kStreamUnroll], q12[kStreamUnroll], q21[kStreamUnroll], q22[kStreamUnroll];
+    int64_t fs[kStreamUnroll];
+#pragma unroll
+    for (int u = 0; u < kStreamUnroll; ++u) {
+        const int64_t f = chunk * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
+        fs[u] = f;
+        if (f < q4) {
+            const int64_t r = f / hq, c = (f - r * hq) * 4;
+            if (bounded) {
+                q11[u] = load4_bounded(X, d.n, r, c);
+                q12[u] = load4_bounded(X, d.n, r, c + h);
+                q21[u] = load4_bounded(X, d.n, r + h, c);
+                q22[u] = load4_bounded(X, d.n, r + h, c + h);
+            } else {
+                const float* p = X + r * ld + c;
+                q11[u] = *reinterpret_cast<const float4*>(p);
+                q12[u] = *reinterpret_cast<const float4*>(p + h);
+                q21[u] = *reinterpret_cast<const float4*>(p + h * ld);
+                q22[u] = *reinterpret_cast<const float4*>(p + h * ld + h);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kStreamUnroll; ++u) {
+        const int64_t f = fs[u];
+        if (f >= q4) continue;
+        float4* o = out + f;
+        if (side == 0) {
+            if (slots == 7) {                       // S1..S7
+                o[0] = f4add(q11[u], q22[u]);
+                o[q4] = f4add(q21[u], q22[u]);
+                o[2 * q4] = q11[u];
+                o[3 * q4] = q22[u];
+                o[4 * q4] = f4add(q11[u], q12[u]);
+                o[5 * q4] = f4sub(q21[u], q11[u]);
+                o[6 * q4] = f4sub(q12[u], q22[u]);
+            } else {                                // S1, S2, S5, S6, S7
+                o[0] = f4add(q11[u], q22[u]);
+                o[q4] = f4add(q21[u], q22[u]);
+                o[2 * q4] = f4add(q11[u], q12[u]);
+                o[3 * q4] = f4sub(q21[u], q11[u]);
+                o[4 * q4] = f4sub(q12[u], q22[u]);
+            }
+        } else {
+            if (slots == 7) {                       // T1..T7
+                o[0] = f4add(q11[u], q22[u]);
+                o[q4] = q11[u];
+                o[2 * q4] = f4sub(q12[u], q22[u]);
+                o[3 * q4] = f4sub(q21[u], q11[u]);
+                o[4 * q4] = q22[u];
+                o[5 * q4] = f4add(q11[u], q12[u]);
+                o[6 * q4] = f4add(q21[u], q22[u]);
+            } else {                                // T1, T3, T4, T6, T7
+                o[0] = f4add(q11[u], q22[u]);
+                o[q4] = f4sub(q12[u], q22[u]);
+                o[2 * q4] = f4sub(q21[u], q11[u]);
+                o[3 * q4] = f4add(q11[u], q12[u]);
+                o[4 * q4] = f4add(q21[u], q22[u]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bf16 split.  hi = RNE(x), then mid/lo = RNE(residual); residuals are exact
+// in binary32.  v_cvt_pk_bf16_f32 rounds to nearest even.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+    __bf16 b = (__bf16)x;
+    return __builtin_bit_cast(uint16_t, b);
+}
+__device__ __forceinline__ float bf16_value(uint16_t b) {
+    return __uint_as_float(((uint32_t)b) << 16);
+}
+
+// Seven operand values of the products of one node at one position
+// (Algorithm 1), A side: S1..S7; B side: T1..T7.
+__device__ __forceinline__ void seven_a(float a11, float a12, float a21, float a22, float* s) {
+    s[0] = a11 + a22; s[1] = a21 + a22; s[2] = a11; s[3] = a22;
+    s[4] = a11 + a12; s[5] = a21 - a11; s[6] = a12 - a22;
+}
+__device__ __forceinline__ void seven_b(float b11, float b12, float b21, float b22, float* t) {
+    t[0] = b11 + b22; t[1] = b11; t[2] = b12 - b22; t[3] = b21 - b11;
+    t[4] = b22; t[5] = b11 + b12; t[6] = b21 + b22;
+}
+
+__device__ __forceinline__ float load1(const float* X, int64_t ld, int64_t n, int64_t r, int64_t c, bool bounded) {
+    if (bounded) return (r < n && c < n) ? X[r * n + c] : 0.0f;
+    return X[r * ld + c];
+}
+
+// Last divide level of the bf16 paths.  NOUT = 7: every node of level
+// depth-1 gives the seven operand pairs of its children (the leaves);
+// NOUT = 1 (depth 0): the root operands themselves.  Each output block
+// (leaf edge L) is written as P bf16 planes; A side row-major, B side
+// transposed (element (k, j) of T at j*L + k).
+//   A side: a thread owns 8 consecutive columns of one row.
+//   B side: a thread owns 8 consecutive rows of one column.
+template <int NOUT, int P>
+__device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t node, int64_t f, bool bounded) {
+    const int64_t L = d.leaf;
+    const int plevel = (NOUT == 7) ? d.depth - 1 : 0;
+    const float* X;
+    int64_t ld;
+    resolve(d, side, plevel, node, X, ld);
+    uint16_t* base = reinterpret_cast<uint16_t*>(d.ws) + (side ? d.leaf_b : d.leaf_a) +
+                     node * (int64_t)NOUT * P * L * L;
+    const int64_t LL = L * L;
+    // (r0, c0): first element; the thread's 8 elements step along dc (A: a
+    // row, B: a column); the output offset of element e of block o, plane p
+    // is ((o*P + p)*LL + out0 + e) with out0 below.
+    int64_t r0, c0, dr, dc, out0;
+    if (side == 0) {
+        r0 = f / (L / 8); c0 = (f - r0 * (L / 8)) * 8; dr = 0; dc = 1; out0 = r0 * L + c0;
+    } else {
+        c0 = f % L; r0 = (f / L) * 8; dr = 1; dc = 0; out0 = c0 * L + r0;
+    }
+    float v[NOUT][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t r = r0 + e * dr, c = c0 + e * dc;
+        if (NOUT == 7) {
+            const float x11 = load1(X, ld, d.n, r, c, bounded);
+            const float x12 = load1(X, ld, d.n, r, c + L, bounded);
+            const float x21 = load1(X, ld, d.n, r + L, c, bounded);
+            const float x22 = load1(X, ld, d.n, r + L, c + L, bounded);
+            float s7[7];
+            if (side == 0) seven_a(x11, x12, x21, x22, s7);
+            else seven_b(x11, x12, x21, x22, s7);
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) v[o][e] = s7[o];
+        } else {
+            v[0][e] = load1(X, ld, d.n, r, c, bounded);
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+        float res[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) res[e] = v[o][e];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            uint32_t w[4];
+#pragma unroll
+            for (int e = 0; e < 8; e += 2) {
+                const uint16_t b0 = bf16_bits(res[e]), b1 = bf16_bits(res[e + 1]);
+                w[e / 2] = (uint32_t)b0 | ((uint32_t)b1 << 16);
+                res[e] = res[e] - bf16_value(b0);
+                res[e + 1] = res[e + 1] - bf16_value(b1);
+            }
+            uint4* dst = reinterpret_cast<uint4*>(base + ((int64_t)o * P + p) * LL + out0);
+            *dst = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+// grid.y = side.  The source is read with bounds when it is the unpadded
+// user matrix (depth <= 1 with padding).
+template <class Src, int P>
+__global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
+    int64_t local;
+    const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
+    const int side = blockIdx.y;
+    const int64_t L = d.leaf;
+    const int64_t per_node = L * (L / 8);         // thread tasks per node
+    const int64_t bpn = (per_node + kStreamThreads - 1) / kStreamThreads;
+    const int64_t node = local / bpn, chunk = local - node * bpn;
+    const int64_t f = chunk * kStreamThreads + threadIdx.x;
+    if (f >= per_node) return;
+    const bool bounded = d.bounded0 && d.depth <= 1;
+    if (d.depth == 0) split_body<1, P>(d, side, node, f, bounded);
+    else split_body<7, P>(d, side, node, f, bounded);
+}
+
+// ---------------------------------------------------------------------------
+// Combine, level l: node's C quadrants from its children's products M1..M7
+// (Algorithm 1 with C22 = M1 - M2 + M3 + M6), additions left to right.
+// Level 0 writes the user's C, cropping to n x n when padded.
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(kStreamThreads) void k_combine(Src src, int level) {
+    int64_t local;
+    const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
+    const bool crop = (level == 0) && d.bounded0;
+    const int64_t m = d.np >> level, h = m >> 1;
+    const int64_t hq = h >> 2;
+    const int64_t q4 = h * hq;
+    const int64_t bpn = (q4 + kStreamPerBlock - 1) / kStreamPerBlock;
+    const int64_t node = local / bpn, chunk = local - node * bpn;
+
+    const float* wsf = reinterpret_cast<const float*>(d.ws);
+    const float4* in = reinterpret_cast<const float4*>(
+        wsf + ((level + 1 == d.depth) ? d.leaf_m : d.comb[level + 1]) + node * 7 * h * h);
+    float* out;
+    int64_t ldo;
+    if (level == 0) {
+        out = d.C;
+        ldo = d.n;
+    } else {
+        out = reinterpret_cast<float*>(d.ws) + d.comb[level] + node * m * m;
+        ldo = m;
+    }
+#pragma unroll
+    for (int u = 0; u < kStreamUnroll; ++u) {
+        const int64_t f = chunk * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
+        if (f >= q4) continue;
+        const float4 m1 = in[f], m2 = in[q4 + f], m3 = in[2 * q4 + f], m4 = in[3 * q4 + f];
+        const float4 m5 = in[4 * q4 + f], m6 = in[5 * q4 + f], m7 = in[6 * q4 + f];
+        const float4 c11 = f4add(f4sub(f4add(m1, m4), m5), m7);
+        const float4 c12 = f4add(m3, m5);
+        const float4 c21 = f4add(m2, m4);
+        const float4 c22 = f4add(f4add(f4sub(m1, m2), m3), m6);
+        const int64_t r = f / hq, c = (f - r * hq) * 4;
+        if (crop) {
+            const float* v11 = &c11.x; const float* v12 = &c12.x;
+            const float* v21 = &c21.x; const float* v22 = &c22.x;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t cc = c + e;
+                if (r < d.n && cc < d.n) out[r * ldo + cc] = v11[e];
+                if (r < d.n && cc + h < d.n) out[r * ldo + cc + h] = v12[e];
+                if (r + h < d.n && cc < d.n) out[(r + h) * ldo + cc] = v21[e];
+                if (r + h < d.n && cc + h < d.n) out[(r + h) * ldo + cc + h] = v22[e];
+            }
+        } else {
+            float* p = out + r * ldo + c;
+            *reinterpret_cast<float4*>(p) = c11;
+            *reinterpret_cast<float4*>(p + h) = c12;
+            *reinterpret_cast<float4*>(p + h * ldo) = c21;
+            *reinterpret_cast<float4*>(p + h * ldo + h) = c22;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+static int64_t pow7(int l) {
+    int64_t p = 1;
+    for (int i = 0; i < l; ++i) p *= 7;
+    return p;
+}
+
+int64_t blocks_pad(const ProbDesc& d) {
+    return (d.np * (d.np / 4) + kStreamPerBlock - 1) / kStreamPerBlock;
+}
+int64_t blocks_divide(const ProbDesc& d, int level) {
+    const int64_t h = (d.np >> level) >> 1;
+    const int64_t q4 = h * (h / 4);
+    return pow7(level) * ((q4 + kStreamPerBlock - 1) / kStreamPerBlock);
+}
+int64_t blocks_split(const ProbDesc& d) {
+    const int64_t L = d.leaf;
+    const int64_t per_node = L * (L / 8);
+    const int64_t nodes = d.depth > 0 ? pow7(d.depth - 1) : 1;
+    return nodes * ((per_node + kStreamThreads - 1) / kStreamThreads);
+}
+int64_t blocks_combine(const ProbDesc& d, int level) { return blocks_divide(d, level); }
+
+template <class Src>
+hipError_t launch_pad(const Src& s, int64_t blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_pad<Src>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s);
+    return hipGetLastError();
+}
+template <class Src>
+hipError_t launch_divide(const Src& s, int level, int64_t blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_divide<Src>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s, level);
+    return hipGetLastError();
+}
+template <class Src>
+hipError_t launch_split(const Src& s, int planes, int64_t blocks, hipStream_t st) {
+    if (planes == 2)
+        hipLaunchKernelGGL((k_split<Src, 2>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s);
+    else
+        hipLaunchKernelGGL((k_split<Src, 3>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s);
+    return hipGetLastError();
+}
+template <class Src>
+hipError_t launch_combine(const Src& s, int level, int64_t blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_combine<Src>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
+    return hipGetLastError();
+}
+
+template hipError_t launch_pad<OneProb>(const OneProb&, int64_t, hipStream_t);
+template hipError_t launch_pad<TableProb>(const TableProb&, int64_t, hipStream_t);
+template hipError_t launch_divide<OneProb>(const OneProb&, int, int64_t, hipStream_t);
+template hipError_t launch_divide<TableProb>(const TableProb&, int, int64_t, hipStream_t);
+template hipError_t launch_split<OneProb>(const OneProb&, int, int64_t, hipStream_t);
+template hipError_t launch_split<TableProb>(const TableProb&, int, int64_t, hipStream_t);
+template hipError_t launch_combine<OneProb>(const OneProb&, int, int64_t, hipStream_t);
+template hipError_t launch_combine<TableProb>(const TableProb&, int, int64_t, hipStream_t);
+
+}  // namespace stk

@@ -1,0 +1,33 @@
+// Host-side launchers of the device kernels (implemented next to the kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace stk {
+
+// Block counts of one launch for one problem.
+int64_t blocks_pad(const ProbDesc& d);
+int64_t blocks_divide(const ProbDesc& d, int level);
+int64_t blocks_split(const ProbDesc& d);
+int64_t blocks_combine(const ProbDesc& d, int level);
+
+template <class Src> hipError_t launch_pad(const Src& s, int64_t blocks, hipStream_t st);
+template <class Src> hipError_t launch_divide(const Src& s, int level, int64_t blocks, hipStream_t st);
+template <class Src> hipError_t launch_split(const Src& s, int planes, int64_t blocks, hipStream_t st);
+template <class Src> hipError_t launch_combine(const Src& s, int level, int64_t blocks, hipStream_t st);
+template <class Src> hipError_t launch_gemm(const Src& s, int planes, int tile, int64_t tiles, int grid, hipStream_t st);
+
+// Resident blocks per CU of the leaf GEMM for (planes, tile).
+int gemm_blocks_per_cu(int planes, int tile);
+
+// Measurement helpers (k_check.hip).
+hipError_t launch_matvec_f64(const float* M, const double* x, double* y, int64_t n, hipStream_t st);
+hipError_t launch_row_errors(const float* C, int64_t n, const int64_t* rows, int64_t nrows,
+                             const double* ref, double* out, hipStream_t st);
+hipError_t launch_generate_normal(float* X, int64_t count, uint64_t seed, hipStream_t st);
+// Binary64 sum of count floats; partials must hold 256 doubles.
+hipError_t launch_sum_f64(const float* X, int64_t count, double* partials, double* out, hipStream_t st);
+
+}  // namespace stk

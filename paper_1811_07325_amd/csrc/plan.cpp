@@ -1,0 +1,179 @@
+// Planner for one Strassen multiply (see plan.hpp).
+//
+// Recursion depth k (Algorithm 2 recurses until the block size is reached; here
+// the leaf size is n_pad / 2^k).  Workspace regions, in order:
+//   div_a[l], div_b[l]  binary32 operand blocks written by the divide of
+//                       level l: 5 per node (the other two operands are views
+//                       of the parent's quadrants), 7 at level 0 when the user
+//                       matrix must be zero-padded on the fly;
+//   leaf_a, leaf_b      bf16 paths: the split leaf operands (P planes each,
+//                       B side transposed), written by the last divide level;
+//   leaf_m              the 7^k leaf products;
+//   comb[l]             combine output of level l >= 1.  These reuse the
+//                       front of the workspace: the divide outputs are dead
+//                       once the leaf products are formed, and comb[l] never
+//                       overlaps comb[l+1] (read while comb[l] is written).
+//   pad_a, pad_b        depth-0 binary32 only: zero-padded copies.
+#include "plan.hpp"
+
+#include <stdexcept>
+
+#include "../../include/stark.h"
+
+namespace stk {
+
+int64_t pow7(int l) {
+    int64_t p = 1;
+    for (int i = 0; i < l; ++i) p *= 7;
+    return p;
+}
+
+int64_t padded_size(int64_t n, int depth) {
+    const int64_t q = kLeafGranule << depth;
+    return (n + q - 1) / q * q;
+}
+
+int max_depth_for(int64_t n) {
+    int k = 0;
+    while (k < STARK_MAX_DEPTH && k < STK_MAXD - 1) {
+        // depth k+1 is usable while padding adds at most a quarter to the
+        // minimal padded edge and every leaf keeps at least one 64-wide tile
+        const int64_t np = padded_size(n, k + 1);
+        if ((np >> (k + 1)) < kLeafGranule || 4 * np > 5 * padded_size(n, 0)) break;
+        ++k;
+    }
+    return k;
+}
+
+int planes_for(int precision) {
+    switch (precision) {
+        case STARK_FP32: return 0;
+        case STARK_BF16X3: return 2;
+        case STARK_BF16X6: return 3;
+        default: return -1;
+    }
+}
+
+static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
+    p = Plan();
+    if (n <= 0) return "n must be positive";
+    if (n > (int64_t)1 << 20) return "n too large";
+    if (depth < 0 || depth > max_depth_for(n)) return "depth out of range for n";
+    const int planes = planes_for(precision);
+    if (planes < 0) return "unknown precision";
+    p.n = n;
+    p.depth = depth;
+    p.precision = precision;
+    p.planes = planes;
+    p.np = padded_size(n, depth);
+    p.leaf = p.np >> depth;
+    p.padded = (p.np != n);
+    p.tile = (p.leaf % 128 == 0) ? 128 : 64;
+    for (int l = 0; l < STK_MAXD; ++l) {
+        p.div_a[l] = p.div_b[l] = p.comb[l] = -1;
+        p.div_slots[l] = 0;
+    }
+    const int64_t N = p.np * p.np;
+    int64_t off = 0;
+    if (depth == 0) {
+        if (planes == 0) {
+            if (p.padded) {
+                p.pad_a = off; off = align256(off + N * 4);
+                p.pad_b = off; off = align256(off + N * 4);
+            }
+        } else {
+            p.leaf_a = off; off = align256(off + planes * N * 2);
+            p.leaf_b = off; off = align256(off + planes * N * 2);
+        }
+        p.leaf_m = -1;   // the product goes straight to C
+        p.fp32_levels = 0;
+        p.bytes = (size_t)(off > 0 ? off : 256);
+        return "";
+    }
+    p.fp32_levels = planes == 0 ? depth : depth - 1;
+    for (int l = 0; l < p.fp32_levels; ++l) {
+        const int slots = (l == 0 && p.padded) ? 7 : 5;
+        const int64_t h = (p.np >> l) >> 1;
+        const int64_t sz = (int64_t)slots * pow7(l) * h * h * 4;
+        p.div_slots[l] = slots;
+        p.div_a[l] = off; off = align256(off + sz);
+        p.div_b[l] = off; off = align256(off + sz);
+    }
+    if (planes > 0) {
+        const int64_t sz = pow7(depth) * planes * p.leaf * p.leaf * 2;
+        p.leaf_a = off; off = align256(off + sz);
+        p.leaf_b = off; off = align256(off + sz);
+    }
+    const int64_t dead_end = off;
+    p.leaf_m = off;
+    off = align256(off + pow7(depth) * p.leaf * p.leaf * 4);
+    int64_t c = 0;
+    for (int l = depth - 1; l >= 1; --l) {
+        const int64_t m = p.np >> l;
+        p.comb[l] = c;
+        c = align256(c + pow7(l) * m * m * 4);
+    }
+    if (c > dead_end) throw std::logic_error("combine outputs do not fit the divide region");
+    p.bytes = (size_t)off;
+    return "";
+}
+
+ProbDesc make_desc(const Plan& p, const float* A, const float* B, float* C, void* ws) {
+    ProbDesc d{};
+    d.A = A;
+    d.B = B;
+    d.C = C;
+    d.ws = static_cast<char*>(ws);
+    d.n = p.n;
+    d.np = p.np;
+    d.leaf = p.leaf;
+    d.depth = p.depth;
+    d.planes = p.planes;
+    d.bounded0 = p.padded ? 1 : 0;
+    d.gemm_tile = p.tile;
+    for (int l = 0; l < STK_MAXD; ++l) {
+        d.div_a[l] = p.div_a[l] >= 0 ? p.div_a[l] / 4 : -1;
+        d.div_b[l] = p.div_b[l] >= 0 ? p.div_b[l] / 4 : -1;
+        d.div_slots[l] = p.div_slots[l];
+        d.comb[l] = p.comb[l] >= 0 ? p.comb[l] / 4 : -1;
+    }
+    d.leaf_a = p.leaf_a >= 0 ? p.leaf_a / 2 : -1;
+    d.leaf_b = p.leaf_b >= 0 ? p.leaf_b / 2 : -1;
+    d.leaf_m = p.leaf_m >= 0 ? p.leaf_m / 4 : -1;
+    d.pad_a = p.pad_a >= 0 ? p.pad_a / 4 : -1;
+    d.pad_b = p.pad_b >= 0 ? p.pad_b / 4 : -1;
+    return d;
+}
+
+Work plan_work(const Plan& p) {
+    Work w{};
+    const double L = (double)p.leaf;
+    const double leaves = (double)pow7(p.depth);
+    w.leaf_flops = 2.0 * L * L * L * leaves;
+    const int prods = p.planes == 0 ? 1 : p.planes == 2 ? 3 : 6;
+    w.mfma_flops = w.leaf_flops * prods;
+    for (int l = 0; l < p.fp32_levels; ++l) {
+        const double h = (double)(p.np >> l) / 2.0;
+        const double nodes = (double)pow7(l);
+        // read 4 quadrants per side, write `slots` blocks per side
+        w.divide_bytes += 2.0 * nodes * (4.0 + p.div_slots[l]) * h * h * 4.0;
+    }
+    if (p.planes > 0) {
+        // last level: read the parent's 4 quadrants (binary32), write 7 x P
+        // bf16 planes per side; depth 0 reads and writes the whole operands
+        const double nodes = p.depth > 0 ? (double)pow7(p.depth - 1) : 1.0;
+        const double in_blocks = p.depth > 0 ? 4.0 : 1.0, out_blocks = p.depth > 0 ? 7.0 : 1.0;
+        w.split_bytes = 2.0 * nodes * (in_blocks * L * L * 4.0 + out_blocks * p.planes * L * L * 2.0);
+    }
+    for (int l = p.depth - 1; l >= 0; --l) {
+        const double h = (double)(p.np >> l) / 2.0;
+        const double nodes = (double)pow7(l);
+        w.combine_bytes += nodes * (7.0 + 4.0) * h * h * 4.0;
+    }
+    if (p.pad_a >= 0) w.pad_bytes = 2.0 * ((double)p.n * p.n * 4.0 + (double)p.np * p.np * 4.0);
+    return w;
+}
+
+}  // namespace stk

@@ -1,0 +1,51 @@
+// Planner: padded size, leaf size, workspace layout and launch sequence of one
+// multiply.  Pure host arithmetic (no HIP calls), so it is testable anywhere.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "common.hpp"
+
+namespace stk {
+
+constexpr int64_t kLeafGranule = 64;   // leaf edge is a multiple of this
+
+struct Plan {
+    int64_t n = 0, np = 0, leaf = 0;
+    int depth = 0;
+    int precision = 0;   // stark_precision
+    int planes = 0;      // 0, 2, 3
+    int tile = 128;      // leaf GEMM tile edge
+    bool padded = false;
+    // Byte offsets (-1 = region absent).
+    int64_t div_a[STK_MAXD], div_b[STK_MAXD];
+    int div_slots[STK_MAXD];
+    int64_t leaf_a = -1, leaf_b = -1, leaf_m = -1;
+    int64_t comb[STK_MAXD];
+    int64_t pad_a = -1, pad_b = -1;
+    size_t bytes = 0;
+    int fp32_levels = 0;  // binary32 divide levels launched (0 .. depth)
+};
+
+int64_t pow7(int l);
+int64_t padded_size(int64_t n, int depth);
+int max_depth_for(int64_t n);
+int planes_for(int precision);  // -1 if unknown
+
+// Returns "" on success, else the reason the plan is invalid.
+std::string make_plan(int64_t n, int depth, int precision, Plan& out);
+
+// Descriptor of the plan with user/workspace pointers filled in.
+ProbDesc make_desc(const Plan& p, const float* A, const float* B, float* C, void* ws);
+
+// Algorithmic work of one multiply (for reports): leaf flops (useful, 2 L^3
+// per leaf) and the bytes the divide / split / combine phases must move.
+struct Work {
+    double leaf_flops, mfma_flops;
+    double divide_bytes, split_bytes, combine_bytes, pad_bytes;
+};
+Work plan_work(const Plan& p);
+
+}  // namespace stk

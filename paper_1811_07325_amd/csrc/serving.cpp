@@ -1,0 +1,387 @@
+// Serving engine (see engine.hpp) and the stark_submit / stark_poll /
+// stark_stats entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+
+#include "ctx.hpp"
+#include "engine.hpp"
+#include "launch.hpp"
+
+namespace stk {
+
+double now_us() {
+    using namespace std::chrono;
+    return duration<double, std::micro>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ----------------------------------------------------------------------------
+// Arena
+// ----------------------------------------------------------------------------
+void Arena::reset(size_t size) {
+    free_.clear();
+    size_ = size;
+    used_ = 0;
+    if (size) free_[0] = size;
+}
+
+bool Arena::alloc(size_t bytes, size_t* off) {
+    bytes = (bytes + 255) / 256 * 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t start = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[start] = rest;
+            used_ += bytes;
+            return true;
+        }
+    }
+    return false;
+}
+
+void Arena::free(size_t off, size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    // merge with the next range
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        free_.erase(nx);
+    }
+    // merge with the previous range
+    if (it != free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            free_.erase(it);
+        }
+    }
+}
+
+size_t Arena::largest_free() const {
+    size_t m = 0;
+    for (const auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+}
+
+int default_serving_depth(int64_t n, int precision) {
+    // binary32 leaves: one level per doubling above 2048; bf16 split leaves
+    // keep their error budget at one level at most
+    int d;
+    if (precision == STARK_FP32) d = n >= 8192 ? 2 : n >= 4096 ? 1 : 0;
+    else d = n >= 4096 ? 1 : 0;
+    return std::min(d, max_depth_for(n));
+}
+
+size_t request_footprint(const Plan& p, bool gen, bool own_c) {
+    const size_t nn = (size_t)p.n * (size_t)p.n * 4;
+    size_t b = (p.bytes + 255) / 256 * 256;
+    if (gen) b += 2 * ((nn + 255) / 256 * 256);
+    if (own_c) b += (nn + 255) / 256 * 256;
+    return b;
+}
+
+// ----------------------------------------------------------------------------
+// Engine
+// ----------------------------------------------------------------------------
+Engine::Engine(stark_ctx* ctx, size_t budget, int slots, hipError_t* err) : ctx_(ctx) {
+    *err = hipSetDevice(ctx->device);
+    if (*err == hipSuccess) *err = hipMalloc(&base_, budget);
+    if (*err == hipSuccess) *err = hipHostMalloc(reinterpret_cast<void**>(&host_sums_), sizeof(double) * slots);
+    if (*err != hipSuccess) return;
+    arena_.reset(budget);
+    slots_.resize(slots);
+    for (auto& s : slots_) {
+        if ((*err = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess) return;
+        if ((*err = hipEventCreate(&s.ev0)) != hipSuccess) return;
+        if ((*err = hipEventCreate(&s.ev1)) != hipSuccess) return;
+        if ((*err = hipMalloc(reinterpret_cast<void**>(&s.partials), 257 * sizeof(double))) != hipSuccess) return;
+    }
+    if (const char* f = std::getenv("STARK_FAULT_INJECT")) fault_tag_ = std::atoll(f);
+    thread_ = std::thread([this] { loop(); });
+}
+
+Engine::~Engine() {
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        stop_ = true;
+    }
+    cv_.notify_all();
+    if (thread_.joinable()) thread_.join();
+    (void)hipSetDevice(ctx_->device);
+    for (auto& s : slots_) {
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
+        if (s.ev0) (void)hipEventDestroy(s.ev0);
+        if (s.ev1) (void)hipEventDestroy(s.ev1);
+        if (s.partials) (void)hipFree(s.partials);
+    }
+    for (auto& kv : live_) delete kv.second;   // every request is in live_ until polled
+    if (base_) (void)hipFree(base_);
+    if (host_sums_) (void)hipHostFree(host_sums_);
+}
+
+stark_status Engine::submit(const stark_request& r, uint64_t* ticket) {
+    if (r.n <= 0 || planes_for((int)r.precision) < 0) {
+        set_error("bad request (n=%lld precision=%d)", (long long)r.n, (int)r.precision);
+        return STARK_EINVAL;
+    }
+    const bool gen = (r.A == nullptr);
+    if (gen != (r.B == nullptr)) { set_error("A and B must both be given or both be NULL"); return STARK_EINVAL; }
+    std::unique_ptr<Req> q(new Req());
+    q->r = r;
+    q->gen = gen;
+    q->own_c = (r.C == nullptr);
+    int depth = r.depth;
+    if (depth == STARK_DEPTH_AUTO) {
+        std::lock_guard<std::mutex> lk(ctx_->mu);
+        auto it = ctx_->tune.find({r.n, (int)r.precision});
+        depth = it != ctx_->tune.end() ? it->second.depth : default_serving_depth(r.n, (int)r.precision);
+    }
+    depth = std::min(std::max(depth, 0), max_depth_for(r.n));
+    const std::string why = make_plan(r.n, depth, (int)r.precision, q->plan);
+    if (!why.empty()) { set_error("%s", why.c_str()); return STARK_EINVAL; }
+    q->bytes = request_footprint(q->plan, q->gen, q->own_c);
+    if (q->bytes > arena_.size()) {
+        set_error("request needs %zu bytes, budget is %zu", q->bytes, arena_.size());
+        return STARK_ENOMEM;
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    if (arrivals_.size() + waiting_.size() >= kMaxQueue) { set_error("queue full"); return STARK_EBUSY; }
+    q->ticket = next_ticket_++;
+    q->t_submit = now_us();
+    *ticket = q->ticket;
+    live_[q->ticket] = q.get();
+    arrivals_.push_back(q.release());
+    cv_.notify_one();
+    return STARK_OK;
+}
+
+stark_status Engine::poll(uint64_t ticket, stark_result* out) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = live_.find(ticket);
+    if (it == live_.end()) { set_error("unknown ticket %llu", (unsigned long long)ticket); return STARK_ENOTFOUND; }
+    Req* q = it->second;
+    if (q->t_done == 0) return STARK_PENDING;
+    if (out) {
+        out->tag = q->r.tag;
+        out->depth = q->plan.depth;
+        out->status = q->status;
+        out->t_submit_us = q->t_submit;
+        out->t_admit_us = q->t_admit;
+        out->t_done_us = q->t_done;
+        out->gpu_ms = q->gpu_ms;
+        out->checksum = q->checksum;
+    }
+    const stark_status st = q->status;
+    live_.erase(it);
+    delete q;
+    return st;
+}
+
+stark_status Engine::stats(stark_stats_t* out) {
+    std::lock_guard<std::mutex> lk(mu_);
+    out->completed = completed_;
+    out->failed = failed_;
+    const double span_s = (last_done_ - first_admit_) * 1e-6;
+    out->throughput_tflops = (first_admit_ >= 0 && span_s > 0) ? flops_ / span_s * 1e-12 : 0.0;
+    std::vector<double> l = lat_ms_;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double q) {
+        if (l.empty()) return 0.0;
+        const size_t i = std::min(l.size() - 1, (size_t)std::ceil(q * l.size()) - (q * l.size() >= 1 ? 1 : 0));
+        return l[i];
+    };
+    out->p50_ms = pct(0.50);
+    out->p99_ms = pct(0.99);
+    out->max_inflight_bytes = (double)max_bytes_;
+    out->max_concurrent = max_inflight_;
+    return STARK_OK;
+}
+
+bool Engine::admit(Req* q, int si) {
+    size_t off;
+    if (!arena_.alloc(q->bytes, &off)) return false;
+    Slot& s = slots_[si];
+    q->off = off;
+    q->slot = si;
+    q->t_admit = now_us();
+    if (first_admit_ < 0) first_admit_ = q->t_admit;
+    s.busy = true;
+    s.req = q;
+    ++inflight_;
+    max_inflight_ = std::max(max_inflight_, inflight_);
+    max_bytes_ = std::max(max_bytes_, arena_.used());
+
+    const size_t nn = (size_t)q->r.n * (size_t)q->r.n * 4;
+    const size_t nn_al = (nn + 255) / 256 * 256;
+    char* base = static_cast<char*>(base_) + off;
+    char* ws = base;
+    char* cur = base + (q->plan.bytes + 255) / 256 * 256;
+    const float* A = q->r.A;
+    const float* B = q->r.B;
+    float* C = q->r.C;
+    if (q->gen) {
+        A = reinterpret_cast<float*>(cur); cur += nn_al;
+        B = reinterpret_cast<float*>(cur); cur += nn_al;
+    }
+    if (q->own_c) { C = reinterpret_cast<float*>(cur); cur += nn_al; }
+
+    hipError_t e = hipSuccess;
+    stark_status rc = STARK_OK;
+    if ((int64_t)q->r.tag == fault_tag_) {
+        rc = STARK_EDEVICE;   // injected failure: nothing is launched
+    } else {
+        e = hipEventRecord(s.ev0, s.stream);
+        if (e == hipSuccess && q->gen) e = launch_generate_normal(const_cast<float*>(A), q->r.n * q->r.n, 2 * q->r.seed, s.stream);
+        if (e == hipSuccess && q->gen) e = launch_generate_normal(const_cast<float*>(B), q->r.n * q->r.n, 2 * q->r.seed + 1, s.stream);
+        if (e == hipSuccess) rc = run_plan(ctx_, q->plan, make_desc(q->plan, A, B, C, ws), STARK_PHASE_ALL, s.stream);
+        if (e == hipSuccess && rc == STARK_OK && q->own_c) {
+            e = launch_sum_f64(C, q->r.n * q->r.n, s.partials, s.partials + 256, s.stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&host_sums_[si], s.partials + 256, sizeof(double), hipMemcpyDeviceToHost, s.stream);
+        }
+        if (e == hipSuccess && rc == STARK_OK) e = hipEventRecord(s.ev1, s.stream);
+    }
+    if (e != hipSuccess || rc != STARK_OK) {
+        q->status = rc != STARK_OK ? rc : STARK_EDEVICE;
+        // make sure nothing of this request is still running before its memory is reused
+        hipStreamSynchronize(s.stream);
+        (void)hipGetLastError();
+        q->t_done = now_us();
+        ++failed_;
+        arena_.free(q->off, q->bytes);
+        s.busy = false;
+        s.req = nullptr;
+        --inflight_;
+    }
+    return true;
+}
+
+void Engine::finish(int si) {
+    Slot& s = slots_[si];
+    Req* q = s.req;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, s.ev0, s.ev1);
+    q->gpu_ms = ms;
+    q->checksum = q->own_c ? host_sums_[si] : 0.0;
+    q->t_done = now_us();
+    q->status = STARK_OK;
+    ++completed_;
+    lat_ms_.push_back((q->t_done - q->t_submit) * 1e-3);
+    flops_ += 2.0 * (double)q->r.n * (double)q->r.n * (double)q->r.n;
+    last_done_ = q->t_done;
+    arena_.free(q->off, q->bytes);
+    s.busy = false;
+    s.req = nullptr;
+    --inflight_;
+}
+
+void Engine::loop() {
+    (void)hipSetDevice(ctx_->device);
+    std::unique_lock<std::mutex> lk(mu_);
+    while (true) {
+        while (!arrivals_.empty()) {
+            waiting_.push_back(arrivals_.front());
+            arrivals_.pop_front();
+        }
+        bool progress = false;
+        // completions
+        for (int si = 0; si < (int)slots_.size(); ++si) {
+            if (!slots_[si].busy) continue;
+            const hipError_t e = hipEventQuery(slots_[si].ev1);
+            if (e == hipSuccess) {
+                finish(si);
+                progress = true;
+            } else if (e != hipErrorNotReady) {
+                Req* q = slots_[si].req;
+                q->status = STARK_EDEVICE;
+                q->t_done = now_us();
+                ++failed_;
+                arena_.free(q->off, q->bytes);
+                slots_[si].busy = false;
+                slots_[si].req = nullptr;
+                --inflight_;
+                (void)hipGetLastError();
+                progress = true;
+            }
+        }
+        // admissions: FIFO with a bounded bypass of requests that do not fit
+        int bypass = 0;
+        for (auto it = waiting_.begin(); it != waiting_.end();) {
+            int free_slot = -1;
+            for (int si = 0; si < (int)slots_.size(); ++si)
+                if (!slots_[si].busy) { free_slot = si; break; }
+            if (free_slot < 0) break;
+            if (admit(*it, free_slot)) {
+                it = waiting_.erase(it);
+                progress = true;
+            } else {
+                if (++bypass > kMaxBypass) break;
+                ++it;
+            }
+        }
+        if (stop_ && waiting_.empty() && inflight_ == 0) break;
+        if (!progress) {
+            if (inflight_ > 0) {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            } else {
+                cv_.wait_for(lk, std::chrono::milliseconds(5));
+            }
+        }
+    }
+}
+
+static stark_status ensure_engine(stark_ctx* ctx) {
+    if (ctx->engine) return STARK_OK;
+    hipError_t err = hipSuccess;
+    std::unique_ptr<Engine> e(new Engine(ctx, ctx->hbm_budget, ctx->max_slots, &err));
+    if (err != hipSuccess) {
+        set_error("serving engine start failed: %s", hipGetErrorString(err));
+        return STARK_EDEVICE;
+    }
+    ctx->engine = std::move(e);
+    return STARK_OK;
+}
+
+}  // namespace stk
+
+using namespace stk;
+
+extern "C" {
+
+stark_status stark_submit(stark_ctx* ctx, const stark_request* r, uint64_t* ticket) {
+    if (!ctx || !r || !ticket) { set_error("NULL argument"); return STARK_EINVAL; }
+    static std::mutex start_mu;
+    {
+        std::lock_guard<std::mutex> lk(start_mu);
+        const stark_status rc = ensure_engine(ctx);
+        if (rc != STARK_OK) return rc;
+    }
+    return ctx->engine->submit(*r, ticket);
+}
+
+stark_status stark_poll(stark_ctx* ctx, uint64_t ticket, stark_result* out) {
+    if (!ctx) { set_error("ctx is NULL"); return STARK_EINVAL; }
+    if (!ctx->engine) { set_error("unknown ticket %llu", (unsigned long long)ticket); return STARK_ENOTFOUND; }
+    return ctx->engine->poll(ticket, out);
+}
+
+stark_status stark_stats(stark_ctx* ctx, stark_stats_t* out) {
+    if (!ctx || !out) { set_error("NULL argument"); return STARK_EINVAL; }
+    std::memset(out, 0, sizeof *out);
+    if (!ctx->engine) return STARK_OK;
+    return ctx->engine->stats(out);
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Autotuner for the recursion depth (the paper's block-size choice: wall clock
+// against partition size is U-shaped, with an optimum per matrix size,
+// Section V-C).  For a new (n, precision) it runs every usable depth on the
+// caller's operands, times three runs after a warm-up with HIP events, and
+// measures each result's error with Freivalds' check in binary64 on the GPU:
+// e = ||C x - A (B x)|| / ||A (B x)|| for a Gaussian x, whose square has the
+// squared relative Frobenius error as its expectation.  The fastest depth
+// whose error is within the tolerance (default 1e-5, STARK_TUNE_TOL) wins;
+// if none is, the most accurate.  Results persist in a small text file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <random>
+#include <vector>
+
+#include "ctx.hpp"
+#include "launch.hpp"
+
+namespace stk {
+
+static void tuner_save(stark_ctx* ctx) {
+    if (ctx->tune_path.empty()) return;
+    FILE* f = std::fopen(ctx->tune_path.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "# n precision depth ms freivalds_error\n");
+    for (const auto& kv : ctx->tune)
+        std::fprintf(f, "%lld %d %d %.6f %.6e\n", (long long)kv.first.first, kv.first.second, kv.second.depth,
+                     kv.second.ms, kv.second.err);
+    std::fclose(f);
+}
+
+void tuner_load(stark_ctx* ctx) {
+    if (ctx->tune_path.empty()) return;
+    FILE* f = std::fopen(ctx->tune_path.c_str(), "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        long long n;
+        int prec, depth;
+        double ms, err;
+        if (std::sscanf(line, "%lld %d %d %lf %lf", &n, &prec, &depth, &ms, &err) == 5 && n > 0 && depth >= 0 &&
+            depth <= max_depth_for(n))
+            ctx->tune[{(int64_t)n, prec}] = TuneEntry{depth, ms, err};
+    }
+    std::fclose(f);
+}
+
+stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int precision,
+                        int dmin, int dmax, double tol, hipStream_t st, std::vector<TuneEntry>& results,
+                        int* depth) {
+    const int maxd = std::min(dmax, max_depth_for(n));
+    if (tol <= 0) tol = ctx->tune_tol;
+    // Gaussian probe (fixed seed) and A (B x), binary64.
+    std::vector<double> hx(n);
+    std::mt19937_64 gen(0x5eed5eedULL);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (auto& v : hx) v = nd(gen);
+    double *dx = nullptr, *dbx = nullptr, *dabx = nullptr, *dcx = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    stark_status rc = STARK_OK;
+    std::vector<double> habx(n), hcx(n);
+    results.clear();
+    auto fail = [&](const char* what, hipError_t e) {
+        set_error("autotuner: %s: %s", what, hipGetErrorString(e));
+        rc = STARK_EDEVICE;
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&dx, n * 8)) != hipSuccess || (e = hipMalloc(&dbx, n * 8)) != hipSuccess ||
+        (e = hipMalloc(&dabx, n * 8)) != hipSuccess || (e = hipMalloc(&dcx, n * 8)) != hipSuccess ||
+        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        fail("allocation", e);
+    }
+    if (rc == STARK_OK) {
+        if ((e = hipMemcpyAsync(dx, hx.data(), n * 8, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = launch_matvec_f64(B, dx, dbx, n, st)) != hipSuccess ||
+            (e = launch_matvec_f64(A, dbx, dabx, n, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(habx.data(), dabx, n * 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            fail("reference product", e);
+    }
+    double nref = 0.0;
+    for (double v : habx) nref += v * v;
+    nref = std::sqrt(nref);
+    for (int d = std::max(dmin, 0); d <= maxd && rc == STARK_OK; ++d) {
+        Plan p;
+        if (!make_plan(n, d, precision, p).empty()) continue;
+        if (ensure_workspace(ctx, p.bytes) != STARK_OK) break;   // deeper plans only grow
+        const ProbDesc desc = make_desc(p, A, B, C, ctx->ws);
+        if ((rc = run_plan(ctx, p, desc, STARK_PHASE_ALL, st)) != STARK_OK) break;
+        std::vector<float> times;
+        for (int r = 0; r < 3 && rc == STARK_OK; ++r) {
+            float ms = 0.f;
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) { fail("event", e); break; }
+            if ((rc = run_plan(ctx, p, desc, STARK_PHASE_ALL, st)) != STARK_OK) break;
+            if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+                fail("timing", e);
+                break;
+            }
+            times.push_back(ms);
+        }
+        if (rc != STARK_OK) break;
+        if ((e = launch_matvec_f64(C, dx, dcx, n, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(hcx.data(), dcx, n * 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess) {
+            fail("error check", e);
+            break;
+        }
+        double num = 0.0;
+        for (int64_t i = 0; i < n; ++i) num += (hcx[i] - habx[i]) * (hcx[i] - habx[i]);
+        std::sort(times.begin(), times.end());
+        results.push_back(TuneEntry{d, times[times.size() / 2], nref > 0 ? std::sqrt(num) / nref : 0.0});
+    }
+    if (dx) (void)hipFree(dx);
+    if (dbx) (void)hipFree(dbx);
+    if (dabx) (void)hipFree(dabx);
+    if (dcx) (void)hipFree(dcx);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != STARK_OK) return rc;
+    if (results.empty()) {
+        set_error("autotuner: no usable depth for n=%lld", (long long)n);
+        return STARK_EINVAL;
+    }
+    const TuneEntry* best = nullptr;
+    for (const auto& r : results)
+        if (r.err <= tol && (!best || r.ms < best->ms)) best = &r;
+    if (!best)
+        for (const auto& r : results)
+            if (!best || r.err < best->err) best = &r;
+    ctx->tune[{n, precision}] = *best;
+    tuner_save(ctx);
+    *depth = best->depth;
+    return STARK_OK;
+}
+
+stark_status tuned_depth(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int precision,
+                         hipStream_t st, int* depth) {
+    auto it = ctx->tune.find({n, precision});
+    if (it != ctx->tune.end()) {
+        *depth = it->second.depth;
+        return STARK_OK;
+    }
+    std::vector<TuneEntry> results;
+    return tune_range(ctx, A, B, C, n, precision, 0, 5, 0.0, st, results, depth);
+}
+
+}  // namespace stk

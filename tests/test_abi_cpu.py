@@ -1,0 +1,132 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol the header
+declares, and its pure host functions (planner, argument checks) behave."""
+import ctypes
+import subprocess
+
+import pytest
+
+from paper_1811_07325_amd import build as _build  # noqa: F401  (import check)
+
+
+@pytest.fixture(scope="module")
+def S():
+    import os
+    from paper_1811_07325_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_1811_07325_amd import stark
+    return stark
+
+
+def test_exports_every_header_symbol(S):
+    declared = S.header_symbols()
+    assert len(declared) >= 16
+    out = subprocess.run(["nm", "-D", "--defined-only", S.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = {l.split()[-1] for l in out.stdout.splitlines() if " T " in l}
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(S.LIB_PATH)
+    for s in declared:
+        assert getattr(lib, s) is not None
+
+
+def test_max_depth(S):
+    assert S.stark_max_depth(512) == 3
+    assert S.stark_max_depth(16384) == 7
+    assert S.stark_max_depth(384) == 1
+    assert S.stark_max_depth(1000) == 4
+    assert S.stark_max_depth(64) == 0
+    assert S.stark_max_depth(0) == 0
+
+
+def _regions(d, depth):
+    regs = []
+    for l in range(depth):
+        if d.div_a[l] >= 0:
+            regs.append(("div_a%d" % l, d.div_a[l]))
+            regs.append(("div_b%d" % l, d.div_b[l]))
+    for name in ("leaf_a", "leaf_b", "leaf_m", "pad_a", "pad_b"):
+        if getattr(d, name) >= 0:
+            regs.append((name, getattr(d, name)))
+    return sorted(regs, key=lambda r: r[1])
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("n,depth", [(512, 2), (4096, 3), (1000, 2), (384, 1), (16384, 4), (65, 0), (3000, 3)])
+def test_plan_layout(S, n, depth, prec):
+    d = S.stark_plan_info(n, depth, prec)
+    np_ = d.n_pad
+    assert np_ >= n and np_ % (64 << depth) == 0 and d.leaf == np_ >> depth
+    planes = {0: 0, 1: 2, 2: 3}[prec]
+    assert d.planes == planes
+    L, h = d.leaf, None
+    # sizes of every region, from the layout rules
+    size = {}
+    fp32_levels = depth if planes == 0 else max(depth - 1, 0)
+    for l in range(depth):
+        if l < fp32_levels:
+            h = (np_ >> l) // 2
+            slots = 7 if (l == 0 and np_ != n) else 5
+            assert d.div_slots[l] == slots
+            size["div_a%d" % l] = size["div_b%d" % l] = slots * 7 ** l * h * h * 4
+        else:
+            assert d.div_a[l] == -1
+    if planes:
+        nodes_out = 7 ** depth
+        size["leaf_a"] = size["leaf_b"] = nodes_out * planes * L * L * 2
+    if depth > 0:
+        size["leaf_m"] = 7 ** depth * L * L * 4
+    else:
+        assert d.leaf_m == -1
+    if d.pad_a >= 0:
+        assert depth == 0 and planes == 0 and np_ != n
+        size["pad_a"] = size["pad_b"] = np_ * np_ * 4
+    regs = _regions(d, depth)
+    assert {r[0] for r in regs} == set(size)
+    # live regions are disjoint and inside the workspace
+    for (a, oa), (b, ob) in zip(regs, regs[1:]):
+        assert oa + size[a] <= ob, (a, b)
+    last = regs[-1] if regs else None
+    if last:
+        assert last[1] + size[last[0]] <= d.bytes
+    # combine outputs: disjoint from each other and from the leaf products
+    comb = [(l, d.comb[l]) for l in range(1, depth)]
+    ends = []
+    for l, off in comb:
+        m = np_ >> l
+        ends.append((off, off + 7 ** l * m * m * 4))
+    ends.sort()
+    for (a0, a1), (b0, b1) in zip(ends, ends[1:]):
+        assert a1 <= b0
+    for a0, a1 in ends:
+        assert a1 <= d.leaf_m
+
+
+def test_workspace_formula_fp32(S):
+    """Unpadded binary32: 2.5 S_k N + (7/4)^k N floats (S_k = sum_{l<k} (7/4)^l)."""
+    for n, k in [(4096, 3), (16384, 2), (8192, 4)]:
+        N = n * n
+        Sk = sum((7 / 4) ** l for l in range(k))
+        expect = (2.5 * Sk + (7 / 4) ** k) * N * 4
+        got = S.stark_workspace_size(n, k, 0)
+        assert abs(got - expect) <= 256 * (4 * k + 2)
+
+
+def test_invalid_arguments_are_rejected(S):
+    with pytest.raises(S.StarkError) as e:
+        S.stark_workspace_size(0, 0, 0)
+    assert e.value.status == S.STARK_EINVAL
+    with pytest.raises(S.StarkError):
+        S.stark_workspace_size(512, 9, 0)
+    with pytest.raises(S.StarkError):
+        S.stark_workspace_size(512, 1, 7)
+    assert "precision" in S.stark_last_error()
+
+
+def test_create_without_gpu_reports_device_error(S):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(S.StarkError) as e:
+        S.stark_create(0)
+    assert e.value.status == S.STARK_EDEVICE

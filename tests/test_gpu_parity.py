@@ -1,0 +1,299 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+* integer inputs (uniform in [-8, 8]): every result is an exact integer below
+  2^24, so every precision must match brute force bit for bit;
+* per-phase checks: the divide, split and combine kernels against the
+  oracle's binary32 step routines, bit for bit;
+* float inputs: against the oracle's arithmetic model of the same depth and
+  leaf precision (binary32 divide/combine, exact leaf sums); the only
+  difference left is the binary32 accumulation order inside the leaf GEMM;
+* full-size configurations on sampled rows and Freivalds' check.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1811_07325_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2}
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1811_07325_amd import stark
+    return stark
+
+
+WS_BYTES = 512 << 20
+
+
+@pytest.fixture(scope="module")
+def ws():
+    # torch-allocated workspace lent to the context, so tests can read it
+    return torch.empty(WS_BYTES, dtype=torch.uint8, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def ctx(S, ws):
+    c = S.stark_create(0, ws, WS_BYTES)
+    yield c
+    S.stark_destroy(c)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def run(S, ctx, A, B, depth, prec, C=None):
+    n = A.shape[0]
+    dA, dB = dev(A), dev(B)
+    dC = torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda") if C is None else C
+    S.stark_gemm(ctx, dA, dB, dC, n, depth, PREC[prec], None)
+    torch.cuda.synchronize()
+    return dC.cpu().numpy()
+
+
+def rel_f(C, ref):
+    return oracle.rel_frobenius(C, ref)
+
+
+# ---------------------------------------------------------------------------
+# Bit-exact integer products (all precisions, padded and ragged sizes).
+# ---------------------------------------------------------------------------
+INT_CASES = [(512, 2, "fp32"), (512, 2, "bf16x3"), (512, 2, "bf16x6"),
+             (512, 0, "fp32"), (512, 1, "fp32"), (512, 3, "fp32"), (512, 0, "bf16x3"), (512, 3, "bf16x3"),
+             (1000, 2, "fp32"), (1000, 2, "bf16x3"), (300, 1, "fp32"), (300, 1, "bf16x3"),
+             (65, 0, "fp32"), (65, 0, "bf16x3"), (200, 2, "fp32"), (200, 2, "bf16x6"), (384, 1, "bf16x3"),
+             (129, 1, "fp32")]
+
+
+@pytest.mark.parametrize("n,depth,prec", INT_CASES)
+def test_integer_inputs_bit_exact(S, ctx, n, depth, prec):
+    print(f"case n={n} depth={depth} prec={prec}", flush=True)
+    A = inputs.integers(n, 0)
+    B = inputs.integers(n, 1)
+    exact = A.astype(np.int64) @ B.astype(np.int64)
+    C = run(S, ctx, A, B, depth, prec)
+    assert np.all(np.isfinite(C))
+    assert np.array_equal(C.astype(np.int64), exact)
+    assert np.array_equal(C, exact.astype(np.float32))
+
+
+# ---------------------------------------------------------------------------
+# Floating-point inputs against the arithmetic model of the same method.
+# ---------------------------------------------------------------------------
+FLOAT_CASES = [(512, 2, "fp32"), (512, 2, "bf16x3"), (512, 2, "bf16x6"), (256, 1, "fp32"),
+               (384, 1, "bf16x3"), (1000, 2, "fp32"), (1000, 2, "bf16x3"), (512, 0, "fp32"),
+               (512, 0, "bf16x3"), (512, 3, "bf16x6")]
+
+
+@pytest.mark.parametrize("n,depth,prec", FLOAT_CASES)
+def test_float_inputs_match_model(S, ctx, n, depth, prec):
+    print(f"case n={n} depth={depth} prec={prec}", flush=True)
+    A = inputs.uniform(n, 0)
+    B = inputs.uniform(n, 1)
+    C = run(S, ctx, A, B, depth, prec)
+    model = oracle.strassen_model_f32(A, B, depth, prec)
+    exact = oracle.gemm_f64(A, B)
+    e_gpu, e_model = rel_f(C, exact), rel_f(model, exact)
+    d = rel_f(C, model)
+    print(f"  rel_frob gpu={e_gpu:.3e} model={e_model:.3e} gpu-vs-model={d:.3e}", flush=True)
+    # binary32 accumulation over a leaf of edge L: a few units of 2^-24 sqrt(L)
+    L = oracle.padded_size(n, depth, 64) >> depth
+    assert d <= 4 * 2.0 ** -24 * np.sqrt(L) * 2 ** depth
+    assert e_gpu <= 1.5 * e_model + 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Per-phase kernels, bit for bit.
+# ---------------------------------------------------------------------------
+def ws_view(ws, offset, count, dtype):
+    itemsize = np.dtype(dtype).itemsize
+    assert 0 <= offset and offset + count * itemsize <= ws.numel()
+    return ws[offset:offset + count * itemsize].cpu().numpy().view(dtype)
+
+
+@pytest.mark.parametrize("n", [256, 250])
+def test_divide_levels_bit_exact(S, ctx, ws, n):
+    depth = 2
+    A = inputs.uniform(n, 3)
+    B = inputs.uniform(n, 4)
+    dA, dB = dev(A), dev(B)
+    dC = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, 0, S.STARK_PHASE_DIVIDE, None)
+    torch.cuda.synchronize()
+    d = S.stark_plan_info(n, depth, 0)
+    np_ = d.n_pad
+    Ap = np.zeros((np_, np_), np.float32); Ap[:n, :n] = A
+    Bp = np.zeros((np_, np_), np.float32); Bp[:n, :n] = B
+    sA5, sB5 = [0, 1, 4, 5, 6], [0, 2, 3, 5, 6]
+    # level 0
+    S0, T0 = oracle.divide_f32(Ap, Bp)
+    h0 = np_ // 2
+    slots0 = d.div_slots[0]
+    ga = ws_view(ws, d.div_a[0], slots0 * h0 * h0, np.float32).reshape(slots0, h0, h0)
+    gb = ws_view(ws, d.div_b[0], slots0 * h0 * h0, np.float32).reshape(slots0, h0, h0)
+    ia, ib = (list(range(7)), list(range(7))) if slots0 == 7 else (sA5, sB5)
+    assert np.array_equal(ga, S0[ia]) and np.array_equal(gb, T0[ib])
+    # level 1: node c has operands (S0[c], T0[c])
+    h1 = h0 // 2
+    ga1 = ws_view(ws, d.div_a[1], 7 * 5 * h1 * h1, np.float32).reshape(7, 5, h1, h1)
+    gb1 = ws_view(ws, d.div_b[1], 7 * 5 * h1 * h1, np.float32).reshape(7, 5, h1, h1)
+    for c in range(7):
+        S1, T1 = oracle.divide_f32(S0[c], T0[c])
+        assert np.array_equal(ga1[c], S1[sA5]), c
+        assert np.array_equal(gb1[c], T1[sB5]), c
+
+
+@pytest.mark.parametrize("prec,depth,n", [("bf16x3", 1, 256), ("bf16x6", 2, 256), ("bf16x3", 0, 128),
+                                          ("bf16x3", 1, 200)])
+def test_split_leaf_operands_bit_exact(S, ctx, ws, prec, depth, n):
+    P = {"bf16x3": 2, "bf16x6": 3}[prec]
+    A = inputs.normal(n, 5)
+    B = inputs.normal(n, 6)
+    dA, dB = dev(A), dev(B)
+    dC = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, PREC[prec], S.STARK_PHASE_DIVIDE, None)
+    torch.cuda.synchronize()
+    d = S.stark_plan_info(n, depth, PREC[prec])
+    np_, L = d.n_pad, d.leaf
+    Ap = np.zeros((np_, np_), np.float32); Ap[:n, :n] = A
+    Bp = np.zeros((np_, np_), np.float32); Bp[:n, :n] = B
+    # leaf operands by the oracle's divide, in leaf order (base-7 digits)
+    Xs, Ys = [Ap], [Bp]
+    for _ in range(depth):
+        nx, ny = [], []
+        for X, Y in zip(Xs, Ys):
+            Sx, Ty = oracle.divide_f32(X, Y)
+            nx.extend(Sx)
+            ny.extend(Ty)
+        Xs, Ys = nx, ny
+    nleaf = 7 ** depth
+    ga = ws_view(ws, d.leaf_a, nleaf * P * L * L, np.uint16).reshape(nleaf, P, L, L)
+    gb = ws_view(ws, d.leaf_b, nleaf * P * L * L, np.uint16).reshape(nleaf, P, L, L)
+    for i in range(nleaf):
+        assert np.array_equal(ga[i], oracle.split_bf16(Xs[i], P)), i
+        # B side is stored transposed: plane[j][k] = split(T)[k][j]
+        assert np.array_equal(gb[i], oracle.split_bf16(Ys[i], P).transpose(0, 2, 1)), i
+
+
+def test_combine_levels_bit_exact(S, ctx, ws):
+    n, depth = 256, 2
+    A = inputs.uniform(n, 7)
+    B = inputs.uniform(n, 8)
+    dA, dB = dev(A), dev(B)
+    dC = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, 0, S.STARK_PHASE_ALL, None)
+    torch.cuda.synchronize()
+    d = S.stark_plan_info(n, depth, 0)
+    L = d.leaf
+    M = ws_view(ws, d.leaf_m, 49 * L * L, np.float32).reshape(49, L, L)
+    m1 = 2 * L
+    C1 = ws_view(ws, d.comb[1], 7 * m1 * m1, np.float32).reshape(7, m1, m1)
+    for node in range(7):
+        assert np.array_equal(C1[node], oracle.combine_f32(M[7 * node:7 * node + 7])), node
+    assert np.array_equal(dC.cpu().numpy(), oracle.combine_f32(C1))
+
+
+def test_leaf_products_close_to_exact(S, ctx, ws):
+    """Each leaf product (FP32 path) against the FP64 product of its operands."""
+    n, depth = 256, 1
+    A = inputs.uniform(n, 9)
+    B = inputs.uniform(n, 10)
+    dA, dB = dev(A), dev(B)
+    dC = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, 0, S.STARK_PHASE_DIVIDE | S.STARK_PHASE_LEAF, None)
+    torch.cuda.synchronize()
+    d = S.stark_plan_info(n, depth, 0)
+    L = d.leaf
+    M = ws_view(ws, d.leaf_m, 7 * L * L, np.float32).reshape(7, L, L)
+    Sx, Ty = oracle.divide_f32(A, B)
+    for i in range(7):
+        ref = oracle.gemm_f64(Sx[i], Ty[i])
+        assert rel_f(M[i], ref) < 4 * 2.0 ** -24 * np.sqrt(L)
+
+
+# ---------------------------------------------------------------------------
+# Graph replay, generator, measurement helpers.
+# ---------------------------------------------------------------------------
+def test_graph_replays_are_identical(S, ctx):
+    n = 512
+    A = inputs.uniform(n, 11)
+    B = inputs.uniform(n, 12)
+    dA, dB = dev(A), dev(B)
+    s = torch.cuda.Stream()
+    outs = []
+    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    for i in range(5):   # eager, capture, replays
+        C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        S.stark_gemm(ctx, dA, dB, C, n, 2, 0, s)
+        s.synchronize()
+        outs.append(C.cpu().numpy().copy())
+        # unrelated eager work between replays
+        _ = (dA * 2.0).sum().item()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert np.array_equal(outs[0], run(S, ctx, A, B, 2, "fp32"))
+
+
+def test_generator_matches_host_twin(S):
+    n = 300
+    X = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    S.stark_generate_normal(X, n, 12345, None)
+    torch.cuda.synchronize()
+    assert np.array_equal(X.cpu().numpy(), inputs.philox_normal(n, 12345))
+
+
+def test_matvec_and_row_errors(S):
+    n = 333
+    M = inputs.normal(n, 1)
+    x = inputs.gaussian_vector(n, 2)
+    dM = dev(M)
+    dx = torch.from_numpy(x).cuda()
+    dy = torch.empty(n, dtype=torch.float64, device="cuda")
+    S.stark_matvec_f64(dM, dx, dy, n, None)
+    rows = inputs.sample_rows(n, 17, 3)
+    ref = M.astype(np.float64)[rows] + 1e-3
+    out = torch.empty(3, dtype=torch.float64, device="cuda")
+    S.stark_row_errors(dM, n, torch.from_numpy(rows).cuda(), rows.size, torch.from_numpy(ref).cuda(), out, None)
+    torch.cuda.synchronize()
+    assert np.allclose(dy.cpu().numpy(), oracle.gemv_f64(M, x), rtol=1e-12, atol=1e-12)
+    o = out.cpu().numpy()
+    dref = M.astype(np.float64)[rows] - ref
+    assert np.isclose(o[0], np.max(np.abs(dref)), rtol=1e-12)
+    assert np.isclose(o[1], np.sum(dref ** 2), rtol=1e-10)
+    assert np.isclose(o[2], np.sum(ref ** 2), rtol=1e-10)
+
+
+def test_argument_errors(S, ctx):
+    n = 128
+    A = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    B = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    with pytest.raises(S.StarkError) as e:
+        S.stark_gemm(ctx, A, B, A, n, 0, 0, None)      # C overlaps A
+    assert e.value.status == S.STARK_EINVAL
+    with pytest.raises(S.StarkError):
+        S.stark_gemm(ctx, A, B, None, n, 0, 0, None)
+    with pytest.raises(S.StarkError):
+        S.stark_gemm(ctx, A, B, torch.empty_like(A), n, 5, 0, None)   # depth too deep
+    with pytest.raises(S.StarkError) as e:
+        S.stark_gemm(ctx, A, B, torch.empty_like(A), n, 0, 9, None)
+    assert e.value.status == S.STARK_EUNSUPPORTED
+
+
+def test_caller_workspace_too_small(S):
+    n = 256
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    c = S.stark_create(0, ws, ws.numel())
+    try:
+        A = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+        with pytest.raises(S.StarkError) as e:
+            S.stark_gemm(c, A, A, torch.empty_like(A), n, 1, 0, None)
+        assert e.value.status == S.STARK_ENOMEM
+    finally:
+        S.stark_destroy(c)

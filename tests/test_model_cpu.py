@@ -1,0 +1,71 @@
+"""Pins for the oracle's arithmetic model of the GPU path (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1811_07325_amd import inputs
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("n,depth", [(16, 0), (16, 2), (13, 1), (40, 3)])
+def test_model_exact_on_small_integers(mode, n, depth):
+    A = inputs.integers(n, 1)
+    B = inputs.integers(n, 2)
+    C = oracle.strassen_model_f32(A, B, depth, mode)
+    assert np.array_equal(C.astype(np.int64), A.astype(np.int64) @ B.astype(np.int64))
+
+
+def test_model_fp32_depth0_is_rounded_classical():
+    A = inputs.uniform(48, 3)
+    B = inputs.uniform(48, 4)
+    C = oracle.strassen_model_f32(A, B, 0, "fp32")
+    assert np.array_equal(C, oracle.gemm_f64(A, B).astype(np.float32))
+
+
+def test_model_bf16x3_depth0_matches_library_split():
+    torch = pytest.importorskip("torch")
+    A = inputs.normal(64, 5)
+    B = inputs.normal(64, 6)
+
+    def planes(x):
+        hi = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+        lo = torch.from_numpy(x - hi).to(torch.bfloat16).to(torch.float32).numpy()
+        return hi.astype(np.float64), lo.astype(np.float64)
+
+    ah, al = planes(A)
+    bh, bl = planes(B)
+    ref = (ah @ bh + ah @ bl + al @ bh).astype(np.float32)
+    C = oracle.strassen_model_f32(A, B, 0, "bf16x3")
+    assert np.max(np.abs(C - ref) / (np.abs(ref) + 1e-30)) <= 2.0 ** -22
+
+
+def test_model_split_error_sizes():
+    """bf16x6 keeps binary32 accuracy; bf16x3 loses about 8 bits (2^-17 per operand)."""
+    A = inputs.normal(64, 7)
+    B = inputs.normal(64, 8)
+    exact = oracle.gemm_f64(A, B)
+    e32 = oracle.rel_frobenius(oracle.strassen_model_f32(A, B, 0, "fp32"), exact)
+    e6 = oracle.rel_frobenius(oracle.strassen_model_f32(A, B, 0, "bf16x6"), exact)
+    e3 = oracle.rel_frobenius(oracle.strassen_model_f32(A, B, 0, "bf16x3"), exact)
+    assert e32 < 1e-7 and e6 < 1e-7
+    assert 5e-7 < e3 < 2e-5
+
+
+def test_philox_known_answers():
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    with open(path) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for r in rows:
+        v = [np.uint64(int(x, 16)) for x in r]
+        out = inputs.philox4x32_10(*v[:6])
+        assert [int(x) for x in out] == [int(x) for x in v[6:]]
+
+
+def test_philox_normal_moments():
+    x = inputs.philox_normal(512, 11).astype(np.float64)
+    assert abs(x.mean()) < 0.01 and abs(x.var() - 1.0) < 0.01
+    assert np.all(np.abs(x) <= 6.0)
+    # exactly reproducible: value * 2^24 is an integer
+    assert np.array_equal(x * 2.0 ** 24, np.round(x * 2.0 ** 24))
