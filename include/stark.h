@@ -216,6 +216,7 @@ typedef struct {
     int64_t comb[STARK_MAX_DEPTH]; /* byte offset of level-l combine output (l>=1) */
     int64_t pad_a, pad_b;     /* byte offsets of padded copies (depth-0 FP32 only) */
     size_t bytes;             /* total workspace                                   */
+    int gemm_tile;            /* leaf GEMM tile class (64, 128 or 256)             */
 } stark_plan_desc;
 
 stark_status stark_plan_info(int64_t n, int depth, stark_precision p, stark_plan_desc* out);

@@ -133,10 +133,10 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
         for (int l = 0; l < max_fp32; ++l)
             add_launch(kDivide, l, 0, [&](int i) { return plans[i].fp32_levels > l ? blocks_divide(descs[i], l) : 0; });
         if (e.planes > 0) add_launch(kSplit, 0, 0, [&](int i) { return blocks_split(descs[i]); });
-        for (int tile : {128, 64})
+        for (int tile : {256, 128, 64})
             add_launch(kGemm, 0, tile, [&](int i) {
                 const Plan& p = plans[i];
-                return p.tile == tile ? pow7(p.depth) * (p.leaf / tile) * (p.leaf / tile) : (int64_t)0;
+                return p.tile == tile ? pow7(p.depth) * gemm_tiles_per_leaf(p.planes, tile, p.leaf) : (int64_t)0;
             });
         for (int l = max_depth - 1; l >= 0; --l)
             add_launch(kCombine, l, 0, [&](int i) { return plans[i].depth > l ? blocks_combine(descs[i], l) : 0; });

@@ -318,6 +318,137 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t tot
 }
 
 // ---------------------------------------------------------------------------
+// bf16-split leaf GEMM for large leaves: block tile BM x BN = 256 x 256
+// (P = 2) or 256 x 128 (P = 3), 8 waves, K steps of 32.  Operand tiles go
+// from global memory straight into LDS (global_load_lds_dwordx4: each lane
+// deposits 16 bytes at LDS base + 16 * lane), two stages deep: the loads of
+// step k+1 are in flight while step k runs on the matrix cores, and no
+// register staging is needed.  The LDS image of a stage is [plane][row][4
+// chunks of 8 bf16], A rows first, then B rows; the chunk index is XOR-ed
+// with (row >> 2) & 3 so that the 16 lanes of an MFMA operand read (16 rows,
+// one chunk) hit 16 different bank groups.  The global address each lane
+// loads is permuted so that its 16 bytes land in that swizzled position.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int P> struct BigTile;
+template <> struct BigTile<2> { static constexpr int BM = 256, BN = 256, WAVES_M = 2, WAVES_N = 4; };
+template <> struct BigTile<3> { static constexpr int BM = 256, BN = 128, WAVES_M = 4, WAVES_N = 2; };
+
+__device__ __forceinline__ int swz4(int row) { return (row >> 2) & 3; }
+
+template <class Src, int P>
+__global__ __launch_bounds__(512) void k_gemm_bf16_big(Src src, int64_t total_tiles) {
+    constexpr int BM = BigTile<P>::BM, BN = BigTile<P>::BN;
+    constexpr int WAVES_M = BigTile<P>::WAVES_M, WAVES_N = BigTile<P>::WAVES_N;
+    constexpr int BK = 32, KC = BK / 8;                 // 16-byte chunks per row and plane
+    constexpr int ROWS = BM + BN;                       // LDS rows per plane (A rows, then B rows)
+    constexpr int UNITS = P * ROWS * KC;                // 16-byte units per stage
+    static_assert(BM % 128 == 0 && BN % 128 == 0, "8 waves x 16 rows per direct load");
+    constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N, TM = WM / 16, TN = WN / 16;
+    __shared__ __attribute__((aligned(16))) uint4 lds[2][UNITS];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w / WAVES_N, wn = w % WAVES_N;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t G = gridDim.x;
+    const int64_t slot = xcd_slot(blockIdx.x, G);
+
+    for (int64_t t = slot; t < total_tiles; t += G) {
+        int64_t local;
+        const ProbDesc& d = src.get(src.locate(t, local));
+        const int64_t L = d.leaf, LL = L * L;
+        const int64_t tm_cnt = L / BM, tn_cnt = L / BN, tpl = tm_cnt * tn_cnt;
+        const int64_t leaf = local / tpl;
+        int64_t tm, tn;
+        tile_coords(local - leaf * tpl, tm_cnt, tn_cnt, tm, tn);
+        const uint16_t* Ah = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_a + leaf * P * LL;
+        const uint16_t* Bh = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_b + leaf * P * LL;
+        float* Cp;
+        int64_t ldc;
+        if (d.depth == 0) { Cp = d.C; ldc = d.n; }
+        else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
+        const bool crop = d.depth == 0 && d.bounded0;
+        const int64_t m0 = tm * BM, n0 = tn * BN;
+
+        // One direct load of a wave fills 64 consecutive LDS units = 16 rows x
+        // 4 chunks of one plane and side.  Group g of a side (rows 16g..16g+15)
+        // of plane p is loaded by wave g % 8.  Lane l covers row 16g + l/4,
+        // chunk (l & 3) ^ swz4(row) = (l & 3) ^ ((l >> 4) & 3).
+        const int kc = (lane & 3) ^ ((lane >> 4) & 3);
+        const uint16_t* a_src = Ah + (m0 + (lane >> 2)) * L + 8 * kc;
+        const uint16_t* b_src = Bh + (n0 + (lane >> 2)) * L + 8 * kc;
+        auto issue = [&](int stage, int64_t k0) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int r = 0; r < BM / 128; ++r) {
+                    const int g = w + 8 * r;
+                    __builtin_amdgcn_global_load_lds(a_src + p * LL + (int64_t)(16 * g) * L + k0,
+                                                     (lds_void_t*)&lds[stage][(p * ROWS + 16 * g) * KC], 16, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < BN / 128; ++r) {
+                    const int g = w + 8 * r;
+                    __builtin_amdgcn_global_load_lds(b_src + p * LL + (int64_t)(16 * g) * L + k0,
+                                                     (lds_void_t*)&lds[stage][(p * ROWS + BM + 16 * g) * KC], 16, 0,
+                                                     0);
+                }
+            }
+        };
+
+        f32x4 acc[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        const int64_t KT = L / BK;
+        issue(0, 0);
+        for (int64_t kt = 0; kt < KT; ++kt) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();     // stage kt landed everywhere; stage kt+1's old reads are done
+            if (kt + 1 < KT) issue((int)((kt + 1) & 1), (kt + 1) * BK);
+            const uint4* sl = lds[kt & 1];
+            bf16x8 b[P][TN];
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int row = BM + wn * WN + 16 * j + li;
+                    b[p][j] = __builtin_bit_cast(bf16x8, sl[(p * ROWS + row) * KC + (lg ^ swz4(row))]);
+                }
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int row = wm * WM + 16 * i + li;
+                bf16x8 a[P];
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    a[p] = __builtin_bit_cast(bf16x8, sl[(p * ROWS + row) * KC + (lg ^ swz4(row))]);
+#pragma unroll
+                for (int q = 0; q < SplitProducts<P>::count; ++q)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            a[SplitProducts<P>::a(q)], b[SplitProducts<P>::b(q)][j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();         // the next tile's first loads overwrite stage 0
+
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
+                    const int64_t col = n0 + wn * WN + 16 * j + li;
+                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r];
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 template <class Src, int BM, int BN>
@@ -329,6 +460,20 @@ template <class Src, int BM, int BN, int P>
 static hipError_t launch_bf16_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
     hipLaunchKernelGGL((k_gemm_bf16<Src, BM, BN, P>), dim3(grid), dim3(kGemmThreads), 0, st, s, tiles);
     return hipGetLastError();
+}
+
+template <class Src, int P>
+static hipError_t launch_bf16_big_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_gemm_bf16_big<Src, P>), dim3(grid), dim3(512), 0, st, s, tiles);
+    return hipGetLastError();
+}
+
+template <int P>
+static int occ_bf16_big() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16_big<OneProb, P>, 512, 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
 }
 
 template <int BM, int BN>
@@ -346,9 +491,15 @@ static int occ_bf16() {
     return n > 0 ? n : 1;
 }
 
+int64_t gemm_tiles_per_leaf(int planes, int tile, int64_t leaf) {
+    if (tile == 256) return planes == 3 ? (leaf / 256) * (leaf / 128) : (leaf / 256) * (leaf / 256);
+    return (leaf / tile) * (leaf / tile);
+}
+
 int gemm_blocks_per_cu(int planes, int tile) {
     // Occupancy does not depend on the descriptor source.
     if (planes == 0) return tile == 128 ? occ_f32<128, 128>() : occ_f32<64, 64>();
+    if (tile == 256) return planes == 2 ? occ_bf16_big<2>() : occ_bf16_big<3>();
     if (planes == 2) return tile == 128 ? occ_bf16<128, 128, 2>() : occ_bf16<64, 64, 2>();
     return tile == 128 ? occ_bf16<128, 128, 3>() : occ_bf16<64, 64, 3>();
 }
@@ -357,6 +508,8 @@ template <class Src>
 hipError_t launch_gemm(const Src& s, int planes, int tile, int64_t tiles, int grid, hipStream_t st) {
     if (planes == 0) return tile == 128 ? launch_f32_t<Src, 128, 128>(s, tiles, grid, st)
                                         : launch_f32_t<Src, 64, 64>(s, tiles, grid, st);
+    if (tile == 256) return planes == 2 ? launch_bf16_big_t<Src, 2>(s, tiles, grid, st)
+                                        : launch_bf16_big_t<Src, 3>(s, tiles, grid, st);
     if (planes == 2) return tile == 128 ? launch_bf16_t<Src, 128, 128, 2>(s, tiles, grid, st)
                                         : launch_bf16_t<Src, 64, 64, 2>(s, tiles, grid, st);
     return tile == 128 ? launch_bf16_t<Src, 128, 128, 3>(s, tiles, grid, st)

@@ -179,14 +179,80 @@ __device__ __forceinline__ float load1(const float* X, int64_t ld, int64_t n, in
 
 // Last divide level of the bf16 paths.  NOUT = 7: every node of level
 // depth-1 gives the seven operand pairs of its children (the leaves);
-// NOUT = 1 (depth 0): the root operands themselves.  Each output block
-// (leaf edge L) is written as P bf16 planes; A side row-major, B side
-// transposed (element (k, j) of T at j*L + k).
-//   A side: a thread owns 8 consecutive columns of one row.
-//   B side: a thread owns 8 consecutive rows of one column.
+// NOUT = 1 (depth 0): the root operands themselves.  Each output block (leaf
+// edge L) is written as P bf16 planes; A side row-major, B side transposed
+// (element (k, j) of T at j*L + k) so the leaf GEMM reads both k-contiguous.
+//
+// A block covers a 64 x 64 tile of output positions; thread t owns rows
+// 4*(t/16)..+3 and columns 4*(t%16)..+3 of it, read as float4 (16 threads
+// cover a 256-byte row segment).  A side: each thread stores 8-byte pieces,
+// 16 threads a 128-byte row segment.  B side: the tile of each output and
+// plane is transposed through LDS (rows of 64 bf16 + 8 pad) and written back
+// as whole 128-byte rows of T^T, kSplitRound outputs at a time.
+constexpr int kSplitTile = 64;
+constexpr int kSplitLdsRow = kSplitTile + 8;        // bf16 per LDS row (144 B, 16-byte aligned)
+
+template <int P> struct SplitRound { static constexpr int R = 2; };
+template <> struct SplitRound<3> { static constexpr int R = 1; };
+
+__device__ __forceinline__ float4 load4(const float* X, int64_t ld, int64_t n, int64_t r, int64_t c, bool bounded) {
+    if (bounded) return load4_bounded(X, n, r, c);
+    return *reinterpret_cast<const float4*>(X + r * ld + c);
+}
+
+// v[o][i][e]: output o at tile row i, column e of this thread's 4 x 4 piece.
+template <int NOUT>
+__device__ __forceinline__ void split_values(const float* X, int64_t ld, int64_t n, int64_t L, int64_t r0, int64_t c0,
+                                             int side, bool bounded, float (&v)[NOUT][4][4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t r = r0 + i;
+        if (NOUT == 7) {
+            const float4 x11 = load4(X, ld, n, r, c0, bounded);
+            const float4 x12 = load4(X, ld, n, r, c0 + L, bounded);
+            const float4 x21 = load4(X, ld, n, r + L, c0, bounded);
+            const float4 x22 = load4(X, ld, n, r + L, c0 + L, bounded);
+            const float* p11 = &x11.x; const float* p12 = &x12.x;
+            const float* p21 = &x21.x; const float* p22 = &x22.x;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float s7[7];
+                if (side == 0) seven_a(p11[e], p12[e], p21[e], p22[e], s7);
+                else seven_b(p11[e], p12[e], p21[e], p22[e], s7);
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o) v[o][i][e] = s7[o];
+            }
+        } else {
+            const float4 x = load4(X, ld, n, r, c0, bounded);
+            v[0][i][0] = x.x; v[0][i][1] = x.y; v[0][i][2] = x.z; v[0][i][3] = x.w;
+        }
+    }
+}
+
+// Split 4 values into P planes: planes[p] holds 4 bf16 packed in 8 bytes.
+template <int P>
+__device__ __forceinline__ void split4(const float (&x)[4], uint2 (&planes)[P]) {
+    float r[4] = {x[0], x[1], x[2], x[3]};
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        uint16_t b[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            b[e] = bf16_bits(r[e]);
+            r[e] = r[e] - bf16_value(b[e]);
+        }
+        planes[p] = make_uint2((uint32_t)b[0] | ((uint32_t)b[1] << 16), (uint32_t)b[2] | ((uint32_t)b[3] << 16));
+    }
+}
+
 template <int NOUT, int P>
-__device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t node, int64_t f, bool bounded) {
+__device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t node, int64_t tile, bool bounded,
+                                           uint16_t* lds) {
     const int64_t L = d.leaf;
+    const int64_t tiles_row = L / kSplitTile;
+    const int64_t R0 = (tile / tiles_row) * kSplitTile, C0 = (tile % tiles_row) * kSplitTile;
+    const int tid = threadIdx.x;
+    const int ri = 4 * (tid >> 4), ci = 4 * (tid & 15);
     const int plevel = (NOUT == 7) ? d.depth - 1 : 0;
     const float* X;
     int64_t ld;
@@ -194,51 +260,57 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
     uint16_t* base = reinterpret_cast<uint16_t*>(d.ws) + (side ? d.leaf_b : d.leaf_a) +
                      node * (int64_t)NOUT * P * L * L;
     const int64_t LL = L * L;
-    // (r0, c0): first element; the thread's 8 elements step along dc (A: a
-    // row, B: a column); the output offset of element e of block o, plane p
-    // is ((o*P + p)*LL + out0 + e) with out0 below.
-    int64_t r0, c0, dr, dc, out0;
+
+    float v[NOUT][4][4];
+    split_values<NOUT>(X, ld, d.n, L, R0 + ri, C0 + ci, side, bounded, v);
+
     if (side == 0) {
-        r0 = f / (L / 8); c0 = (f - r0 * (L / 8)) * 8; dr = 0; dc = 1; out0 = r0 * L + c0;
-    } else {
-        c0 = f % L; r0 = (f / L) * 8; dr = 1; dc = 0; out0 = c0 * L + r0;
-    }
-    float v[NOUT][8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int64_t r = r0 + e * dr, c = c0 + e * dc;
-        if (NOUT == 7) {
-            const float x11 = load1(X, ld, d.n, r, c, bounded);
-            const float x12 = load1(X, ld, d.n, r, c + L, bounded);
-            const float x21 = load1(X, ld, d.n, r + L, c, bounded);
-            const float x22 = load1(X, ld, d.n, r + L, c + L, bounded);
-            float s7[7];
-            if (side == 0) seven_a(x11, x12, x21, x22, s7);
-            else seven_b(x11, x12, x21, x22, s7);
+        for (int o = 0; o < NOUT; ++o)
 #pragma unroll
-            for (int o = 0; o < NOUT; ++o) v[o][e] = s7[o];
-        } else {
-            v[0][e] = load1(X, ld, d.n, r, c, bounded);
-        }
-    }
+            for (int i = 0; i < 4; ++i) {
+                uint2 pl[P];
+                split4<P>(v[o][i], pl);
 #pragma unroll
-    for (int o = 0; o < NOUT; ++o) {
-        float res[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) res[e] = v[o][e];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            uint32_t w[4];
-#pragma unroll
-            for (int e = 0; e < 8; e += 2) {
-                const uint16_t b0 = bf16_bits(res[e]), b1 = bf16_bits(res[e + 1]);
-                w[e / 2] = (uint32_t)b0 | ((uint32_t)b1 << 16);
-                res[e] = res[e] - bf16_value(b0);
-                res[e + 1] = res[e + 1] - bf16_value(b1);
+                for (int p = 0; p < P; ++p)
+                    *reinterpret_cast<uint2*>(base + ((int64_t)o * P + p) * LL + (R0 + ri + i) * L + C0 + ci) = pl[p];
             }
-            uint4* dst = reinterpret_cast<uint4*>(base + ((int64_t)o * P + p) * LL + out0);
-            *dst = make_uint4(w[0], w[1], w[2], w[3]);
+        return;
+    }
+    constexpr int R = NOUT == 1 ? 1 : SplitRound<P>::R;
+    constexpr int TILE_U16 = kSplitTile * kSplitLdsRow;
+#pragma unroll
+    for (int o0 = 0; o0 < NOUT; o0 += R) {
+        // transpose into LDS: column ci + e of T becomes row ci + e of T^T
+#pragma unroll
+        for (int oo = 0; oo < R; ++oo) {
+            if (o0 + oo >= NOUT) break;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float col[4] = {v[o0 + oo][0][e], v[o0 + oo][1][e], v[o0 + oo][2][e], v[o0 + oo][3][e]};
+                uint2 pl[P];
+                split4<P>(col, pl);
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    *reinterpret_cast<uint2*>(lds + (oo * P + p) * TILE_U16 + (ci + e) * kSplitLdsRow + ri) = pl[p];
+            }
         }
+        __syncthreads();
+        // write back whole rows of T^T: 8 chunks of 16 bytes per row
+#pragma unroll
+        for (int oo = 0; oo < R; ++oo) {
+            if (o0 + oo >= NOUT) break;
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int id = tid + 256 * h;
+                    const int j = id >> 3, q = id & 7;
+                    const uint4 val = *reinterpret_cast<const uint4*>(lds + (oo * P + p) * TILE_U16 + j * kSplitLdsRow + 8 * q);
+                    *reinterpret_cast<uint4*>(base + ((int64_t)(o0 + oo) * P + p) * LL + (C0 + j) * L + R0 + 8 * q) = val;
+                }
+        }
+        __syncthreads();
     }
 }
 
@@ -246,18 +318,17 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
 // user matrix (depth <= 1 with padding).
 template <class Src, int P>
 __global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
+    constexpr int R = SplitRound<P>::R;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[R * P * kSplitTile * kSplitLdsRow];
     int64_t local;
     const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
     const int side = blockIdx.y;
     const int64_t L = d.leaf;
-    const int64_t per_node = L * (L / 8);         // thread tasks per node
-    const int64_t bpn = (per_node + kStreamThreads - 1) / kStreamThreads;
-    const int64_t node = local / bpn, chunk = local - node * bpn;
-    const int64_t f = chunk * kStreamThreads + threadIdx.x;
-    if (f >= per_node) return;
+    const int64_t tiles = (L / kSplitTile) * (L / kSplitTile);
+    const int64_t node = local / tiles, tile = local - node * tiles;
     const bool bounded = d.bounded0 && d.depth <= 1;
-    if (d.depth == 0) split_body<1, P>(d, side, node, f, bounded);
-    else split_body<7, P>(d, side, node, f, bounded);
+    if (d.depth == 0) split_body<1, P>(d, side, node, tile, bounded, lds);
+    else split_body<7, P>(d, side, node, tile, bounded, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,10 +409,9 @@ int64_t blocks_divide(const ProbDesc& d, int level) {
     return pow7(level) * ((q4 + kStreamPerBlock - 1) / kStreamPerBlock);
 }
 int64_t blocks_split(const ProbDesc& d) {
-    const int64_t L = d.leaf;
-    const int64_t per_node = L * (L / 8);
+    const int64_t tiles = (d.leaf / kSplitTile) * (d.leaf / kSplitTile);
     const int64_t nodes = d.depth > 0 ? pow7(d.depth - 1) : 1;
-    return nodes * ((per_node + kStreamThreads - 1) / kStreamThreads);
+    return nodes * tiles;
 }
 int64_t blocks_combine(const ProbDesc& d, int level) { return blocks_divide(d, level); }
 

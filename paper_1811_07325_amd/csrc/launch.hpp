@@ -19,6 +19,9 @@ template <class Src> hipError_t launch_split(const Src& s, int planes, int64_t b
 template <class Src> hipError_t launch_combine(const Src& s, int level, int64_t blocks, hipStream_t st);
 template <class Src> hipError_t launch_gemm(const Src& s, int planes, int tile, int64_t tiles, int grid, hipStream_t st);
 
+// Tiles of one leaf of edge `leaf` for the GEMM variant (planes, tile class).
+int64_t gemm_tiles_per_leaf(int planes, int tile, int64_t leaf);
+
 // Resident blocks per CU of the leaf GEMM for (planes, tile).
 int gemm_blocks_per_cu(int planes, int tile);
 

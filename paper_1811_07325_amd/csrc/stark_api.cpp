@@ -35,9 +35,9 @@ void set_error(const char* fmt, ...) {
 const char* get_error() { return t_err.c_str(); }
 
 int gemm_grid(stark_ctx* ctx, int planes, int tile, int64_t tiles) {
-    static int occ_cache[4][2] = {{0}};
+    static int occ_cache[3][3] = {{0}};
     const int pi = planes == 0 ? 0 : planes == 2 ? 1 : 2;
-    const int ti = tile == 128 ? 0 : 1;
+    const int ti = tile == 128 ? 0 : tile == 64 ? 1 : 2;
     if (!occ_cache[pi][ti]) occ_cache[pi][ti] = gemm_blocks_per_cu(planes, tile);
     const int64_t g = (int64_t)ctx->num_cu * occ_cache[pi][ti];
     return (int)std::min<int64_t>(g, tiles);
@@ -52,7 +52,7 @@ stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned
         if (p.planes > 0) STK_HIP(launch_split(src, p.planes, blocks_split(d), st));
     }
     if (mask & STARK_PHASE_LEAF) {
-        const int64_t tiles = pow7(p.depth) * (p.leaf / p.tile) * (p.leaf / p.tile);
+        const int64_t tiles = pow7(p.depth) * gemm_tiles_per_leaf(p.planes, p.tile, p.leaf);
         STK_HIP(launch_gemm(src, p.planes, p.tile, tiles, gemm_grid(ctx, p.planes, p.tile, tiles), st));
     }
     if (mask & STARK_PHASE_COMBINE) {
@@ -195,6 +195,7 @@ stark_status stark_plan_info(int64_t n, int depth, stark_precision prec, stark_p
     out->pad_a = p.pad_a;
     out->pad_b = p.pad_b;
     out->bytes = p.bytes;
+    out->gemm_tile = p.tile;
     return STARK_OK;
 }
 
@@ -233,7 +234,8 @@ stark_status stark_create(stark_ctx** out, const stark_config* cfg) {
     // resident-block counts of every leaf-GEMM variant, cached before any
     // second thread (the serving engine) can launch
     for (int pl : {0, 2, 3})
-        for (int tile : {128, 64}) (void)gemm_grid(ctx.get(), pl, tile, 1);
+        for (int tile : {256, 128, 64})
+            if (pl > 0 || tile != 256) (void)gemm_grid(ctx.get(), pl, tile, 1);
     *out = ctx.release();
     return STARK_OK;
 }

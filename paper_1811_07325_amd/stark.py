@@ -80,7 +80,8 @@ class stark_plan_desc(ctypes.Structure):
                 ("div_slots", ctypes.c_int * STARK_MAX_DEPTH),
                 ("leaf_a", ctypes.c_int64), ("leaf_b", ctypes.c_int64), ("leaf_m", ctypes.c_int64),
                 ("comb", ctypes.c_int64 * STARK_MAX_DEPTH),
-                ("pad_a", ctypes.c_int64), ("pad_b", ctypes.c_int64), ("bytes", ctypes.c_size_t)]
+                ("pad_a", ctypes.c_int64), ("pad_b", ctypes.c_int64), ("bytes", ctypes.c_size_t),
+                ("gemm_tile", ctypes.c_int)]
 
 
 def _load() -> ctypes.CDLL:

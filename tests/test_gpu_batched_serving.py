@@ -1,0 +1,238 @@
+"""Batched launches and the serving engine on the GPU, through the C ABI.
+
+Both paths run the same kernels as a single multiply, with the same plan per
+problem, so their results must equal the single-call results bit for bit;
+integer inputs must equal brute force; float inputs are checked against the
+FP64 oracle on sampled rows.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1811_07325_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1811_07325_amd import stark
+    return stark
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    c = S.stark_create(0)
+    yield c
+    S.stark_destroy(c)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def single(S, ctx, dA, dB, n, depth, prec):
+    C = torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda")
+    S.stark_gemm(ctx, dA, dB, C, n, min(depth, S.stark_max_depth(n)), prec, None)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# Batched
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_batched_integer_exact_and_equal_to_single(S, ctx, prec):
+    sizes = [256, 384, 1000, 65, 300, 1024, 448, 128, 129, 512]
+    depth = 2
+    As = [inputs.integers(n, 100 + i) for i, n in enumerate(sizes)]
+    Bs = [inputs.integers(n, 200 + i) for i, n in enumerate(sizes)]
+    dA = [dev(a) for a in As]
+    dB = [dev(b) for b in Bs]
+    dC = [torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda") for n in sizes]
+    S.stark_gemm_batched(ctx, dA, dB, dC, sizes, depth, prec, None)
+    torch.cuda.synchronize()
+    for i, n in enumerate(sizes):
+        C = dC[i].cpu().numpy()
+        exact = As[i].astype(np.int64) @ Bs[i].astype(np.int64)
+        assert np.array_equal(C.astype(np.int64), exact), (i, n)
+        assert np.array_equal(C, single(S, ctx, dA[i], dB[i], n, depth, prec)), (i, n)
+
+
+def test_batched_float_equal_to_single_and_replays(S, ctx):
+    sizes = [1000, 256, 2048, 384, 777]
+    depth = 2
+    As = [inputs.uniform(n, 300 + i) for i, n in enumerate(sizes)]
+    Bs = [inputs.uniform(n, 400 + i) for i, n in enumerate(sizes)]
+    dA = [dev(a) for a in As]
+    dB = [dev(b) for b in Bs]
+    dC = [torch.empty((n, n), dtype=torch.float32, device="cuda") for n in sizes]
+    st = torch.cuda.Stream()
+    outs = []
+    for rep in range(4):           # eager, capture, two replays
+        for c in dC:
+            c.fill_(float("nan"))
+        torch.cuda.synchronize()
+        S.stark_gemm_batched(ctx, dA, dB, dC, sizes, depth, 1, st)
+        st.synchronize()
+        outs.append([c.cpu().numpy().copy() for c in dC])
+    for rep in outs[1:]:
+        for a, b in zip(outs[0], rep):
+            assert np.array_equal(a, b)
+    for i, n in enumerate(sizes):
+        assert np.array_equal(outs[0][i], single(S, ctx, dA[i], dB[i], n, depth, 1)), i
+
+
+def test_batched_64_uneven_problems(S):
+    """64 problems, n drawn from {256, 384, 1000, 1024, 2048, 3000, 4096}, FP32,
+    uniform[-1, 1]; every problem against the FP64 oracle on sampled rows."""
+    rng = np.random.default_rng(4)
+    sizes = [int(x) for x in rng.choice([256, 384, 1000, 1024, 2048, 3000, 4096], size=64)]
+    depth = 2
+    c = S.stark_create(0)
+    try:
+        As = [inputs.uniform(n, 1000 + i) for i, n in enumerate(sizes)]
+        Bs = [inputs.uniform(n, 2000 + i) for i, n in enumerate(sizes)]
+        dA = [dev(a) for a in As]
+        dB = [dev(b) for b in Bs]
+        dC = [torch.empty((n, n), dtype=torch.float32, device="cuda") for n in sizes]
+        S.stark_gemm_batched(c, dA, dB, dC, sizes, depth, 0, None)
+        torch.cuda.synchronize()
+        worst = 0.0
+        for i, n in enumerate(sizes):
+            rows = inputs.sample_rows(n, 4, 3000 + i)
+            ref = oracle.rows_f64(As[i], Bs[i], rows)
+            got = dC[i][torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+            err = np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2))
+            worst = max(worst, err)
+            assert err < 1e-5, (i, n, err)
+        print(f"worst sampled-row rel error over 64 problems: {worst:.2e}")
+        # spot-check bitwise equality with single calls
+        for i in (0, 17, 63):
+            assert np.array_equal(dC[i].cpu().numpy(), single(S, c, dA[i], dB[i], sizes[i], depth, 0))
+    finally:
+        S.stark_destroy(c)
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+def wait(S, c, tickets):
+    res = {}
+    pending = list(tickets)
+    while pending:
+        nxt = []
+        for t in pending:
+            r = S.stark_poll(c, t)
+            if r is None:
+                nxt.append(t)
+            else:
+                res[t] = r
+        pending = nxt
+    return res
+
+
+def test_serving_alone_vs_mix_bitwise(S):
+    c = S.stark_create(0, hbm_budget_bytes=8 << 30, max_slots=6)
+    try:
+        rng = np.random.default_rng(7)
+        reqs = []
+        for i in range(18):
+            n = int(rng.choice([128, 200, 512, 777, 1024, 2048]))
+            prec = int(rng.choice([0, 1]))
+            A, B = inputs.normal(n, 50 + i), inputs.normal(n, 90 + i)
+            reqs.append((n, prec, dev(A), dev(B), A, B))
+        alone = []
+        for n, prec, dA, dB, _, _ in reqs:
+            C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            t = S.stark_submit(c, n, prec, S.STARK_DEPTH_AUTO, dA, dB, C, tag=n)
+            wait(S, c, [t])
+            alone.append(C.cpu().numpy())
+        mixC = [torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda") for n, *_ in reqs]
+        tickets = [S.stark_submit(c, n, prec, S.STARK_DEPTH_AUTO, dA, dB, C, tag=i)
+                   for i, ((n, prec, dA, dB, _, _), C) in enumerate(zip(reqs, mixC))]
+        res = wait(S, c, tickets)
+        st = S.stark_stats(c)
+        assert st.completed == 2 * len(reqs) and st.failed == 0
+        assert st.max_concurrent > 1, "requests never overlapped"
+        for i, (C, a) in enumerate(zip(mixC, alone)):
+            assert np.array_equal(C.cpu().numpy(), a), i
+        # and equal to the single-call path at the depth the engine used
+        for i in (0, 5, 11):
+            n, prec, dA, dB, A, B = reqs[i]
+            d = res[tickets[i]].depth
+            C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            S.stark_gemm(c, dA, dB, C, n, d, prec, None)
+            torch.cuda.synchronize()
+            assert np.array_equal(C.cpu().numpy(), alone[i])
+        assert st.p99_ms >= st.p50_ms > 0
+    finally:
+        S.stark_destroy(c)
+
+
+def test_serving_generated_operands_and_checksums(S):
+    c = S.stark_create(0, hbm_budget_bytes=8 << 30, max_slots=4)
+    try:
+        spec = [(300, 1, 11), (640, 0, 12), (1024, 1, 13), (2000, 0, 14), (256, 2, 15)]
+        alone = {}
+        for n, p, seed in spec:
+            t = S.stark_submit(c, n, p, S.STARK_DEPTH_AUTO, seed=seed, tag=seed)
+            alone[seed] = wait(S, c, [t])[t].checksum
+        tickets = [S.stark_submit(c, n, p, S.STARK_DEPTH_AUTO, seed=seed, tag=seed) for n, p, seed in spec * 3]
+        res = wait(S, c, tickets)
+        for t, r in res.items():
+            assert r.checksum == alone[r.tag]
+        # the checksum is the sum of C = (1^T A)(B 1); A, B from the host twin
+        for n, p, seed in spec[:3]:
+            A = inputs.philox_normal(n, 2 * seed).astype(np.float64)
+            B = inputs.philox_normal(n, 2 * seed + 1).astype(np.float64)
+            ref = A.sum(axis=0) @ B.sum(axis=1)
+            bound = 1e-4 * n * np.sqrt(n) * n   # n * ||E||_F with ||E||_F <= 1e-4 ||C||_F
+            assert abs(alone[seed] - ref) <= bound, (n, alone[seed], ref)
+    finally:
+        S.stark_destroy(c)
+
+
+def test_serving_admission_respects_budget(S):
+    budget = 64 << 20
+    c = S.stark_create(0, hbm_budget_bytes=budget, max_slots=8)
+    try:
+        tickets = [S.stark_submit(c, 1024, 1, 1, seed=i, tag=i) for i in range(10)]
+        wait(S, c, tickets)
+        st = S.stark_stats(c)
+        assert st.completed == 10
+        assert st.max_inflight_bytes <= budget
+        with pytest.raises(S.StarkError) as e:
+            S.stark_submit(c, 4096, 0, 2, seed=1)
+        assert e.value.status == S.STARK_ENOMEM
+        rc, _ = S.stark_poll_status(c, 123456789)
+        assert rc == S.STARK_ENOTFOUND
+    finally:
+        S.stark_destroy(c)
+
+
+def test_serving_injected_failure_is_isolated(S, monkeypatch):
+    monkeypatch.setenv("STARK_FAULT_INJECT", "3")
+    c = S.stark_create(0, hbm_budget_bytes=2 << 30, max_slots=4)
+    try:
+        tickets = [S.stark_submit(c, 512, 1, 1, seed=i, tag=i) for i in range(6)]
+        out = {}
+        pending = list(tickets)
+        while pending:
+            nxt = []
+            for t in pending:
+                rc, r = S.stark_poll_status(c, t)
+                if rc == S.STARK_PENDING:
+                    nxt.append(t)
+                else:
+                    out[r.tag] = rc
+            pending = nxt
+        assert out[3] == S.STARK_EDEVICE
+        assert all(out[i] == S.STARK_OK for i in range(6) if i != 3)
+        st = S.stark_stats(c)
+        assert st.failed == 1 and st.completed == 5
+    finally:
+        S.stark_destroy(c)

@@ -44,6 +44,13 @@ def ctx(S, ws):
     S.stark_destroy(c)
 
 
+@pytest.fixture(scope="module")
+def ctx_big(S):
+    c = S.stark_create(0)     # library-owned workspace
+    yield c
+    S.stark_destroy(c)
+
+
 def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
@@ -68,7 +75,7 @@ INT_CASES = [(512, 2, "fp32"), (512, 2, "bf16x3"), (512, 2, "bf16x6"),
              (512, 0, "fp32"), (512, 1, "fp32"), (512, 3, "fp32"), (512, 0, "bf16x3"), (512, 3, "bf16x3"),
              (1000, 2, "fp32"), (1000, 2, "bf16x3"), (300, 1, "fp32"), (300, 1, "bf16x3"),
              (65, 0, "fp32"), (65, 0, "bf16x3"), (200, 2, "fp32"), (200, 2, "bf16x6"), (384, 1, "bf16x3"),
-             (129, 1, "fp32")]
+             (129, 0, "fp32"), (250, 1, "bf16x6"), (1, 0, "fp32"), (2, 0, "bf16x3"), (63, 0, "bf16x6")]
 
 
 @pytest.mark.parametrize("n,depth,prec", INT_CASES)
@@ -81,6 +88,20 @@ def test_integer_inputs_bit_exact(S, ctx, n, depth, prec):
     assert np.all(np.isfinite(C))
     assert np.array_equal(C.astype(np.int64), exact)
     assert np.array_equal(C, exact.astype(np.float32))
+
+
+@pytest.mark.parametrize("n,depth,prec", [(4096, 1, "bf16x3"), (4096, 0, "bf16x6"), (4096, 1, "bf16x6"),
+                                          (4032, 1, "bf16x3")])
+def test_integer_inputs_bit_exact_large_tiles(S, ctx_big, n, depth, prec):
+    """Leaves wide enough for the 256-wide tile class."""
+    print(f"case n={n} depth={depth} prec={prec}", flush=True)
+    assert S.stark_plan_info(n, depth, PREC[prec]).gemm_tile == 256
+    A = inputs.integers(n, 0)
+    B = inputs.integers(n, 1)
+    # every partial sum is an integer below 2^53: BLAS double products are exact
+    exact = (A.astype(np.float64) @ B.astype(np.float64)).astype(np.float32)
+    C = run(S, ctx_big, A, B, depth, prec)
+    assert np.array_equal(C, exact)
 
 
 # ---------------------------------------------------------------------------
@@ -97,7 +118,8 @@ def test_float_inputs_match_model(S, ctx, n, depth, prec):
     A = inputs.uniform(n, 0)
     B = inputs.uniform(n, 1)
     C = run(S, ctx, A, B, depth, prec)
-    model = oracle.strassen_model_f32(A, B, depth, prec)
+    # same zero padding as the library (multiple of 2^depth * 64)
+    model = oracle.strassen_model_f32(A, B, depth, prec, oracle.padded_size(n, depth, 64))
     exact = oracle.gemm_f64(A, B)
     e_gpu, e_model = rel_f(C, exact), rel_f(model, exact)
     d = rel_f(C, model)
