@@ -82,6 +82,22 @@ __device__ __forceinline__ void resolve(const ProbDesc& d, int side, int level, 
     }
 }
 
+// Layout of a bf16 leaf-operand plane (edge L, "rows" = the A rows or the B
+// columns, "k" = the contraction index).  The plane is cut into blocks of 16
+// rows x 32 k (1 KB each), stored block-row-major: block (r/16, k/32) at
+// ((r/16) * (L/32) + k/32) * 512 elements.  Inside a block, row r holds 4
+// chunks of 8 k; chunk c is stored at position c ^ swz4(r) of the row.  The
+// swizzle makes the LDS reads of MFMA operands (one chunk of 16 consecutive
+// rows) hit distinct bank groups for both 8- and 16-lane LDS phases, and a
+// block is copied to LDS unchanged, so one 64-lane 16-byte load moves one
+// contiguous block.
+__device__ __forceinline__ int swz4(int row) { return ((row >> 1) & 3) ^ ((row >> 3) & 1); }
+
+__device__ __forceinline__ int64_t blk_offset(int64_t r, int64_t k, int64_t L) {
+    const int rr = (int)(r & 15);
+    return (((r >> 4) * (L >> 5) + (k >> 5)) << 9) + ((rr * 4 + ((int)((k >> 3) & 3) ^ swz4(rr))) << 3) + (k & 7);
+}
+
 // A launch covers one problem (kernel-argument descriptor) or many (device
 // table).  `first_block` holds, per problem, the first block index of this
 // launch that belongs to it (ascending, first_block[0] == 0).

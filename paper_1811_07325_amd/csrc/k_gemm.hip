@@ -4,8 +4,8 @@
 //
 //  k_gemm_f32   binary32 operands read in place (views included), MFMA
 //               v_mfma_f32_16x16x4_f32, binary32 accumulation.
-//  k_gemm_bf16  operands pre-split into P bf16 planes (A row-major, B
-//               transposed so both are k-contiguous), MFMA
+//  k_gemm_bf16  operands pre-split into P bf16 planes (blocked layout of
+//               blk_offset; B transposed so both are k-contiguous), MFMA
 //               v_mfma_f32_16x16x32_bf16 over the cross products of the
 //               planes whose magnitude matters, binary32 accumulation.
 //
@@ -245,13 +245,13 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t tot
                 for (int i = 0; i < A_LD; ++i) {
                     const int idx = tid + kGemmThreads * i;
                     const int row = idx >> 2, q = idx & 3;
-                    ra[p][i] = *reinterpret_cast<const uint4*>(Ah + p * LL + (m0 + row) * L + k0 + 8 * q);
+                    ra[p][i] = *reinterpret_cast<const uint4*>(Ah + p * LL + blk_offset(m0 + row, k0 + 8 * q, L));
                 }
 #pragma unroll
                 for (int i = 0; i < B_LD; ++i) {
                     const int idx = tid + kGemmThreads * i;
                     const int row = idx >> 2, q = idx & 3;
-                    rb[p][i] = *reinterpret_cast<const uint4*>(Bh + p * LL + (n0 + row) * L + k0 + 8 * q);
+                    rb[p][i] = *reinterpret_cast<const uint4*>(Bh + p * LL + blk_offset(n0 + row, k0 + 8 * q, L));
                 }
             }
         };
@@ -331,22 +331,62 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t tot
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-template <int P> struct BigTile;
-template <> struct BigTile<2> { static constexpr int BM = 256, BN = 256, WAVES_M = 2, WAVES_N = 4; };
-template <> struct BigTile<3> { static constexpr int BM = 256, BN = 128, WAVES_M = 4, WAVES_N = 2; };
+// Configurations of the large-leaf kernel: block tile, wave grid, pipeline
+// depth (LDS stages).  STARK_BIG_CFG selects one at build time (tuning).
+template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int STAGES_>
+struct BigCfgT {
+    static constexpr int BM = BM_, BN = BN_, WAVES_M = WAVES_M_, WAVES_N = WAVES_N_, STAGES = STAGES_;
+    static constexpr int NW = WAVES_M * WAVES_N, NT = 64 * NW;
+};
+#ifndef STARK_BIG_CFG
+#define STARK_BIG_CFG 0
+#endif
+template <int P> struct BigCfg;
+#if STARK_BIG_CFG == 1      // 4 waves of 128 x 128
+template <> struct BigCfg<2> : BigCfgT<256, 256, 2, 2, 2> {};
+#elif STARK_BIG_CFG == 2    // 256 x 128, 8 waves of 64 x 64, three stages
+template <> struct BigCfg<2> : BigCfgT<256, 128, 4, 2, 3> {};
+#elif STARK_BIG_CFG == 3    // 128 x 128, 4 waves of 64 x 64, four stages
+template <> struct BigCfg<2> : BigCfgT<128, 128, 2, 2, 4> {};
+#elif STARK_BIG_CFG == 4    // 256 x 128, 4 waves of 128 x 64, three stages
+template <> struct BigCfg<2> : BigCfgT<256, 128, 2, 2, 3> {};
+#else                       // 256 x 256, 8 waves of 128 x 64, two stages
+template <> struct BigCfg<2> : BigCfgT<256, 256, 2, 4, 2> {};
+#endif
+template <> struct BigCfg<3> : BigCfgT<256, 128, 4, 2, 2> {};
 
-__device__ __forceinline__ int swz4(int row) { return (row >> 2) & 3; }
 
+
+// Wait until at most N of this wave's vector-memory operations are pending.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// ---------------------------------------------------------------------------
+// bf16-split leaf GEMM for large leaves.  Operand tiles go from global
+// memory straight into LDS (global_load_lds_dwordx4: each lane deposits 16
+// bytes at LDS base + 16 * lane), STAGES deep: while step k runs on the
+// matrix cores the loads of steps k+1 .. k+STAGES-1 are in flight, with no
+// register staging.  The LDS image of a stage is [plane][row][4 chunks of 8
+// bf16], A rows first, then B rows, chunks swizzled by swz4 -- the same image
+// as the operands' blocked layout in HBM (blk_offset), so each load copies a
+// contiguous 1 KB block.
+// ---------------------------------------------------------------------------
 template <class Src, int P>
-__global__ __launch_bounds__(512) void k_gemm_bf16_big(Src src, int64_t total_tiles) {
-    constexpr int BM = BigTile<P>::BM, BN = BigTile<P>::BN;
-    constexpr int WAVES_M = BigTile<P>::WAVES_M, WAVES_N = BigTile<P>::WAVES_N;
+__global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_t total_tiles) {
+    using Cfg = BigCfg<P>;
+    constexpr int BM = Cfg::BM, BN = Cfg::BN, NW = Cfg::NW, STAGES = Cfg::STAGES;
+    constexpr int WAVES_N = Cfg::WAVES_N;
     constexpr int BK = 32, KC = BK / 8;                 // 16-byte chunks per row and plane
     constexpr int ROWS = BM + BN;                       // LDS rows per plane (A rows, then B rows)
     constexpr int UNITS = P * ROWS * KC;                // 16-byte units per stage
-    static_assert(BM % 128 == 0 && BN % 128 == 0, "8 waves x 16 rows per direct load");
-    constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N, TM = WM / 16, TN = WN / 16;
-    __shared__ __attribute__((aligned(16))) uint4 lds[2][UNITS];
+    constexpr int GA = BM / 16, GB = BN / 16;           // 16-row groups per side
+    static_assert(GA % NW == 0 && GB % NW == 0, "groups must split evenly over the waves");
+    constexpr int LPS = P * (GA + GB) / NW;             // direct loads per lane per stage
+    constexpr int WM = BM / Cfg::WAVES_M, WN = BN / WAVES_N, TM = WM / 16, TN = WN / 16;
+    __shared__ __attribute__((aligned(16))) uint4 lds[STAGES][UNITS];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w / WAVES_N, wn = w % WAVES_N;
@@ -371,26 +411,27 @@ __global__ __launch_bounds__(512) void k_gemm_bf16_big(Src src, int64_t total_ti
         const bool crop = d.depth == 0 && d.bounded0;
         const int64_t m0 = tm * BM, n0 = tn * BN;
 
-        // One direct load of a wave fills 64 consecutive LDS units = 16 rows x
-        // 4 chunks of one plane and side.  Group g of a side (rows 16g..16g+15)
-        // of plane p is loaded by wave g % 8.  Lane l covers row 16g + l/4,
-        // chunk (l & 3) ^ swz4(row) = (l & 3) ^ ((l >> 4) & 3).
-        const int kc = (lane & 3) ^ ((lane >> 4) & 3);
-        const uint16_t* a_src = Ah + (m0 + (lane >> 2)) * L + 8 * kc;
-        const uint16_t* b_src = Bh + (n0 + (lane >> 2)) * L + 8 * kc;
+        // One direct load of a wave moves one 1 KB block of the blocked
+        // operand layout (16 rows x 32 k, chunks already swizzled) into 64
+        // consecutive LDS units.  Block row g of a side (rows 16g..16g+15) of
+        // plane p is loaded by wave g % NW; lane l moves bytes 16l..16l+15.
+        const int64_t blocks_k = L >> 5;                  // blocks per block row
+        const uint16_t* a_src = Ah + ((m0 >> 4) * blocks_k << 9) + 8 * lane;
+        const uint16_t* b_src = Bh + ((n0 >> 4) * blocks_k << 9) + 8 * lane;
         auto issue = [&](int stage, int64_t k0) {
+            const int64_t kb = (k0 >> 5) << 9;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
 #pragma unroll
-                for (int r = 0; r < BM / 128; ++r) {
-                    const int g = w + 8 * r;
-                    __builtin_amdgcn_global_load_lds(a_src + p * LL + (int64_t)(16 * g) * L + k0,
+                for (int r = 0; r < GA / NW; ++r) {
+                    const int g = w + NW * r;
+                    __builtin_amdgcn_global_load_lds(a_src + p * LL + ((int64_t)g * blocks_k << 9) + kb,
                                                      (lds_void_t*)&lds[stage][(p * ROWS + 16 * g) * KC], 16, 0, 0);
                 }
 #pragma unroll
-                for (int r = 0; r < BN / 128; ++r) {
-                    const int g = w + 8 * r;
-                    __builtin_amdgcn_global_load_lds(b_src + p * LL + (int64_t)(16 * g) * L + k0,
+                for (int r = 0; r < GB / NW; ++r) {
+                    const int g = w + NW * r;
+                    __builtin_amdgcn_global_load_lds(b_src + p * LL + ((int64_t)g * blocks_k << 9) + kb,
                                                      (lds_void_t*)&lds[stage][(p * ROWS + BM + 16 * g) * KC], 16, 0,
                                                      0);
                 }
@@ -404,12 +445,17 @@ __global__ __launch_bounds__(512) void k_gemm_bf16_big(Src src, int64_t total_ti
             for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
         const int64_t KT = L / BK;
-        issue(0, 0);
+#pragma unroll
+        for (int s = 0; s < STAGES - 1; ++s)
+            if (s < KT) issue(s, s * BK);
         for (int64_t kt = 0; kt < KT; ++kt) {
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();     // stage kt landed everywhere; stage kt+1's old reads are done
-            if (kt + 1 < KT) issue((int)((kt + 1) & 1), (kt + 1) * BK);
-            const uint4* sl = lds[kt & 1];
+            // step kt has landed once at most the loads of the later steps
+            // already issued (up to STAGES-2 of them) are pending
+            if (kt + STAGES - 2 < KT) wait_vmcnt<LPS * (STAGES - 2)>();
+            else wait_vmcnt<0>();
+            __syncthreads();     // every wave's part of step kt landed; step kt-1's reads are done
+            if (kt + STAGES - 1 < KT) issue((int)((kt + STAGES - 1) % STAGES), (kt + STAGES - 1) * BK);
+            const uint4* sl = lds[kt % STAGES];
             bf16x8 b[P][TN];
 #pragma unroll
             for (int p = 0; p < P; ++p)
@@ -433,7 +479,7 @@ __global__ __launch_bounds__(512) void k_gemm_bf16_big(Src src, int64_t total_ti
                             a[SplitProducts<P>::a(q)], b[SplitProducts<P>::b(q)][j], acc[i][j], 0, 0, 0);
             }
         }
-        __syncthreads();         // the next tile's first loads overwrite stage 0
+        __syncthreads();         // the next tile's first loads overwrite the stages
 
 #pragma unroll
         for (int i = 0; i < TM; ++i)
@@ -464,14 +510,14 @@ static hipError_t launch_bf16_t(const Src& s, int64_t tiles, int grid, hipStream
 
 template <class Src, int P>
 static hipError_t launch_bf16_big_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemm_bf16_big<Src, P>), dim3(grid), dim3(512), 0, st, s, tiles);
+    hipLaunchKernelGGL((k_gemm_bf16_big<Src, P>), dim3(grid), dim3(BigCfg<P>::NT), 0, st, s, tiles);
     return hipGetLastError();
 }
 
 template <int P>
 static int occ_bf16_big() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16_big<OneProb, P>, 512, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16_big<OneProb, P>, BigCfg<P>::NT, 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
@@ -492,7 +538,9 @@ static int occ_bf16() {
 }
 
 int64_t gemm_tiles_per_leaf(int planes, int tile, int64_t leaf) {
-    if (tile == 256) return planes == 3 ? (leaf / 256) * (leaf / 128) : (leaf / 256) * (leaf / 256);
+    if (tile == 256)
+        return planes == 3 ? (leaf / BigCfg<3>::BM) * (leaf / BigCfg<3>::BN)
+                           : (leaf / BigCfg<2>::BM) * (leaf / BigCfg<2>::BN);
     return (leaf / tile) * (leaf / tile);
 }
 

@@ -180,15 +180,17 @@ __device__ __forceinline__ float load1(const float* X, int64_t ld, int64_t n, in
 // Last divide level of the bf16 paths.  NOUT = 7: every node of level
 // depth-1 gives the seven operand pairs of its children (the leaves);
 // NOUT = 1 (depth 0): the root operands themselves.  Each output block (leaf
-// edge L) is written as P bf16 planes; A side row-major, B side transposed
-// (element (k, j) of T at j*L + k) so the leaf GEMM reads both k-contiguous.
+// edge L) is written as P bf16 planes in the blocked layout of blk_offset
+// (common.hpp): A side with rows = rows of S, B side with rows = columns of T
+// (transposed), so the leaf GEMM reads both k-contiguous.
 //
 // A block covers a 64 x 64 tile of output positions; thread t owns rows
 // 4*(t/16)..+3 and columns 4*(t%16)..+3 of it, read as float4 (16 threads
-// cover a 256-byte row segment).  A side: each thread stores 8-byte pieces,
-// 16 threads a 128-byte row segment.  B side: the tile of each output and
-// plane is transposed through LDS (rows of 64 bf16 + 8 pad) and written back
-// as whole 128-byte rows of T^T, kSplitRound outputs at a time.
+// cover a 256-byte row segment).  A side: each thread stores 8-byte pieces;
+// a tile fills 8 whole 1 KB blocks per output and plane.  B side: the tile of
+// each output and plane is transposed through LDS (rows of 64 bf16 + 8 pad)
+// and written back in 16-byte chunks of T^T rows, kSplitRound outputs at a
+// time.
 constexpr int kSplitTile = 64;
 constexpr int kSplitLdsRow = kSplitTile + 8;        // bf16 per LDS row (144 B, 16-byte aligned)
 
@@ -273,7 +275,8 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
                 split4<P>(v[o][i], pl);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    *reinterpret_cast<uint2*>(base + ((int64_t)o * P + p) * LL + (R0 + ri + i) * L + C0 + ci) = pl[p];
+                    *reinterpret_cast<uint2*>(base + ((int64_t)o * P + p) * LL + blk_offset(R0 + ri + i, C0 + ci, L)) =
+                        pl[p];
             }
         return;
     }
@@ -307,7 +310,8 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
                     const int id = tid + 256 * h;
                     const int j = id >> 3, q = id & 7;
                     const uint4 val = *reinterpret_cast<const uint4*>(lds + (oo * P + p) * TILE_U16 + j * kSplitLdsRow + 8 * q);
-                    *reinterpret_cast<uint4*>(base + ((int64_t)(o0 + oo) * P + p) * LL + (C0 + j) * L + R0 + 8 * q) = val;
+                    *reinterpret_cast<uint4*>(base + ((int64_t)(o0 + oo) * P + p) * LL + blk_offset(C0 + j, R0 + 8 * q, L)) =
+                        val;
                 }
         }
         __syncthreads();

@@ -12,7 +12,9 @@ import os
 import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libstark.so")
+# STARK_LIBRARY selects another build of the same library (e.g. a different
+# leaf-GEMM configuration); by default the in-tree libstark.so.
+LIB_PATH = os.environ.get("STARK_LIBRARY") or os.path.join(_HERE, "libstark.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "stark.h")
 
 STARK_OK = 0

@@ -171,6 +171,17 @@ def test_divide_levels_bit_exact(S, ctx, ws, n):
         assert np.array_equal(gb1[c], T1[sB5]), c
 
 
+def unblock(x, L):
+    """Blocked bf16 plane layout of the library (1 KB blocks of 16 rows x 32 k,
+    block-row-major; chunk c of row r stored at c ^ swz(r)) -> row-major."""
+    r = np.arange(L)[:, None]
+    k = np.arange(L)[None, :]
+    rr = r & 15
+    swz = ((rr >> 1) & 3) ^ ((rr >> 3) & 1)
+    off = (((r >> 4) * (L >> 5) + (k >> 5)) << 9) + ((rr * 4 + (((k >> 3) & 3) ^ swz)) << 3) + (k & 7)
+    return x[..., off]
+
+
 @pytest.mark.parametrize("prec,depth,n", [("bf16x3", 1, 256), ("bf16x6", 2, 256), ("bf16x3", 0, 128),
                                           ("bf16x3", 1, 200)])
 def test_split_leaf_operands_bit_exact(S, ctx, ws, prec, depth, n):
@@ -195,8 +206,8 @@ def test_split_leaf_operands_bit_exact(S, ctx, ws, prec, depth, n):
             ny.extend(Ty)
         Xs, Ys = nx, ny
     nleaf = 7 ** depth
-    ga = ws_view(ws, d.leaf_a, nleaf * P * L * L, np.uint16).reshape(nleaf, P, L, L)
-    gb = ws_view(ws, d.leaf_b, nleaf * P * L * L, np.uint16).reshape(nleaf, P, L, L)
+    ga = unblock(ws_view(ws, d.leaf_a, nleaf * P * L * L, np.uint16).reshape(nleaf, P, L * L), L)
+    gb = unblock(ws_view(ws, d.leaf_b, nleaf * P * L * L, np.uint16).reshape(nleaf, P, L * L), L)
     for i in range(nleaf):
         assert np.array_equal(ga[i], oracle.split_bf16(Xs[i], P)), i
         # B side is stored transposed: plane[j][k] = split(T)[k][j]
