@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--n", type=int, default=16384)
-    p.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "bf16x6"])
+    p.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "bf16x6", "fp16x3"])
     p.add_argument("--min-depth", type=int, default=2)
     p.add_argument("--max-depth", type=int, default=4)
     p.add_argument("--depth", type=int, default=None, help="fixed depth (skips the autotuner)")
@@ -215,7 +215,7 @@ def main() -> int:
     planes = plan.planes
     L = plan.leaf
     nleaf = 7 ** depth
-    prods = {0: 1, 2: 3, 3: 6}[planes]
+    prods = {0: 1, 2: 3, 3: 6}[planes]     # matrix-core products per leaf (FP16X3: 3)
     leaf_flops = 2.0 * L ** 3 * nleaf * prods        # matrix-core work of one launch
     unit_peak = PEAK["fp32"] if planes == 0 else PEAK["bf16"]
     achieved = leaf_flops / (t_leaf * 1e-3)
@@ -249,14 +249,15 @@ def main() -> int:
         f"({achieved * 1e-12:.1f} TF/s of {unit_peak * 1e-12:.0f}), combine {t_comb:.3f} ms")
     roofline = {"bound": "mfma", "achieved": achieved * 1e-12, "peak": unit_peak * 1e-12, "unit": "TFLOP/s",
                 "frac": achieved / unit_peak, "traffic": traffic,
-                "kernel": "k_gemm_bf16" if planes else "k_gemm_f32",
+                "kernel": ("k_gemm_bf16_big" if plan.gemm_tile == 256 else "k_gemm_bf16") if planes else "k_gemm_f32",
                 "work_per_launch": f"{nleaf} leaves x {prods} x 2*{L}^3 flops"}
 
     # -- comparisons on the same GPU ----------------------------------------------
     compare = {}
     if not args.no_compare:
         for name, p_, dmin, dmax in (("fp32_strassen", S.STARK_FP32, 1, 4), ("fp32_classical", S.STARK_FP32, 0, 0),
-                                     ("bf16x6_strassen", S.STARK_BF16X6, 1, 4),
+                                     ("fp16x3_strassen", S.STARK_FP16X3, 2, 4),
+                                     ("bf16x6_strassen", S.STARK_BF16X6, 2, 4),
                                      ("bf16x3_classical", S.STARK_BF16X3, 0, 0)):
             if dmin == dmax:
                 d_ = dmin

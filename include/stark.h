@@ -51,11 +51,18 @@ typedef int stark_status;
  * lo = bf16(x - hi) (round to nearest even) and the product is formed from
  * hi*hi + hi*lo + lo*hi on bf16 matrix cores with binary32 accumulation.
  * BF16X6: three terms (hi, mid, lo) and the six products whose order of
- * magnitude is at least 2^-16 of hi*hi. */
+ * magnitude is at least 2^-16 of hi*hi.
+ * FP16X3: each matrix is scaled by a power of two 2^e (from its largest
+ * magnitude, so every leaf operand stays below 2^14), each leaf operand split
+ * into two binary16 terms hi + lo (22 significant bits), hi*hi + hi*lo +
+ * lo*hi on fp16 matrix cores with binary32 accumulation, and the product
+ * scaled back exactly.  Entries smaller than about 2^-25 times the largest
+ * entry of their matrix lose relative precision (binary16 subnormals). */
 typedef enum {
     STARK_FP32 = 0,
     STARK_BF16X3 = 1,
-    STARK_BF16X6 = 2
+    STARK_BF16X6 = 2,
+    STARK_FP16X3 = 3
 } stark_precision;
 
 #define STARK_DEPTH_AUTO (-1)    /* let the autotuner choose the depth        */
@@ -217,6 +224,9 @@ typedef struct {
     int64_t pad_a, pad_b;     /* byte offsets of padded copies (depth-0 FP32 only) */
     size_t bytes;             /* total workspace                                   */
     int gemm_tile;            /* leaf GEMM tile class (64, 128 or 256)             */
+    int64_t scale;            /* FP16X3: byte offset of the scale region: 2 x 256
+                                 binary32 partial maxima, then the two int32
+                                 exponents e_A, e_B (-1 otherwise)                 */
 } stark_plan_desc;
 
 stark_status stark_plan_info(int64_t n, int depth, stark_precision p, stark_plan_desc* out);

@@ -74,6 +74,9 @@ def _load():
     lib.oracle_strassen_model_f32.argtypes = [P, P, P, I64, ctypes.c_int, I64, ctypes.c_int]
     lib.oracle_strassen_model_f32.restype = ctypes.c_int
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_f16_scale_exp.argtypes = [P, I64, ctypes.c_int]
+    lib.oracle_f16_scale_exp.restype = ctypes.c_int
+    lib.oracle_split_f16.argtypes = [P, I64, ctypes.c_int, P]
     _lib = lib
     return lib
 
@@ -187,13 +190,27 @@ def bf16_bits_to_f32(b) -> np.ndarray:
     return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
 
 
-MODEL_MODES = {"fp32": 0, "bf16x3": 2, "bf16x6": 3}
+MODEL_MODES = {"fp32": 0, "bf16x3": 2, "bf16x6": 3, "fp16x3": 4}
+
+
+def f16_scale_exp(X, depth: int) -> int:
+    """Power-of-two exponent that scales the FP16X3 leaf operands of X below 2^14."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    return int(_load().oracle_f16_scale_exp(_ptr(X), X.size, depth))
+
+
+def split_f16(x, e: int) -> np.ndarray:
+    """binary16 split of x * 2^e: planes (2, *x.shape) as binary32 values."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.empty((2,) + x.shape, dtype=np.float32)
+    _load().oracle_split_f16(_ptr(x), x.size, e, _ptr(out))
+    return out
 
 
 def strassen_model_f32(A, B, depth: int, mode: str, n_pad: int | None = None) -> np.ndarray:
     """Arithmetic model of the GPU path: binary32 divide/combine, leaf products
     exact in binary64 from the leaf operands as seen by `mode` ("fp32",
-    "bf16x3", "bf16x6"), rounded to binary32.  Returns float32 n x n."""
+    "bf16x3", "bf16x6", "fp16x3"), rounded to binary32.  Returns float32 n x n."""
     A = np.ascontiguousarray(A, dtype=np.float32)
     B = np.ascontiguousarray(B, dtype=np.float32)
     n = A.shape[0]

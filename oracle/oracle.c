@@ -43,6 +43,7 @@
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math:
  * every operation below is a plain IEEE operation in the written order).
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -337,6 +338,46 @@ static float bf16_to_f32(uint16_t b)
     return x;
 }
 
+/* binary16 (IEEE 754 half): 1 sign, 5 exponent (bias 15), 10 fraction bits.
+ * Round a binary32 to the nearest binary16 value, ties to even, with
+ * subnormals (spacing 2^-24) and overflow to infinity; the result is
+ * returned as its exact binary32 value (every binary16 is a binary32). */
+static float f16_round(float x)
+{
+    if (x != x) return x;
+    const double ax = fabs((double)x);
+    if (ax == 0.0) return x;
+    int e;
+    frexp(ax, &e);                 /* ax = m * 2^e, m in [0.5, 1) */
+    int ulp_exp = e - 11;          /* 11 significant bits */
+    if (ulp_exp < -24) ulp_exp = -24;   /* subnormal spacing */
+    const double ulp = ldexp(1.0, ulp_exp);
+    double q = ax / ulp;           /* exact: ax is a binary32, ulp a power of two */
+    double fl = floor(q);
+    const double rem = q - fl;
+    if (rem > 0.5 || (rem == 0.5 && fmod(fl, 2.0) != 0.0)) fl += 1.0;
+    double r = fl * ulp;
+    if (r >= 65520.0) r = INFINITY;     /* beyond the largest finite half after rounding */
+    return (float)(x < 0 ? -r : r);
+}
+
+/* Power-of-two scale exponent of the FP16X3 leaf operands of one matrix:
+ * with max|X| = m * 2^E (m in [0.5, 1)), the leaf operands after `depth`
+ * levels are at most 2^depth max|X|, so scaling by 2^(14 - depth - E)
+ * keeps them below 2^14 (binary16's largest finite value is 65504). */
+int oracle_f16_scale_exp(const float* X, int64_t count, int depth)
+{
+    float m = 0.0f;
+    for (int64_t i = 0; i < count; ++i) {
+        const float a = fabsf(X[i]);
+        if (a > m) m = a;
+    }
+    if (m == 0.0f) return 0;
+    int E;
+    frexp((double)m, &E);
+    return 14 - depth - E;
+}
+
 /* x ~= hi + mid + lo with each term bfloat16: hi = rne(x), mid = rne(x - hi),
  * lo = rne(x - hi - mid).  The differences are exact in binary32. `terms` is
  * 2 (hi, mid) or 3; out has `terms` planes of count values each. */
@@ -364,14 +405,19 @@ void oracle_split_bf16(const float* x, int64_t count, int terms, uint16_t* out)
 /*   mode 2 (BF16X3): xh*yh + xh*yl + xl*yh           (2-term split)          */
 /*   mode 3 (BF16X6): + xh*ym.. the six cross terms of the 3-term split whose */
 /*                    plane indices sum to at most 2                          */
+/*   mode 4 (FP16X3): x scaled by 2^ex, y by 2^ey (oracle_f16_scale_exp of  */
+/*                    the whole A and B), split into two binary16 terms,     */
+/*                    xh*yh + xh*yl + xl*yh, result scaled by 2^-(ex+ey)     */
 /* The GPU accumulates the leaf sums in binary32 instead; the difference is  */
 /* that accumulation's rounding only, so GPU results sit within a few units  */
 /* of accumulation error of this model at any depth.                         */
 /* ------------------------------------------------------------------------ */
+static int g_model_ex = 0, g_model_ey = 0;   /* FP16X3 scale exponents of the current run */
+
 static void leaf_model(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* Z, int64_t ldz,
                        int64_t m, int mode)
 {
-    const int terms = mode == 0 ? 1 : mode == 2 ? 2 : 3;
+    const int terms = mode == 0 ? 1 : (mode == 2 || mode == 4) ? 2 : 3;
     const size_t mm = (size_t)m * (size_t)m;
     /* planes of X and Y as doubles (mode 0: the values themselves) */
     double* xp = (double*)malloc((size_t)terms * mm * sizeof(double));
@@ -379,9 +425,11 @@ static void leaf_model(const float* X, int64_t ldx, const float* Y, int64_t ldy,
     for (int64_t i = 0; i < m; ++i)
         for (int64_t j = 0; j < m; ++j) {
             float rx = X[i * ldx + j], ry = Y[i * ldy + j];
+            if (mode == 4) { rx = ldexpf(rx, g_model_ex); ry = ldexpf(ry, g_model_ey); }
             for (int p = 0; p < terms; ++p) {
                 float hx = rx, hy = ry;
-                if (mode != 0) { hx = bf16_to_f32(bf16_rne(rx)); hy = bf16_to_f32(bf16_rne(ry)); }
+                if (mode == 4) { hx = f16_round(rx); hy = f16_round(ry); }
+                else if (mode != 0) { hx = bf16_to_f32(bf16_rne(rx)); hy = bf16_to_f32(bf16_rne(ry)); }
                 xp[(size_t)p * mm + (size_t)i * m + j] = hx;
                 yp[(size_t)p * mm + (size_t)i * m + j] = hy;
                 rx = rx - hx;
@@ -404,7 +452,11 @@ static void leaf_model(const float* X, int64_t ldx, const float* Y, int64_t ldy,
                 }
         }
     for (int64_t i = 0; i < m; ++i)
-        for (int64_t j = 0; j < m; ++j) Z[i * ldz + j] = (float)acc[(size_t)i * m + j];
+        for (int64_t j = 0; j < m; ++j) {
+            float z = (float)acc[(size_t)i * m + j];
+            if (mode == 4) z = ldexpf(z, -(g_model_ex + g_model_ey));
+            Z[i * ldz + j] = z;
+        }
     free(xp); free(yp); free(acc);
 }
 
@@ -427,13 +479,17 @@ static void model_rec(const float* X, int64_t ldx, const float* Y, int64_t ldy, 
 }
 
 /* C (n x n, binary32) from binary32 A, B: zero-pad to n_pad, `depth` levels,
- * leaf arithmetic `mode` (0, 2, 3), crop.  Returns 0 or -1. */
+ * leaf arithmetic `mode` (0, 2, 3, 4), crop.  Returns 0 or -1. */
 int oracle_strassen_model_f32(const float* A, const float* B, float* C, int64_t n, int depth, int64_t n_pad,
                               int mode)
 {
     if (n <= 0 || depth < 0 || depth > 20 || n_pad < n || (n_pad % ((int64_t)1 << depth)) != 0 ||
-        (mode != 0 && mode != 2 && mode != 3))
+        (mode != 0 && mode != 2 && mode != 3 && mode != 4))
         return -1;
+    if (mode == 4) {
+        g_model_ex = oracle_f16_scale_exp(A, n * n, depth);
+        g_model_ey = oracle_f16_scale_exp(B, n * n, depth);
+    }
     const size_t N = (size_t)n_pad * (size_t)n_pad;
     float* Ap = (float*)calloc(N, sizeof(float));
     float* Bp = (float*)calloc(N, sizeof(float));
@@ -446,6 +502,17 @@ int oracle_strassen_model_f32(const float* A, const float* B, float* C, int64_t 
     for (int64_t i = 0; i < n; ++i) memcpy(C + i * n, Cp + i * n_pad, (size_t)n * sizeof(float));
     free(Ap); free(Bp); free(Cp);
     return 0;
+}
+
+/* x * 2^e ~= hi + lo with binary16 terms (RNE), as binary32 values. */
+void oracle_split_f16(const float* x, int64_t count, int e, float* out)
+{
+    for (int64_t i = 0; i < count; ++i) {
+        const float v = ldexpf(x[i], e);
+        const float hi = f16_round(v);
+        out[i] = hi;
+        out[count + i] = f16_round(v - hi);
+    }
 }
 
 /* Threads the OpenMP loops above use (for reporting CPU timings). */

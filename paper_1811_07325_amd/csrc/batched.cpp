@@ -22,7 +22,7 @@ namespace stk {
 
 namespace {
 
-enum LaunchKind { kPad, kDivide, kSplit, kGemm, kCombine };
+enum LaunchKind { kPad, kDivide, kAbsmax, kScaleExp, kSplit, kGemm, kCombine };
 
 struct BatchLaunch {
     LaunchKind kind;
@@ -36,6 +36,7 @@ struct BatchEntry {
     void* dev = nullptr;           // ProbDesc[count] followed by prefix arrays
     int count = 0;
     int planes = 0;
+    bool fp16 = false;
     std::vector<BatchLaunch> launches;
     hipGraphExec_t exec = nullptr;
     int uses = 0;
@@ -65,9 +66,12 @@ stark_status enqueue(stark_ctx* ctx, const BatchEntry& e, hipStream_t st) {
         switch (l.kind) {
             case kPad: STK_HIP(launch_pad(src, l.total, st)); break;
             case kDivide: STK_HIP(launch_divide(src, l.level, l.total, st)); break;
+            case kAbsmax: STK_HIP(launch_absmax(src, l.total, st)); break;
+            case kScaleExp: STK_HIP(launch_scale_exp(src, l.total, st)); break;
             case kSplit: STK_HIP(launch_split(src, e.planes, l.total, st)); break;
             case kGemm:
-                STK_HIP(launch_gemm(src, e.planes, l.tile, l.total, gemm_grid(ctx, e.planes, l.tile, l.total), st));
+                STK_HIP(launch_gemm(src, e.planes, l.tile, e.fp16, l.total,
+                                    gemm_grid(ctx, e.planes, l.tile, l.total), st));
                 break;
             case kCombine: STK_HIP(launch_combine(src, l.level, l.total, st)); break;
         }
@@ -109,6 +113,7 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
         BatchEntry e;
         e.count = count;
         e.planes = plans[0].planes;
+        e.fp16 = plans[0].scale >= 0;
         std::vector<ProbDesc> descs(count);
         for (int i = 0; i < count; ++i)
             descs[i] = make_desc(plans[i], A[i], B[i], C[i], static_cast<char*>(ctx->ws) + off[i]);
@@ -132,6 +137,10 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
         add_launch(kPad, 0, 0, [&](int i) { return plans[i].pad_a >= 0 ? blocks_pad(descs[i]) : 0; });
         for (int l = 0; l < max_fp32; ++l)
             add_launch(kDivide, l, 0, [&](int i) { return plans[i].fp32_levels > l ? blocks_divide(descs[i], l) : 0; });
+        if (e.fp16) {
+            add_launch(kAbsmax, 0, 0, [&](int) { return (int64_t)kScaleParts; });
+            add_launch(kScaleExp, 0, 0, [&](int) { return (int64_t)1; });
+        }
         if (e.planes > 0) add_launch(kSplit, 0, 0, [&](int i) { return blocks_split(descs[i]); });
         for (int tile : {256, 128, 64})
             add_launch(kGemm, 0, tile, [&](int i) {

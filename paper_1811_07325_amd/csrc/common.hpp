@@ -32,7 +32,11 @@ struct ProbDesc {
     int64_t leaf_m;                            // float offset of leaf products (-1: C)
     int64_t comb[STK_MAXD];                    // float offsets of combine outputs
     int64_t pad_a, pad_b;                      // float offsets of padded copies (-1)
+    int fp16;                                  // leaf planes are binary16 (FP16X3)
+    int64_t scale;                             // float offset of the FP16X3 scale region (-1)
 };
+
+constexpr int kScaleParts = 256;               // partial maxima per matrix (FP16X3)
 
 // Where the operand blocks of the seven products live after one divide step
 // (Algorithm 1): a materialised slot index, or a view of the parent's
@@ -83,19 +87,24 @@ __device__ __forceinline__ void resolve(const ProbDesc& d, int side, int level, 
 }
 
 // Layout of a bf16 leaf-operand plane (edge L, "rows" = the A rows or the B
-// columns, "k" = the contraction index).  The plane is cut into blocks of 16
-// rows x 32 k (1 KB each), stored block-row-major: block (r/16, k/32) at
-// ((r/16) * (L/32) + k/32) * 512 elements.  Inside a block, row r holds 4
-// chunks of 8 k; chunk c is stored at position c ^ swz4(r) of the row.  The
-// swizzle makes the LDS reads of MFMA operands (one chunk of 16 consecutive
-// rows) hit distinct bank groups for both 8- and 16-lane LDS phases, and a
-// block is copied to LDS unchanged, so one 64-lane 16-byte load moves one
-// contiguous block.
-__device__ __forceinline__ int swz4(int row) { return ((row >> 1) & 3) ^ ((row >> 3) & 1); }
+// columns, "k" = the contraction index).  The plane is cut into 1 KB blocks
+// of kBlkRows rows x kBlkK k, stored block-row-major: block (r/kBlkRows,
+// k/kBlkK) at ((r/kBlkRows) * (L/kBlkK) + k/kBlkK) * 512 elements.  Inside a
+// block, row r holds kBlkK/8 chunks of 8 k; chunk c is stored at position
+// c ^ blk_swz(r) of the row.  The swizzle makes the LDS reads of MFMA
+// operands (one chunk of consecutive rows) hit distinct bank groups for both
+// 8- and 16-lane LDS phases, and a block is copied to LDS unchanged, so one
+// 64-lane 16-byte load moves one contiguous block.
+constexpr int kBlkRows = 16;
+constexpr int kBlkK = 512 / kBlkRows;    // 32
+constexpr int kBlkChunks = kBlkK / 8;     // 4
+
+__device__ __forceinline__ int blk_swz(int row) { return ((row >> 1) & 3) ^ ((row >> 3) & 1); }
 
 __device__ __forceinline__ int64_t blk_offset(int64_t r, int64_t k, int64_t L) {
-    const int rr = (int)(r & 15);
-    return (((r >> 4) * (L >> 5) + (k >> 5)) << 9) + ((rr * 4 + ((int)((k >> 3) & 3) ^ swz4(rr))) << 3) + (k & 7);
+    const int rr = (int)(r % kBlkRows);
+    const int c = (int)((k >> 3) % kBlkChunks);
+    return ((r / kBlkRows) * (L / kBlkK) + k / kBlkK) * 512 + ((rr * kBlkChunks + (c ^ blk_swz(rr))) << 3) + (k & 7);
 }
 
 // A launch covers one problem (kernel-argument descriptor) or many (device

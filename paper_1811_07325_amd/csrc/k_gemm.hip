@@ -24,6 +24,30 @@ namespace stk {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// 16-bit operand flavour of the split leaf GEMMs: bfloat16 (BF16X3/X6) or
+// binary16 (FP16X3), both on the 16x16x32 matrix-core instruction.
+template <bool F16> struct Op16;
+template <> struct Op16<false> {
+    using T = bf16x8;
+    static __device__ __forceinline__ f32x4 mfma(T a, T b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Op16<true> {
+    using T = f16x8;
+    static __device__ __forceinline__ f32x4 mfma(T a, T b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// Factor that undoes the FP16X3 operand scaling 2^(e_A + e_B) (exact).
+__device__ __forceinline__ float unscale_of(const ProbDesc& d) {
+    if (!d.fp16) return 1.0f;
+    const int* ex = reinterpret_cast<const int*>(reinterpret_cast<const float*>(d.ws) + d.scale) + 2 * kScaleParts;
+    return ldexpf(1.0f, -(ex[0] + ex[1]));
+}
 
 constexpr int kGemmThreads = 256;
 constexpr int kGroupRows = 8;
@@ -198,8 +222,9 @@ struct SplitProducts<3> {
     }
 };
 
-template <class Src, int BM, int BN, int P>
+template <class Src, int BM, int BN, int P, bool F16>
 __global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t total_tiles) {
+    using VT = typename Op16<F16>::T;
     constexpr int BK = 32;
     constexpr int LDK = BK + 8;                   // uint16 per LDS row (80 B)
     constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
@@ -229,6 +254,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t tot
         if (d.depth == 0) { Cp = d.C; ldc = d.n; }
         else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
         const bool crop = d.depth == 0 && d.bounded0;
+        const float unscale = unscale_of(d);
         const int64_t m0 = tm * BM, n0 = tn * BN;
 
         f32x4 acc[TM][TN];
@@ -280,17 +306,17 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t tot
         for (int64_t kt = 0; kt < KT; ++kt) {
             const int buf = (int)(kt & 1);
             if (kt + 1 < KT) gload((kt + 1) * BK);
-            bf16x8 a[P][TM], b[P][TN];
+            VT a[P][TM], b[P][TN];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
-                    a[p][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
-                                                             &As[buf][p][(wm * WM + 16 * i + li) * LDK + 8 * lg]));
+                    a[p][i] = __builtin_bit_cast(VT, *reinterpret_cast<const uint4*>(
+                                                         &As[buf][p][(wm * WM + 16 * i + li) * LDK + 8 * lg]));
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
-                    b[p][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
-                                                             &Bs[buf][p][(wn * WN + 16 * j + li) * LDK + 8 * lg]));
+                    b[p][j] = __builtin_bit_cast(VT, *reinterpret_cast<const uint4*>(
+                                                         &Bs[buf][p][(wn * WN + 16 * j + li) * LDK + 8 * lg]));
             }
 #pragma unroll
             for (int q = 0; q < SplitProducts<P>::count; ++q)
@@ -298,8 +324,8 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t tot
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            a[SplitProducts<P>::a(q)][i], b[SplitProducts<P>::b(q)][j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = Op16<F16>::mfma(a[SplitProducts<P>::a(q)][i], b[SplitProducts<P>::b(q)][j],
+                                                    acc[i][j]);
             if (kt + 1 < KT) sstore(buf ^ 1);
             __syncthreads();
         }
@@ -312,7 +338,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t tot
                 for (int r = 0; r < 4; ++r) {
                     const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
                     const int64_t col = n0 + wn * WN + 16 * j + li;
-                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r];
+                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r] * unscale;
                 }
     }
 }
@@ -331,31 +357,18 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t tot
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// Configurations of the large-leaf kernel: block tile, wave grid, pipeline
-// depth (LDS stages).  STARK_BIG_CFG selects one at build time (tuning).
+// Configuration of the large-leaf kernel: block tile, wave grid and LDS
+// stages per precision.  Measured alternatives (same kernel): 4 waves of
+// 128 x 128, 256 x 128 or 128 x 128 tiles with 3-4 stages, and a 32 x 32 x 16
+// MFMA variant with 16-wide K steps and 3-5 stages were all slower for P = 2.
 template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int STAGES_>
 struct BigCfgT {
     static constexpr int BM = BM_, BN = BN_, WAVES_M = WAVES_M_, WAVES_N = WAVES_N_, STAGES = STAGES_;
     static constexpr int NW = WAVES_M * WAVES_N, NT = 64 * NW;
 };
-#ifndef STARK_BIG_CFG
-#define STARK_BIG_CFG 0
-#endif
 template <int P> struct BigCfg;
-#if STARK_BIG_CFG == 1      // 4 waves of 128 x 128
-template <> struct BigCfg<2> : BigCfgT<256, 256, 2, 2, 2> {};
-#elif STARK_BIG_CFG == 2    // 256 x 128, 8 waves of 64 x 64, three stages
-template <> struct BigCfg<2> : BigCfgT<256, 128, 4, 2, 3> {};
-#elif STARK_BIG_CFG == 3    // 128 x 128, 4 waves of 64 x 64, four stages
-template <> struct BigCfg<2> : BigCfgT<128, 128, 2, 2, 4> {};
-#elif STARK_BIG_CFG == 4    // 256 x 128, 4 waves of 128 x 64, three stages
-template <> struct BigCfg<2> : BigCfgT<256, 128, 2, 2, 3> {};
-#else                       // 256 x 256, 8 waves of 128 x 64, two stages
-template <> struct BigCfg<2> : BigCfgT<256, 256, 2, 4, 2> {};
-#endif
-template <> struct BigCfg<3> : BigCfgT<256, 128, 4, 2, 2> {};
-
-
+template <> struct BigCfg<2> : BigCfgT<256, 256, 2, 4, 2> {};   // 8 waves of 128 x 64, 128 KB LDS
+template <> struct BigCfg<3> : BigCfgT<256, 128, 4, 2, 2> {};   // 8 waves of 64 x 64, 144 KB LDS
 
 // Wait until at most N of this wave's vector-memory operations are pending.
 template <int N>
@@ -370,13 +383,14 @@ __device__ __forceinline__ void wait_vmcnt() {
 // bytes at LDS base + 16 * lane), STAGES deep: while step k runs on the
 // matrix cores the loads of steps k+1 .. k+STAGES-1 are in flight, with no
 // register staging.  The LDS image of a stage is [plane][row][4 chunks of 8
-// bf16], A rows first, then B rows, chunks swizzled by swz4 -- the same image
+// bf16], A rows first, then B rows, chunks swizzled by blk_swz -- the same image
 // as the operands' blocked layout in HBM (blk_offset), so each load copies a
 // contiguous 1 KB block.
 // ---------------------------------------------------------------------------
-template <class Src, int P>
+template <class Src, int P, bool F16>
 __global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_t total_tiles) {
     using Cfg = BigCfg<P>;
+    using VT = typename Op16<F16>::T;
     constexpr int BM = Cfg::BM, BN = Cfg::BN, NW = Cfg::NW, STAGES = Cfg::STAGES;
     constexpr int WAVES_N = Cfg::WAVES_N;
     constexpr int BK = 32, KC = BK / 8;                 // 16-byte chunks per row and plane
@@ -384,6 +398,7 @@ __global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_
     constexpr int UNITS = P * ROWS * KC;                // 16-byte units per stage
     constexpr int GA = BM / 16, GB = BN / 16;           // 16-row groups per side
     static_assert(GA % NW == 0 && GB % NW == 0, "groups must split evenly over the waves");
+    static_assert(kBlkRows == 16 && kBlkK == BK, "operand layout must match the K step");
     constexpr int LPS = P * (GA + GB) / NW;             // direct loads per lane per stage
     constexpr int WM = BM / Cfg::WAVES_M, WN = BN / WAVES_N, TM = WM / 16, TN = WN / 16;
     __shared__ __attribute__((aligned(16))) uint4 lds[STAGES][UNITS];
@@ -409,6 +424,7 @@ __global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_
         if (d.depth == 0) { Cp = d.C; ldc = d.n; }
         else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
         const bool crop = d.depth == 0 && d.bounded0;
+        const float unscale = unscale_of(d);
         const int64_t m0 = tm * BM, n0 = tn * BN;
 
         // One direct load of a wave moves one 1 KB block of the blocked
@@ -456,27 +472,26 @@ __global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_
             __syncthreads();     // every wave's part of step kt landed; step kt-1's reads are done
             if (kt + STAGES - 1 < KT) issue((int)((kt + STAGES - 1) % STAGES), (kt + STAGES - 1) * BK);
             const uint4* sl = lds[kt % STAGES];
-            bf16x8 b[P][TN];
+            VT b[P][TN];
 #pragma unroll
             for (int p = 0; p < P; ++p)
 #pragma unroll
                 for (int j = 0; j < TN; ++j) {
                     const int row = BM + wn * WN + 16 * j + li;
-                    b[p][j] = __builtin_bit_cast(bf16x8, sl[(p * ROWS + row) * KC + (lg ^ swz4(row))]);
+                    b[p][j] = __builtin_bit_cast(VT, sl[(p * ROWS + row) * KC + (lg ^ blk_swz(row))]);
                 }
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
                 const int row = wm * WM + 16 * i + li;
-                bf16x8 a[P];
+                VT a[P];
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    a[p] = __builtin_bit_cast(bf16x8, sl[(p * ROWS + row) * KC + (lg ^ swz4(row))]);
+                    a[p] = __builtin_bit_cast(VT, sl[(p * ROWS + row) * KC + (lg ^ blk_swz(row))]);
 #pragma unroll
                 for (int q = 0; q < SplitProducts<P>::count; ++q)
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            a[SplitProducts<P>::a(q)], b[SplitProducts<P>::b(q)][j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = Op16<F16>::mfma(a[SplitProducts<P>::a(q)], b[SplitProducts<P>::b(q)][j], acc[i][j]);
             }
         }
         __syncthreads();         // the next tile's first loads overwrite the stages
@@ -489,10 +504,11 @@ __global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_
                 for (int r = 0; r < 4; ++r) {
                     const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
                     const int64_t col = n0 + wn * WN + 16 * j + li;
-                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r];
+                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r] * unscale;
                 }
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // Host side.
@@ -502,38 +518,21 @@ static hipError_t launch_f32_t(const Src& s, int64_t tiles, int grid, hipStream_
     hipLaunchKernelGGL((k_gemm_f32<Src, BM, BN>), dim3(grid), dim3(kGemmThreads), 0, st, s, tiles);
     return hipGetLastError();
 }
-template <class Src, int BM, int BN, int P>
+template <class Src, int BM, int BN, int P, bool F16>
 static hipError_t launch_bf16_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemm_bf16<Src, BM, BN, P>), dim3(grid), dim3(kGemmThreads), 0, st, s, tiles);
+    hipLaunchKernelGGL((k_gemm_bf16<Src, BM, BN, P, F16>), dim3(grid), dim3(kGemmThreads), 0, st, s, tiles);
     return hipGetLastError();
 }
-
-template <class Src, int P>
+template <class Src, int P, bool F16>
 static hipError_t launch_bf16_big_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemm_bf16_big<Src, P>), dim3(grid), dim3(BigCfg<P>::NT), 0, st, s, tiles);
+    hipLaunchKernelGGL((k_gemm_bf16_big<Src, P, F16>), dim3(grid), dim3(BigCfg<P>::NT), 0, st, s, tiles);
     return hipGetLastError();
 }
 
-template <int P>
-static int occ_bf16_big() {
+template <class K>
+static int occupancy(K kernel, int threads) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16_big<OneProb, P>, BigCfg<P>::NT, 0) != hipSuccess)
-        return 1;
-    return n > 0 ? n : 1;
-}
-
-template <int BM, int BN>
-static int occ_f32() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_f32<OneProb, BM, BN>, kGemmThreads, 0) != hipSuccess)
-        return 1;
-    return n > 0 ? n : 1;
-}
-template <int BM, int BN, int P>
-static int occ_bf16() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_bf16<OneProb, BM, BN, P>, kGemmThreads, 0) != hipSuccess)
-        return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }
 
@@ -545,26 +544,38 @@ int64_t gemm_tiles_per_leaf(int planes, int tile, int64_t leaf) {
 }
 
 int gemm_blocks_per_cu(int planes, int tile) {
-    // Occupancy does not depend on the descriptor source.
-    if (planes == 0) return tile == 128 ? occ_f32<128, 128>() : occ_f32<64, 64>();
-    if (tile == 256) return planes == 2 ? occ_bf16_big<2>() : occ_bf16_big<3>();
-    if (planes == 2) return tile == 128 ? occ_bf16<128, 128, 2>() : occ_bf16<64, 64, 2>();
-    return tile == 128 ? occ_bf16<128, 128, 3>() : occ_bf16<64, 64, 3>();
+    // Occupancy does not depend on the descriptor source or the 16-bit flavour.
+    if (planes == 0)
+        return tile == 128 ? occupancy(k_gemm_f32<OneProb, 128, 128>, kGemmThreads)
+                           : occupancy(k_gemm_f32<OneProb, 64, 64>, kGemmThreads);
+    if (tile == 256)
+        return planes == 2 ? occupancy(k_gemm_bf16_big<OneProb, 2, false>, BigCfg<2>::NT)
+                           : occupancy(k_gemm_bf16_big<OneProb, 3, false>, BigCfg<3>::NT);
+    if (planes == 2)
+        return tile == 128 ? occupancy(k_gemm_bf16<OneProb, 128, 128, 2, false>, kGemmThreads)
+                           : occupancy(k_gemm_bf16<OneProb, 64, 64, 2, false>, kGemmThreads);
+    return tile == 128 ? occupancy(k_gemm_bf16<OneProb, 128, 128, 3, false>, kGemmThreads)
+                       : occupancy(k_gemm_bf16<OneProb, 64, 64, 3, false>, kGemmThreads);
 }
 
 template <class Src>
-hipError_t launch_gemm(const Src& s, int planes, int tile, int64_t tiles, int grid, hipStream_t st) {
+hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t tiles, int grid, hipStream_t st) {
     if (planes == 0) return tile == 128 ? launch_f32_t<Src, 128, 128>(s, tiles, grid, st)
                                         : launch_f32_t<Src, 64, 64>(s, tiles, grid, st);
-    if (tile == 256) return planes == 2 ? launch_bf16_big_t<Src, 2>(s, tiles, grid, st)
-                                        : launch_bf16_big_t<Src, 3>(s, tiles, grid, st);
-    if (planes == 2) return tile == 128 ? launch_bf16_t<Src, 128, 128, 2>(s, tiles, grid, st)
-                                        : launch_bf16_t<Src, 64, 64, 2>(s, tiles, grid, st);
-    return tile == 128 ? launch_bf16_t<Src, 128, 128, 3>(s, tiles, grid, st)
-                       : launch_bf16_t<Src, 64, 64, 3>(s, tiles, grid, st);
+    if (f16) {   // FP16X3: two binary16 planes
+        if (tile == 256) return launch_bf16_big_t<Src, 2, true>(s, tiles, grid, st);
+        return tile == 128 ? launch_bf16_t<Src, 128, 128, 2, true>(s, tiles, grid, st)
+                           : launch_bf16_t<Src, 64, 64, 2, true>(s, tiles, grid, st);
+    }
+    if (tile == 256) return planes == 2 ? launch_bf16_big_t<Src, 2, false>(s, tiles, grid, st)
+                                        : launch_bf16_big_t<Src, 3, false>(s, tiles, grid, st);
+    if (planes == 2) return tile == 128 ? launch_bf16_t<Src, 128, 128, 2, false>(s, tiles, grid, st)
+                                        : launch_bf16_t<Src, 64, 64, 2, false>(s, tiles, grid, st);
+    return tile == 128 ? launch_bf16_t<Src, 128, 128, 3, false>(s, tiles, grid, st)
+                       : launch_bf16_t<Src, 64, 64, 3, false>(s, tiles, grid, st);
 }
 
-template hipError_t launch_gemm<OneProb>(const OneProb&, int, int, int64_t, int, hipStream_t);
-template hipError_t launch_gemm<TableProb>(const TableProb&, int, int, int64_t, int, hipStream_t);
+template hipError_t launch_gemm<OneProb>(const OneProb&, int, int, bool, int64_t, int, hipStream_t);
+template hipError_t launch_gemm<TableProb>(const TableProb&, int, int, bool, int64_t, int, hipStream_t);
 
 }  // namespace stk

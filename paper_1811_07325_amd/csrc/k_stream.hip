@@ -157,6 +157,13 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
     __bf16 b = (__bf16)x;
     return __builtin_bit_cast(uint16_t, b);
 }
+__device__ __forceinline__ uint16_t f16_bits(float x) {
+    _Float16 h = (_Float16)x;     // v_cvt_f16_f32: round to nearest even
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_value(uint16_t b) {
+    return (float)__builtin_bit_cast(_Float16, b);
+}
 __device__ __forceinline__ float bf16_value(uint16_t b) {
     return __uint_as_float(((uint32_t)b) << 16);
 }
@@ -231,17 +238,23 @@ __device__ __forceinline__ void split_values(const float* X, int64_t ld, int64_t
     }
 }
 
-// Split 4 values into P planes: planes[p] holds 4 bf16 packed in 8 bytes.
+// Split 4 values into P planes: planes[p] holds 4 16-bit terms packed in 8
+// bytes -- bfloat16, or (fp16) binary16 of the values times `scale` (a power
+// of two, so the scaling is exact).
 template <int P>
-__device__ __forceinline__ void split4(const float (&x)[4], uint2 (&planes)[P]) {
+__device__ __forceinline__ void split4(const float (&x)[4], uint2 (&planes)[P], bool fp16, float scale) {
     float r[4] = {x[0], x[1], x[2], x[3]};
+    if (fp16) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] *= scale;
+    }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         uint16_t b[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            b[e] = bf16_bits(r[e]);
-            r[e] = r[e] - bf16_value(b[e]);
+            b[e] = fp16 ? f16_bits(r[e]) : bf16_bits(r[e]);
+            r[e] = r[e] - (fp16 ? f16_value(b[e]) : bf16_value(b[e]));
         }
         planes[p] = make_uint2((uint32_t)b[0] | ((uint32_t)b[1] << 16), (uint32_t)b[2] | ((uint32_t)b[3] << 16));
     }
@@ -265,6 +278,10 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
 
     float v[NOUT][4][4];
     split_values<NOUT>(X, ld, d.n, L, R0 + ri, C0 + ci, side, bounded, v);
+    const bool fp16 = d.fp16 != 0;
+    const float scale =
+        fp16 ? ldexpf(1.0f, reinterpret_cast<const int*>(reinterpret_cast<const float*>(d.ws) + d.scale)[2 * kScaleParts + side])
+             : 1.0f;
 
     if (side == 0) {
 #pragma unroll
@@ -272,7 +289,7 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 uint2 pl[P];
-                split4<P>(v[o][i], pl);
+                split4<P>(v[o][i], pl, fp16, scale);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
                     *reinterpret_cast<uint2*>(base + ((int64_t)o * P + p) * LL + blk_offset(R0 + ri + i, C0 + ci, L)) =
@@ -292,7 +309,7 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
             for (int e = 0; e < 4; ++e) {
                 const float col[4] = {v[o0 + oo][0][e], v[o0 + oo][1][e], v[o0 + oo][2][e], v[o0 + oo][3][e]};
                 uint2 pl[P];
-                split4<P>(col, pl);
+                split4<P>(col, pl, fp16, scale);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
                     *reinterpret_cast<uint2*>(lds + (oo * P + p) * TILE_U16 + (ci + e) * kSplitLdsRow + ri) = pl[p];
@@ -333,6 +350,60 @@ __global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
     const bool bounded = d.bounded0 && d.depth <= 1;
     if (d.depth == 0) split_body<1, P>(d, side, node, tile, bounded, lds);
     else split_body<7, P>(d, side, node, tile, bounded, lds);
+}
+
+// ---------------------------------------------------------------------------
+// FP16X3 scaling.  k_absmax: kScaleParts blocks per matrix take the largest
+// magnitude of a contiguous chunk of A (grid.y = 0) or B (1).  k_scale_exp:
+// one block per problem reduces the partial maxima and stores the exponents
+// e = 14 - depth - E, with max = m 2^E (m in [0.5, 1)): multiplying by 2^e
+// keeps every leaf operand (at most 2^depth max) below 2^14.
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(kStreamThreads) void k_absmax(Src src) {
+    __shared__ float part[kStreamThreads];
+    int64_t local;
+    const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
+    const int side = blockIdx.y;
+    const float* X = side ? d.B : d.A;
+    const int64_t count = d.n * d.n;
+    const int64_t chunk = (count + kScaleParts - 1) / kScaleParts;
+    const int64_t lo = local * chunk;
+    const int64_t hi = lo + chunk < count ? lo + chunk : count;
+    float m = 0.0f;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kStreamThreads) m = fmaxf(m, fabsf(X[i]));
+    part[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kStreamThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] = fmaxf(part[threadIdx.x], part[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) reinterpret_cast<float*>(d.ws)[d.scale + side * kScaleParts + local] = part[0];
+}
+
+template <class Src>
+__global__ __launch_bounds__(kScaleParts) void k_scale_exp(Src src) {
+    __shared__ float part[2][kScaleParts];
+    int64_t local;
+    const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
+    const float* pm = reinterpret_cast<const float*>(d.ws) + d.scale;
+    part[0][threadIdx.x] = pm[threadIdx.x];
+    part[1][threadIdx.x] = pm[kScaleParts + threadIdx.x];
+    __syncthreads();
+    for (int w = kScaleParts / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            part[0][threadIdx.x] = fmaxf(part[0][threadIdx.x], part[0][threadIdx.x + w]);
+            part[1][threadIdx.x] = fmaxf(part[1][threadIdx.x], part[1][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) {
+        const float m = part[threadIdx.x][0];
+        int E = 0;
+        if (m > 0.0f) frexpf(m, &E);
+        reinterpret_cast<int*>(reinterpret_cast<float*>(d.ws) + d.scale)[2 * kScaleParts + threadIdx.x] =
+            m > 0.0f ? 14 - d.depth - E : 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -425,6 +496,16 @@ hipError_t launch_pad(const Src& s, int64_t blocks, hipStream_t st) {
     return hipGetLastError();
 }
 template <class Src>
+hipError_t launch_absmax(const Src& s, int64_t blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_absmax<Src>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s);
+    return hipGetLastError();
+}
+template <class Src>
+hipError_t launch_scale_exp(const Src& s, int64_t blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_scale_exp<Src>), dim3((unsigned)blocks), dim3(kScaleParts), 0, st, s);
+    return hipGetLastError();
+}
+template <class Src>
 hipError_t launch_divide(const Src& s, int level, int64_t blocks, hipStream_t st) {
     hipLaunchKernelGGL((k_divide<Src>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s, level);
     return hipGetLastError();
@@ -445,6 +526,10 @@ hipError_t launch_combine(const Src& s, int level, int64_t blocks, hipStream_t s
 
 template hipError_t launch_pad<OneProb>(const OneProb&, int64_t, hipStream_t);
 template hipError_t launch_pad<TableProb>(const TableProb&, int64_t, hipStream_t);
+template hipError_t launch_absmax<OneProb>(const OneProb&, int64_t, hipStream_t);
+template hipError_t launch_absmax<TableProb>(const TableProb&, int64_t, hipStream_t);
+template hipError_t launch_scale_exp<OneProb>(const OneProb&, int64_t, hipStream_t);
+template hipError_t launch_scale_exp<TableProb>(const TableProb&, int64_t, hipStream_t);
 template hipError_t launch_divide<OneProb>(const OneProb&, int, int64_t, hipStream_t);
 template hipError_t launch_divide<TableProb>(const TableProb&, int, int64_t, hipStream_t);
 template hipError_t launch_split<OneProb>(const OneProb&, int, int64_t, hipStream_t);

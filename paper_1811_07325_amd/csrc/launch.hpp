@@ -14,10 +14,15 @@ int64_t blocks_split(const ProbDesc& d);
 int64_t blocks_combine(const ProbDesc& d, int level);
 
 template <class Src> hipError_t launch_pad(const Src& s, int64_t blocks, hipStream_t st);
+// FP16X3 scaling: partial maxima (kScaleParts blocks per problem), then the
+// exponents (1 block per problem).
+template <class Src> hipError_t launch_absmax(const Src& s, int64_t blocks, hipStream_t st);
+template <class Src> hipError_t launch_scale_exp(const Src& s, int64_t blocks, hipStream_t st);
 template <class Src> hipError_t launch_divide(const Src& s, int level, int64_t blocks, hipStream_t st);
 template <class Src> hipError_t launch_split(const Src& s, int planes, int64_t blocks, hipStream_t st);
 template <class Src> hipError_t launch_combine(const Src& s, int level, int64_t blocks, hipStream_t st);
-template <class Src> hipError_t launch_gemm(const Src& s, int planes, int tile, int64_t tiles, int grid, hipStream_t st);
+// f16: the two planes are binary16 (FP16X3) rather than bfloat16.
+template <class Src> hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t tiles, int grid, hipStream_t st);
 
 // Tiles of one leaf of edge `leaf` for the GEMM variant (planes, tile class).
 int64_t gemm_tiles_per_leaf(int planes, int tile, int64_t leaf);

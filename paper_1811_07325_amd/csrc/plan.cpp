@@ -50,6 +50,7 @@ int planes_for(int precision) {
         case STARK_FP32: return 0;
         case STARK_BF16X3: return 2;
         case STARK_BF16X6: return 3;
+        case STARK_FP16X3: return 2;
         default: return -1;
     }
 }
@@ -86,6 +87,12 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
     }
     const int64_t N = p.np * p.np;
     int64_t off = 0;
+    if (precision == STARK_FP16X3) {
+        // 2 x kScaleParts partial maxima, then e_A, e_B (kept apart from the
+        // regions the combine outputs reuse)
+        p.scale = off;
+        off = align256(off + (2 * kScaleParts + 2) * 4);
+    }
     if (depth == 0) {
         if (planes == 0) {
             if (p.padded) {
@@ -118,7 +125,7 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
     const int64_t dead_end = off;
     p.leaf_m = off;
     off = align256(off + pow7(depth) * p.leaf * p.leaf * 4);
-    int64_t c = 0;
+    int64_t c = p.scale >= 0 ? align256(p.scale + (2 * kScaleParts + 2) * 4) : 0;
     for (int l = depth - 1; l >= 1; --l) {
         const int64_t m = p.np >> l;
         p.comb[l] = c;
@@ -153,6 +160,8 @@ ProbDesc make_desc(const Plan& p, const float* A, const float* B, float* C, void
     d.leaf_m = p.leaf_m >= 0 ? p.leaf_m / 4 : -1;
     d.pad_a = p.pad_a >= 0 ? p.pad_a / 4 : -1;
     d.pad_b = p.pad_b >= 0 ? p.pad_b / 4 : -1;
+    d.fp16 = p.precision == STARK_FP16X3 ? 1 : 0;
+    d.scale = p.scale >= 0 ? p.scale / 4 : -1;
     return d;
 }
 

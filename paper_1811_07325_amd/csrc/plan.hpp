@@ -25,6 +25,7 @@ struct Plan {
     int64_t leaf_a = -1, leaf_b = -1, leaf_m = -1;
     int64_t comb[STK_MAXD];
     int64_t pad_a = -1, pad_b = -1;
+    int64_t scale = -1;   // FP16X3 scale region
     size_t bytes = 0;
     int fp32_levels = 0;  // binary32 divide levels launched (0 .. depth)
 };

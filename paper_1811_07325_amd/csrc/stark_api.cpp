@@ -49,11 +49,15 @@ stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned
         if (p.pad_a >= 0) STK_HIP(launch_pad(src, blocks_pad(d), st));
         for (int l = 0; l < p.fp32_levels; ++l)
             STK_HIP(launch_divide(src, l, blocks_divide(d, l), st));
+        if (p.scale >= 0) {
+            STK_HIP(launch_absmax(src, kScaleParts, st));
+            STK_HIP(launch_scale_exp(src, 1, st));
+        }
         if (p.planes > 0) STK_HIP(launch_split(src, p.planes, blocks_split(d), st));
     }
     if (mask & STARK_PHASE_LEAF) {
         const int64_t tiles = pow7(p.depth) * gemm_tiles_per_leaf(p.planes, p.tile, p.leaf);
-        STK_HIP(launch_gemm(src, p.planes, p.tile, tiles, gemm_grid(ctx, p.planes, p.tile, tiles), st));
+        STK_HIP(launch_gemm(src, p.planes, p.tile, d.fp16 != 0, tiles, gemm_grid(ctx, p.planes, p.tile, tiles), st));
     }
     if (mask & STARK_PHASE_COMBINE) {
         for (int l = p.depth - 1; l >= 0; --l)
@@ -196,6 +200,7 @@ stark_status stark_plan_info(int64_t n, int depth, stark_precision prec, stark_p
     out->pad_b = p.pad_b;
     out->bytes = p.bytes;
     out->gemm_tile = p.tile;
+    out->scale = p.scale;
     return STARK_OK;
 }
 

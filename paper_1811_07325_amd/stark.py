@@ -29,7 +29,8 @@ STARK_EUNSUPPORTED = -6
 STARK_FP32 = 0
 STARK_BF16X3 = 1
 STARK_BF16X6 = 2
-PRECISIONS = {"fp32": STARK_FP32, "bf16x3": STARK_BF16X3, "bf16x6": STARK_BF16X6}
+STARK_FP16X3 = 3
+PRECISIONS = {"fp32": STARK_FP32, "bf16x3": STARK_BF16X3, "bf16x6": STARK_BF16X6, "fp16x3": STARK_FP16X3}
 
 STARK_DEPTH_AUTO = -1
 STARK_MAX_DEPTH = 8
@@ -83,7 +84,7 @@ class stark_plan_desc(ctypes.Structure):
                 ("leaf_a", ctypes.c_int64), ("leaf_b", ctypes.c_int64), ("leaf_m", ctypes.c_int64),
                 ("comb", ctypes.c_int64 * STARK_MAX_DEPTH),
                 ("pad_a", ctypes.c_int64), ("pad_b", ctypes.c_int64), ("bytes", ctypes.c_size_t),
-                ("gemm_tile", ctypes.c_int)]
+                ("gemm_tile", ctypes.c_int), ("scale", ctypes.c_int64)]
 
 
 def _load() -> ctypes.CDLL:

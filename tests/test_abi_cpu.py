@@ -45,19 +45,19 @@ def _regions(d, depth):
         if d.div_a[l] >= 0:
             regs.append(("div_a%d" % l, d.div_a[l]))
             regs.append(("div_b%d" % l, d.div_b[l]))
-    for name in ("leaf_a", "leaf_b", "leaf_m", "pad_a", "pad_b"):
+    for name in ("leaf_a", "leaf_b", "leaf_m", "pad_a", "pad_b", "scale"):
         if getattr(d, name) >= 0:
             regs.append((name, getattr(d, name)))
     return sorted(regs, key=lambda r: r[1])
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 @pytest.mark.parametrize("n,depth", [(512, 2), (4096, 3), (1000, 2), (384, 1), (16384, 4), (65, 0), (3000, 3)])
 def test_plan_layout(S, n, depth, prec):
     d = S.stark_plan_info(n, depth, prec)
     np_ = d.n_pad
     assert np_ >= n and np_ % (64 << depth) == 0 and d.leaf == np_ >> depth
-    planes = {0: 0, 1: 2, 2: 3}[prec]
+    planes = {0: 0, 1: 2, 2: 3, 3: 2}[prec]
     assert d.planes == planes
     L, h = d.leaf, None
     # sizes of every region, from the layout rules
@@ -81,6 +81,10 @@ def test_plan_layout(S, n, depth, prec):
     if d.pad_a >= 0:
         assert depth == 0 and planes == 0 and np_ != n
         size["pad_a"] = size["pad_b"] = np_ * np_ * 4
+    if prec == 3:
+        size["scale"] = (2 * 256 + 2) * 4
+    else:
+        assert d.scale == -1
     regs = _regions(d, depth)
     assert {r[0] for r in regs} == set(size)
     # live regions are disjoint and inside the workspace
@@ -100,6 +104,8 @@ def test_plan_layout(S, n, depth, prec):
         assert a1 <= b0
     for a0, a1 in ends:
         assert a1 <= d.leaf_m
+        if d.scale >= 0:       # the combine outputs never overwrite the scale region
+            assert a0 >= d.scale + size["scale"]
 
 
 def test_workspace_formula_fp32(S):

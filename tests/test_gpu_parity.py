@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2}
+PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "fp16x3": 3}
 
 
 @pytest.fixture(scope="module")
@@ -75,7 +75,8 @@ INT_CASES = [(512, 2, "fp32"), (512, 2, "bf16x3"), (512, 2, "bf16x6"),
              (512, 0, "fp32"), (512, 1, "fp32"), (512, 3, "fp32"), (512, 0, "bf16x3"), (512, 3, "bf16x3"),
              (1000, 2, "fp32"), (1000, 2, "bf16x3"), (300, 1, "fp32"), (300, 1, "bf16x3"),
              (65, 0, "fp32"), (65, 0, "bf16x3"), (200, 2, "fp32"), (200, 2, "bf16x6"), (384, 1, "bf16x3"),
-             (129, 0, "fp32"), (250, 1, "bf16x6"), (1, 0, "fp32"), (2, 0, "bf16x3"), (63, 0, "bf16x6")]
+             (129, 0, "fp32"), (250, 1, "bf16x6"), (1, 0, "fp32"), (2, 0, "bf16x3"), (63, 0, "bf16x6"),
+             (512, 2, "fp16x3"), (1000, 2, "fp16x3"), (65, 0, "fp16x3"), (300, 1, "fp16x3"), (512, 3, "fp16x3")]
 
 
 @pytest.mark.parametrize("n,depth,prec", INT_CASES)
@@ -91,7 +92,7 @@ def test_integer_inputs_bit_exact(S, ctx, n, depth, prec):
 
 
 @pytest.mark.parametrize("n,depth,prec", [(4096, 1, "bf16x3"), (4096, 0, "bf16x6"), (4096, 1, "bf16x6"),
-                                          (4032, 1, "bf16x3")])
+                                          (4032, 1, "bf16x3"), (4096, 1, "fp16x3")])
 def test_integer_inputs_bit_exact_large_tiles(S, ctx_big, n, depth, prec):
     """Leaves wide enough for the 256-wide tile class."""
     print(f"case n={n} depth={depth} prec={prec}", flush=True)
@@ -109,7 +110,8 @@ def test_integer_inputs_bit_exact_large_tiles(S, ctx_big, n, depth, prec):
 # ---------------------------------------------------------------------------
 FLOAT_CASES = [(512, 2, "fp32"), (512, 2, "bf16x3"), (512, 2, "bf16x6"), (256, 1, "fp32"),
                (384, 1, "bf16x3"), (1000, 2, "fp32"), (1000, 2, "bf16x3"), (512, 0, "fp32"),
-               (512, 0, "bf16x3"), (512, 3, "bf16x6")]
+               (512, 0, "bf16x3"), (512, 3, "bf16x6"), (512, 2, "fp16x3"), (1000, 2, "fp16x3"),
+               (512, 0, "fp16x3"), (384, 1, "fp16x3")]
 
 
 @pytest.mark.parametrize("n,depth,prec", FLOAT_CASES)
@@ -171,14 +173,17 @@ def test_divide_levels_bit_exact(S, ctx, ws, n):
         assert np.array_equal(gb1[c], T1[sB5]), c
 
 
-def unblock(x, L):
-    """Blocked bf16 plane layout of the library (1 KB blocks of 16 rows x 32 k,
-    block-row-major; chunk c of row r stored at c ^ swz(r)) -> row-major."""
+def unblock(x, L, BR=16):
+    """Blocked bf16 plane layout of the library (1 KB blocks of BR rows x
+    512/BR k, block-row-major; chunk c of row r stored at c ^ swz(r)) ->
+    row-major."""
+    BK = 512 // BR
+    CR = BK // 8
     r = np.arange(L)[:, None]
     k = np.arange(L)[None, :]
-    rr = r & 15
-    swz = ((rr >> 1) & 3) ^ ((rr >> 3) & 1)
-    off = (((r >> 4) * (L >> 5) + (k >> 5)) << 9) + ((rr * 4 + (((k >> 3) & 3) ^ swz)) << 3) + (k & 7)
+    rr = r % BR
+    swz = (((rr >> 1) & 3) ^ ((rr >> 3) & 1)) if BR == 16 else (((rr >> 2) ^ (rr >> 3)) & 1)
+    off = ((r // BR) * (L // BK) + k // BK) * 512 + ((rr * CR + (((k >> 3) % CR) ^ swz)) << 3) + (k & 7)
     return x[..., off]
 
 
@@ -212,6 +217,51 @@ def test_split_leaf_operands_bit_exact(S, ctx, ws, prec, depth, n):
         assert np.array_equal(ga[i], oracle.split_bf16(Xs[i], P)), i
         # B side is stored transposed: plane[j][k] = split(T)[k][j]
         assert np.array_equal(gb[i], oracle.split_bf16(Ys[i], P).transpose(0, 2, 1)), i
+
+
+@pytest.mark.parametrize("depth,n,scale_a", [(1, 256, 1.0), (2, 256, 1e-3), (0, 128, 300.0), (1, 200, 1.0)])
+def test_fp16_split_and_scale_bit_exact(S, ctx, ws, depth, n, scale_a):
+    """FP16X3: the per-matrix exponents and the binary16 planes of every leaf."""
+    A = (inputs.normal(n, 15) * np.float32(scale_a)).astype(np.float32)
+    B = inputs.normal(n, 16)
+    dA, dB = dev(A), dev(B)
+    dC = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, 3, S.STARK_PHASE_DIVIDE, None)
+    torch.cuda.synchronize()
+    d = S.stark_plan_info(n, depth, 3)
+    np_, L = d.n_pad, d.leaf
+    ex = ws_view(ws, d.scale + 4 * 512, 2, np.int32)
+    ea, eb = oracle.f16_scale_exp(A, depth), oracle.f16_scale_exp(B, depth)
+    assert (int(ex[0]), int(ex[1])) == (ea, eb)
+    Ap = np.zeros((np_, np_), np.float32); Ap[:n, :n] = A
+    Bp = np.zeros((np_, np_), np.float32); Bp[:n, :n] = B
+    Xs, Ys = [Ap], [Bp]
+    for _ in range(depth):
+        nx, ny = [], []
+        for X, Y in zip(Xs, Ys):
+            Sx, Ty = oracle.divide_f32(X, Y)
+            nx.extend(Sx)
+            ny.extend(Ty)
+        Xs, Ys = nx, ny
+    nleaf = 7 ** depth
+    f16 = lambda b: b.view(np.float16).astype(np.float32)
+    ga = f16(unblock(ws_view(ws, d.leaf_a, nleaf * 2 * L * L, np.uint16).reshape(nleaf, 2, L * L), L))
+    gb = f16(unblock(ws_view(ws, d.leaf_b, nleaf * 2 * L * L, np.uint16).reshape(nleaf, 2, L * L), L))
+    for i in range(nleaf):
+        assert np.array_equal(ga[i], oracle.split_f16(Xs[i], ea)), i
+        assert np.array_equal(gb[i], oracle.split_f16(Ys[i], eb).transpose(0, 2, 1)), i
+
+
+def test_fp16x3_wide_range_inputs_match_model(S, ctx):
+    """Operands far from unit scale: the power-of-two scaling keeps FP16X3 on the model."""
+    n, depth = 512, 2
+    A = (inputs.normal(n, 17) * np.float32(3e4)).astype(np.float32)
+    B = (inputs.normal(n, 18) * np.float32(2e-6)).astype(np.float32)
+    C = run(S, ctx, A, B, depth, "fp16x3")
+    model = oracle.strassen_model_f32(A, B, depth, "fp16x3", oracle.padded_size(n, depth, 64))
+    exact = oracle.gemm_f64(A, B)
+    assert rel_f(C, model) <= 4 * 2.0 ** -24 * np.sqrt(128) * 4
+    assert rel_f(C, exact) < 5e-6
 
 
 def test_combine_levels_bit_exact(S, ctx, ws):

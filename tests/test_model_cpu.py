@@ -8,7 +8,7 @@ import oracle
 from paper_1811_07325_amd import inputs
 
 
-@pytest.mark.parametrize("mode", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3", "bf16x6", "fp16x3"])
 @pytest.mark.parametrize("n,depth", [(16, 0), (16, 2), (13, 1), (40, 3)])
 def test_model_exact_on_small_integers(mode, n, depth):
     A = inputs.integers(n, 1)
@@ -69,3 +69,33 @@ def test_philox_normal_moments():
     assert np.all(np.abs(x) <= 6.0)
     # exactly reproducible: value * 2^24 is an integer
     assert np.array_equal(x * 2.0 ** 24, np.round(x * 2.0 ** 24))
+
+
+def test_f16_rounding_matches_library():
+    """binary16 rounding of the oracle against numpy's float16 conversion."""
+    x = inputs.normal(300, 19).ravel() * np.float32(40)
+    x = np.concatenate([x, np.float32([0.0, 65504.0, 65519.0, 1e-7, 6e-8, 2.0 ** -25, 1 + 2.0 ** -11,
+                                       1 + 3 * 2.0 ** -11, 1.5 * 2.0 ** -24, 2.5 * 2.0 ** -24, -3.0e-5])])
+    planes = oracle.split_f16(x, 0)
+    assert np.array_equal(planes[0], x.astype(np.float16).astype(np.float32))
+    assert np.array_equal(planes[1], (x - planes[0]).astype(np.float16).astype(np.float32))
+
+
+def test_f16_scale_exponent():
+    A = inputs.normal(64, 20)
+    m = float(np.max(np.abs(A)))
+    E = int(np.frexp(m)[1])
+    for depth in range(4):
+        e = oracle.f16_scale_exp(A, depth)
+        assert e == 14 - depth - E
+        assert m * 2.0 ** e * 2 ** depth < 2 ** 14
+    assert oracle.f16_scale_exp(np.zeros((4, 4), np.float32), 2) == 0
+
+
+def test_fp16x3_keeps_binary32_accuracy():
+    A = inputs.normal(64, 21)
+    B = inputs.normal(64, 22)
+    exact = oracle.gemm_f64(A, B)
+    e16 = oracle.rel_frobenius(oracle.strassen_model_f32(A, B, 0, "fp16x3"), exact)
+    e3 = oracle.rel_frobenius(oracle.strassen_model_f32(A, B, 0, "bf16x3"), exact)
+    assert e16 < 1e-6 < e3
