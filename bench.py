@@ -52,8 +52,11 @@ def parse():
     p.add_argument("--no-serving", action="store_true")
     p.add_argument("--serving-requests", type=int, default=2000)
     p.add_argument("--rows", type=int, default=256, help="sampled rows for the error check")
-    p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "leaf_gemm_traffic.json"),
-                   help="HBM traffic of the leaf GEMM measured by rocprofv3 counters (JSON), if present")
+    p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "leaf_gemm_traffic.txt"),
+                   help="HBM traffic of the leaf GEMM measured by rocprofv3 counters, if present")
+    p.add_argument("--phase-reps", type=int, default=5, help="repetitions of each phase for the live roofline")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB device-to-device elementwise copy (counter calibration) and exit")
     return p.parse_args()
 
 
@@ -113,12 +116,51 @@ def run_serving(S, count: int, seed: int = 5, budget: int = 96 << 30, slots: int
     return out
 
 
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration(torch) -> int:
+    """A streaming kernel of known traffic: y = -x over 1 GiB of binary32
+    (reads 1 GiB, writes 1 GiB), three times.  Hardware counters read on it
+    give the factor that turns the same counters read on other kernels into
+    bytes."""
+    x = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "kernel": "neg", "reps": 3}), flush=True)
+    return 0
+
+
+def read_traffic(path: str, key: str):
+    """Leaf-GEMM HBM bytes per launch (fetch + write) recorded for `key`, or
+    None when absent or taken on another version of the GEMM source."""
+    if not os.path.exists(path):
+        return None
+    from paper_1811_07325_amd.profsum import source_digest
+    digest = None
+    for line in open(path):
+        f = line.split()
+        if line.startswith("# source_sha256"):
+            digest = f[2]
+        elif f and not line.startswith("#") and f[0] == key:
+            if digest != source_digest():
+                log(f"traffic for {key} was taken on another GEMM source: not reported")
+                return None
+            return float(f[1]) + float(f[2])
+    return None
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         return 2
     import torch
+
+    if args.copy_calibration:
+        return copy_calibration(torch)
 
     from paper_1811_07325_amd import inputs
     from paper_1811_07325_amd import stark as S
@@ -196,7 +238,7 @@ def main() -> int:
     # -- roofline of the dominant kernel (leaf GEMM), timed live --------------
     plan = S.stark_plan_info(n, depth, prec)
     S.stark_gemm_phases(ctx, A, B, C, n, depth, prec, S.STARK_PHASE_DIVIDE, st)
-    reps = 5
+    reps = max(1, args.phase_reps)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     e[0].record(st)
     for _ in range(reps):
@@ -219,13 +261,7 @@ def main() -> int:
     leaf_flops = 2.0 * L ** 3 * nleaf * prods        # matrix-core work of one launch
     unit_peak = PEAK["fp32"] if planes == 0 else PEAK["bf16"]
     achieved = leaf_flops / (t_leaf * 1e-3)
-    traffic = None
-    if os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            tr = json.load(f)
-        key = f"n{n}_d{depth}_{args.precision}"
-        if key in tr:
-            traffic = tr[key]
+    traffic = read_traffic(args.traffic, f"n{n}_d{depth}_{args.precision}")
     # divide (+ split) and combine: algorithmic bytes, see the planner
     Np = plan.n_pad ** 2
     div_bytes = split_bytes = comb_bytes = 0.0
