@@ -17,7 +17,8 @@
  *
  * Conventions for every call:
  *   - Matrices are device pointers to row-major binary32 with leading
- *     dimension n (n x n, contiguous).  The caller owns them; the library
+ *     dimension n (n x n, contiguous), 16-byte aligned (EINVAL otherwise;
+ *     allocator results always are).  The caller owns them; the library
  *     never frees caller memory.  A, B, C must stay valid until the work
  *     enqueued on `stream` has completed.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
@@ -100,8 +101,8 @@ int stark_max_depth(int64_t n);
 /* C = A * B with `depth` Strassen levels (Algorithm 1; depth 0 is the
  * classical product on the same leaf kernels).  depth = STARK_DEPTH_AUTO asks
  * the autotuner (which may also run measurements on `stream` the first time a
- * size is seen).  C must not overlap A or B.  Errors: EINVAL (null pointer,
- * n <= 0, depth out of range, overlap), ENOMEM (caller workspace too small),
+ * size is seen).  C must not overlap A or B.  Errors: EINVAL (null or
+ * misaligned pointer, n <= 0, depth out of range, overlap), ENOMEM (caller workspace too small),
  * EUNSUPPORTED, EDEVICE. */
 stark_status stark_gemm(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n,
                         int depth, stark_precision p, void* stream);

@@ -89,6 +89,10 @@ stark_status run_cached(stark_ctx* ctx, const Plan& p, const float* A, const flo
 // Make sure the context workspace holds `bytes` (caller lock held).
 stark_status ensure_workspace(stark_ctx* ctx, size_t bytes);
 
+// User operands of one multiply: non-NULL, n > 0, 16-byte aligned, C
+// overlapping neither A nor B.  Sets the error message.
+stark_status check_operands(const float* A, const float* B, const float* C, int64_t n);
+
 // Autotuner (tuner.cpp): depth for (n, precision), measuring on the caller's
 // operands if the size is new.  Caller lock held.
 stark_status tuned_depth(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int precision,

@@ -343,18 +343,6 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t tot
     }
 }
 
-// ---------------------------------------------------------------------------
-// bf16-split leaf GEMM for large leaves: block tile BM x BN = 256 x 256
-// (P = 2) or 256 x 128 (P = 3), 8 waves, K steps of 32.  Operand tiles go
-// from global memory straight into LDS (global_load_lds_dwordx4: each lane
-// deposits 16 bytes at LDS base + 16 * lane), two stages deep: the loads of
-// step k+1 are in flight while step k runs on the matrix cores, and no
-// register staging is needed.  The LDS image of a stage is [plane][row][4
-// chunks of 8 bf16], A rows first, then B rows; the chunk index is XOR-ed
-// with (row >> 2) & 3 so that the 16 lanes of an MFMA operand read (16 rows,
-// one chunk) hit 16 different bank groups.  The global address each lane
-// loads is permuted so that its 16 bytes land in that swizzled position.
-// ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 // Configuration of the large-leaf kernel: block tile, wave grid and LDS
@@ -511,11 +499,147 @@ __global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_
 
 
 // ---------------------------------------------------------------------------
+// binary32 leaf GEMM for large leaves: 256 x 256 block tile, 8 waves of
+// 128 x 64, K steps of 16, three LDS stages filled by direct global->LDS
+// loads straight from the binary32 operands (views included: leading
+// dimension from the recursion), no register staging.
+//   A stage image: [256 rows][4 chunks of 4 k], chunk position c ^ blk_swz(row
+//     mod 16) (as the 16-bit blocked layout), one load = one 16-row block.
+//   B stage image: [16 k][64 chunks of 4 n], chunk position c ^ f32_bswz(k),
+//     one load = one 256-wide k-row.
+// The permutation is applied on the global side (lane l fetches the chunk
+// that belongs at LDS unit l), so both MFMA operand reads are bank-conflict
+// free.  MFMA s of a step gives lane group g the k = 4g + s, as in
+// k_gemm_f32, so the accumulation sequence (and the result) is the same as
+// that kernel's.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int f32_bswz(int k) { return ((k >> 2) & 1) << 2; }
+
+constexpr int kF32BigThreads = 512;
+
+template <class Src>
+__global__ __launch_bounds__(kF32BigThreads) void k_gemm_f32_big(Src src, int64_t total_tiles) {
+    constexpr int BM = 256, BN = 256, BK = 16, NW = 8, WAVES_N = 4, STAGES = 3;
+    constexpr int WM = 128, WN = 64, TM = WM / 16, TN = WN / 16;
+    constexpr int AU = BM * BK / 4;                    // 16-byte units of A per stage
+    constexpr int UNITS = AU + BK * BN / 4;            // plus B
+    constexpr int GA = BM / 16;                        // A blocks of 16 rows per stage
+    static_assert(GA % NW == 0 && BK % NW == 0, "loads must split evenly over the waves");
+    constexpr int LPS = GA / NW + BK / NW;             // direct loads per lane per stage
+    __shared__ __attribute__((aligned(16))) uint4 lds[STAGES][UNITS];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w / WAVES_N, wn = w % WAVES_N;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t G = gridDim.x;
+    const int64_t slot = xcd_slot(blockIdx.x, G);
+
+    for (int64_t t = slot; t < total_tiles; t += G) {
+        int64_t local;
+        const ProbDesc& d = src.get(src.locate(t, local));
+        const int64_t L = d.leaf;
+        const int64_t tm_cnt = L / BM, tn_cnt = L / BN, tpl = tm_cnt * tn_cnt;
+        const int64_t leaf = local / tpl;
+        int64_t tm, tn;
+        tile_coords(local - leaf * tpl, tm_cnt, tn_cnt, tm, tn);
+        const float *Ap, *Bp;
+        int64_t lda, ldb;
+        resolve(d, 0, d.depth, leaf, Ap, lda);
+        resolve(d, 1, d.depth, leaf, Bp, ldb);
+        float* Cp;
+        int64_t ldc;
+        if (d.depth == 0) { Cp = d.C; ldc = d.n; }
+        else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * L * L; ldc = L; }
+        const bool crop = d.depth == 0 && d.bounded0;
+        const int64_t m0 = tm * BM, n0 = tn * BN;
+
+        // Per-lane sources.  A block g (rows 16g..16g+15) goes to wave g % NW;
+        // lane l fills unit 4*(l/4) + l%4 of the block: row l/4, position
+        // l%4, holding chunk (l%4) ^ blk_swz(l/4).  B k-row r goes to wave
+        // r % NW; lane l fills position l, holding chunk l ^ f32_bswz(r).
+        const int arow = lane >> 2;
+        const float* a_src = Ap + (m0 + arow) * lda + 4 * ((lane & 3) ^ blk_swz(arow));
+        auto issue = [&](int stage, int64_t k0) {
+#pragma unroll
+            for (int r = 0; r < GA / NW; ++r) {
+                const int g = w + NW * r;
+                __builtin_amdgcn_global_load_lds(a_src + (int64_t)(16 * g) * lda + k0,
+                                                 (lds_void_t*)&lds[stage][64 * g], 16, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < BK / NW; ++r) {
+                const int kr = w + NW * r;
+                __builtin_amdgcn_global_load_lds(Bp + (k0 + kr) * ldb + n0 + 4 * (lane ^ f32_bswz(kr)),
+                                                 (lds_void_t*)&lds[stage][AU + 64 * kr], 16, 0, 0);
+            }
+        };
+
+        f32x4 acc[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        const int64_t KT = L / BK;
+#pragma unroll
+        for (int s = 0; s < STAGES - 1; ++s)
+            if (s < KT) issue(s, s * BK);
+        for (int64_t kt = 0; kt < KT; ++kt) {
+            if (kt + STAGES - 2 < KT) wait_vmcnt<LPS * (STAGES - 2)>();
+            else wait_vmcnt<0>();
+            __syncthreads();     // step kt landed for every wave; step kt-1's reads are done
+            if (kt + STAGES - 1 < KT) issue((int)((kt + STAGES - 1) % STAGES), (kt + STAGES - 1) * BK);
+            const uint4* sl = lds[kt % STAGES];
+            const float* sb = reinterpret_cast<const float*>(sl + AU);
+            float b[TN][4];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int col = wn * WN + 16 * j + li;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int k = 4 * lg + s;
+                    b[j][s] = sb[k * BN + 4 * ((col >> 2) ^ f32_bswz(k)) + (col & 3)];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int row = wm * WM + 16 * i + li;
+                const float4 a = __builtin_bit_cast(float4, sl[4 * row + (lg ^ blk_swz(row & 15))]);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float av = s == 0 ? a.x : s == 1 ? a.y : s == 2 ? a.z : a.w;
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[j][s], acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();         // the next tile's first loads overwrite the stages
+
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
+                    const int64_t col = n0 + wn * WN + 16 * j + li;
+                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r];
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 template <class Src, int BM, int BN>
 static hipError_t launch_f32_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
     hipLaunchKernelGGL((k_gemm_f32<Src, BM, BN>), dim3(grid), dim3(kGemmThreads), 0, st, s, tiles);
+    return hipGetLastError();
+}
+template <class Src>
+static hipError_t launch_f32_big_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_gemm_f32_big<Src>), dim3(grid), dim3(kF32BigThreads), 0, st, s, tiles);
     return hipGetLastError();
 }
 template <class Src, int BM, int BN, int P, bool F16>
@@ -537,7 +661,7 @@ static int occupancy(K kernel, int threads) {
 }
 
 int64_t gemm_tiles_per_leaf(int planes, int tile, int64_t leaf) {
-    if (tile == 256)
+    if (tile == 256)   // 256 x 128 for three bf16 planes, else 256 x 256 (binary32 and two planes)
         return planes == 3 ? (leaf / BigCfg<3>::BM) * (leaf / BigCfg<3>::BN)
                            : (leaf / BigCfg<2>::BM) * (leaf / BigCfg<2>::BN);
     return (leaf / tile) * (leaf / tile);
@@ -546,8 +670,9 @@ int64_t gemm_tiles_per_leaf(int planes, int tile, int64_t leaf) {
 int gemm_blocks_per_cu(int planes, int tile) {
     // Occupancy does not depend on the descriptor source or the 16-bit flavour.
     if (planes == 0)
-        return tile == 128 ? occupancy(k_gemm_f32<OneProb, 128, 128>, kGemmThreads)
-                           : occupancy(k_gemm_f32<OneProb, 64, 64>, kGemmThreads);
+        return tile == 256   ? occupancy(k_gemm_f32_big<OneProb>, kF32BigThreads)
+               : tile == 128 ? occupancy(k_gemm_f32<OneProb, 128, 128>, kGemmThreads)
+                             : occupancy(k_gemm_f32<OneProb, 64, 64>, kGemmThreads);
     if (tile == 256)
         return planes == 2 ? occupancy(k_gemm_bf16_big<OneProb, 2, false>, BigCfg<2>::NT)
                            : occupancy(k_gemm_bf16_big<OneProb, 3, false>, BigCfg<3>::NT);
@@ -560,8 +685,9 @@ int gemm_blocks_per_cu(int planes, int tile) {
 
 template <class Src>
 hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t tiles, int grid, hipStream_t st) {
-    if (planes == 0) return tile == 128 ? launch_f32_t<Src, 128, 128>(s, tiles, grid, st)
-                                        : launch_f32_t<Src, 64, 64>(s, tiles, grid, st);
+    if (planes == 0) return tile == 256   ? launch_f32_big_t<Src>(s, tiles, grid, st)
+                            : tile == 128 ? launch_f32_t<Src, 128, 128>(s, tiles, grid, st)
+                                          : launch_f32_t<Src, 64, 64>(s, tiles, grid, st);
     if (f16) {   // FP16X3: two binary16 planes
         if (tile == 256) return launch_bf16_big_t<Src, 2, true>(s, tiles, grid, st);
         return tile == 128 ? launch_bf16_t<Src, 128, 128, 2, true>(s, tiles, grid, st)

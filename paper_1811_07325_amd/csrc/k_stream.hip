@@ -367,12 +367,27 @@ __global__ __launch_bounds__(kStreamThreads) void k_absmax(Src src) {
     const int side = blockIdx.y;
     const float* X = side ? d.B : d.A;
     const int64_t count = d.n * d.n;
-    const int64_t chunk = (count + kScaleParts - 1) / kScaleParts;
-    const int64_t lo = local * chunk;
+    // chunks of a multiple of 4 elements, so every chunk starts 16-byte aligned
+    const int64_t chunk = ((count + kScaleParts - 1) / kScaleParts + 3) & ~int64_t(3);
+    const int64_t lo = local * chunk < count ? local * chunk : count;
     const int64_t hi = lo + chunk < count ? lo + chunk : count;
-    float m = 0.0f;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kStreamThreads) m = fmaxf(m, fabsf(X[i]));
-    part[threadIdx.x] = m;
+    const int64_t nv = (hi - lo) >> 2;
+    const float4* X4 = reinterpret_cast<const float4*>(X + lo);
+    static_assert(kStreamUnroll == 4, "the final reduction below folds four partial maxima");
+    float m[kStreamUnroll] = {};
+    for (int64_t i = threadIdx.x; i < nv; i += kStreamUnroll * kStreamThreads) {
+        float4 v[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            const int64_t j = i + u * kStreamThreads;
+            v[u] = j < nv ? X4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u)
+            m[u] = fmaxf(m[u], fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)), fmaxf(fabsf(v[u].z), fabsf(v[u].w))));
+    }
+    for (int64_t i = lo + 4 * nv + threadIdx.x; i < hi; i += kStreamThreads) m[0] = fmaxf(m[0], fabsf(X[i]));
+    part[threadIdx.x] = fmaxf(fmaxf(m[0], m[1]), fmaxf(m[2], m[3]));
     __syncthreads();
     for (int w = kStreamThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) part[threadIdx.x] = fmaxf(part[threadIdx.x], part[threadIdx.x + w]);

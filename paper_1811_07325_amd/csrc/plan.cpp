@@ -72,12 +72,12 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
     p.leaf = p.np >> depth;
     p.padded = (p.np != n);
     // Leaf GEMM tile class: the largest whose tile count still fills the
-    // chip (256 CUs); 256-wide tiles exist for the bf16 paths only.
+    // chip (256 CUs).
     {
         const int64_t leaves = pow7(depth);
         const int64_t t256 = leaves * (p.leaf / 256) * (p.leaf / 256);
         const int64_t t128 = leaves * (p.leaf / 128) * (p.leaf / 128);
-        if (planes > 0 && p.leaf % 256 == 0 && t256 >= 256) p.tile = 256;
+        if (p.leaf % 256 == 0 && t256 >= 256) p.tile = 256;
         else if (p.leaf % 128 == 0 && (t128 >= 128 || p.leaf % 64 != 0)) p.tile = 128;
         else p.tile = 64;
     }

@@ -136,6 +136,14 @@ stark_status Engine::submit(const stark_request& r, uint64_t* ticket) {
     }
     const bool gen = (r.A == nullptr);
     if (gen != (r.B == nullptr)) { set_error("A and B must both be given or both be NULL"); return STARK_EINVAL; }
+    {   // user operands get the alignment and overlap checks of stark_gemm
+        const uintptr_t bits = (uintptr_t)r.A | (uintptr_t)r.B | (uintptr_t)r.C;
+        if (bits & 15) { set_error("A, B and C must be 16-byte aligned"); return STARK_EINVAL; }
+        if (!gen && r.C) {
+            const stark_status rc = check_operands(r.A, r.B, r.C, r.n);
+            if (rc != STARK_OK) return rc;
+        }
+    }
     std::unique_ptr<Req> q(new Req());
     q->r = r;
     q->gen = gen;

@@ -156,6 +156,20 @@ static bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
     return pa < pb + bn && pb < pa + an;
 }
 
+stark_status check_operands(const float* A, const float* B, const float* C, int64_t n) {
+    if (!A || !B || !C) { set_error("A, B and C must be non-NULL device pointers"); return STARK_EINVAL; }
+    if (n <= 0) { set_error("n must be positive"); return STARK_EINVAL; }
+    if (((uintptr_t)A | (uintptr_t)B | (uintptr_t)C) & 15) {
+        set_error("A, B and C must be 16-byte aligned");
+        return STARK_EINVAL;
+    }
+    const size_t bytes = (size_t)n * (size_t)n * sizeof(float);
+    if (overlaps(C, bytes, A, bytes) || overlaps(C, bytes, B, bytes)) {
+        set_error("C overlaps A or B");
+        return STARK_EINVAL;
+    }
+    return STARK_OK;
+}
 }  // namespace stk
 
 using namespace stk;
@@ -263,16 +277,6 @@ stark_status stark_destroy(stark_ctx* ctx) {
     return rc;
 }
 
-static stark_status check_operands(const float* A, const float* B, const float* C, int64_t n) {
-    if (!A || !B || !C) { set_error("A, B and C must be non-NULL device pointers"); return STARK_EINVAL; }
-    if (n <= 0) { set_error("n must be positive"); return STARK_EINVAL; }
-    const size_t bytes = (size_t)n * (size_t)n * sizeof(float);
-    if (overlaps(C, bytes, A, bytes) || overlaps(C, bytes, B, bytes)) {
-        set_error("C overlaps A or B");
-        return STARK_EINVAL;
-    }
-    return STARK_OK;
-}
 
 stark_status stark_gemm(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int depth,
                         stark_precision prec, void* stream) {

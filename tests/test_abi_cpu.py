@@ -139,10 +139,13 @@ def test_create_without_gpu_reports_device_error(S):
 
 
 def test_tile_class_choice(S):
-    # 256-wide tiles only for bf16 leaves that fill the chip with them
+    # 256-wide tiles for leaves that fill the chip with them
     assert S.stark_plan_info(16384, 2, 1).gemm_tile == 256
     assert S.stark_plan_info(16384, 4, 2).gemm_tile == 256
-    assert S.stark_plan_info(16384, 2, 0).gemm_tile == 128
+    assert S.stark_plan_info(16384, 2, 0).gemm_tile == 256
+    assert S.stark_plan_info(16384, 3, 0).gemm_tile == 256
+    assert S.stark_plan_info(4096, 3, 0).gemm_tile == 256   # 343 leaves of 512
+    assert S.stark_plan_info(4096, 0, 0).gemm_tile == 256
     assert S.stark_plan_info(4096, 1, 1).gemm_tile == 256
     assert S.stark_plan_info(2048, 1, 1).gemm_tile == 128
     assert S.stark_plan_info(512, 2, 1).gemm_tile == 64    # 49 leaves of 128: more, smaller tiles

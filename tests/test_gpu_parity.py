@@ -92,7 +92,8 @@ def test_integer_inputs_bit_exact(S, ctx, n, depth, prec):
 
 
 @pytest.mark.parametrize("n,depth,prec", [(4096, 1, "bf16x3"), (4096, 0, "bf16x6"), (4096, 1, "bf16x6"),
-                                          (4032, 1, "bf16x3"), (4096, 1, "fp16x3")])
+                                          (4032, 1, "bf16x3"), (4096, 1, "fp16x3"), (4096, 0, "fp32"),
+                                          (4096, 1, "fp32"), (4032, 1, "fp32")])
 def test_integer_inputs_bit_exact_large_tiles(S, ctx_big, n, depth, prec):
     """Leaves wide enough for the 256-wide tile class."""
     print(f"case n={n} depth={depth} prec={prec}", flush=True)
@@ -130,6 +131,28 @@ def test_float_inputs_match_model(S, ctx, n, depth, prec):
     L = oracle.padded_size(n, depth, 64) >> depth
     assert d <= 4 * 2.0 ** -24 * np.sqrt(L) * 2 ** depth
     assert e_gpu <= 1.5 * e_model + 1e-6
+
+
+@pytest.mark.parametrize("n,depth,prec", [(4096, 1, "fp32"), (4096, 1, "bf16x3")])
+def test_float_large_tiles_match_model(S, ctx_big, n, depth, prec):
+    """The 256-wide tile kernels on float inputs: against the arithmetic
+    model on every element, against the FP64 product on sampled rows."""
+    print(f"case n={n} depth={depth} prec={prec}", flush=True)
+    assert S.stark_plan_info(n, depth, PREC[prec]).gemm_tile == 256
+    A = inputs.uniform(n, 0)
+    B = inputs.uniform(n, 1)
+    C = run(S, ctx_big, A, B, depth, prec)
+    model = oracle.strassen_model_f32(A, B, depth, prec, oracle.padded_size(n, depth, 64))
+    rows = inputs.sample_rows(n, 64, 2)
+    ref = oracle.rows_f64(A, B, rows)
+    e_gpu, e_model = rel_f(C[rows], ref), rel_f(model[rows], ref)
+    d = rel_f(C, model)
+    print(f"  rel_frob(rows) gpu={e_gpu:.3e} model={e_model:.3e} gpu-vs-model={d:.3e}", flush=True)
+    # the model's leaves are exact: the GPU adds binary32 accumulation over L
+    L = oracle.padded_size(n, depth, 64) >> depth
+    bound = 4 * 2.0 ** -24 * np.sqrt(L) * 2 ** depth
+    assert d <= bound
+    assert e_gpu <= 1.5 * e_model + bound
 
 
 # ---------------------------------------------------------------------------
@@ -367,6 +390,11 @@ def test_argument_errors(S, ctx):
     with pytest.raises(S.StarkError) as e:
         S.stark_gemm(ctx, A, B, torch.empty_like(A), n, 0, 9, None)
     assert e.value.status == S.STARK_EUNSUPPORTED
+    # a view 4 bytes into an allocation is rejected before any launch
+    shifted = torch.zeros(n * n + 1, dtype=torch.float32, device="cuda")[1:].view(n, n)
+    with pytest.raises(S.StarkError) as e:
+        S.stark_gemm(ctx, shifted, B, torch.empty_like(A), n, 0, 0, None)
+    assert e.value.status == S.STARK_EINVAL and "aligned" in str(e.value)
 
 
 def test_caller_workspace_too_small(S):
