@@ -119,15 +119,21 @@ COPY_BYTES = 1 << 30
 
 def copy_calibration(torch) -> int:
     """A streaming kernel of known traffic: y = -x over 1 GiB of binary32
-    (reads 1 GiB, writes 1 GiB), three times.  Hardware counters read on it
+    (reads 1 GiB, writes 1 GiB), four times (the last three timed).  Hardware counters read on it
     give the factor that turns the same counters read on other kernels into
     bytes."""
     x = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     y = torch.empty_like(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.neg(x, out=y)
+    e0.record()
     for _ in range(3):
         torch.neg(x, out=y)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": COPY_BYTES, "kernel": "neg", "reps": 3}), flush=True)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    print(json.dumps({"copy_bytes": COPY_BYTES, "kernel": "neg", "reps": 4, "ms": ms,
+                      "read_write_gbs": 2 * COPY_BYTES / (ms * 1e-3) * 1e-9}), flush=True)
     return 0
 
 
@@ -228,9 +234,14 @@ def main() -> int:
     y = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
     S.stark_matvec_f64(B, x, y[0], n, st)
     S.stark_matvec_f64(A, y[0], y[1], n, st)
-    S.stark_matvec_f64(C, x, y[2], n, st)
-    st.synchronize()
-    freiv = float(torch.linalg.norm(y[2] - y[1]) / torch.linalg.norm(y[1]))
+
+    def freivalds() -> float:
+        """||C x - A (B x)|| / ||A (B x)|| for the result now in C."""
+        S.stark_matvec_f64(C, x, y[2], n, st)
+        st.synchronize()
+        return float(torch.linalg.norm(y[2] - y[1]) / torch.linalg.norm(y[1]))
+
+    freiv = freivalds()
     log(f"  error: rel_frob(rows)={rel_rows:.3e} max_abs={max_abs:.3e} freivalds={freiv:.3e}")
 
     # -- roofline of the dominant kernel (leaf GEMM), timed live --------------
@@ -292,7 +303,8 @@ def main() -> int:
         for name, p_, dmin, dmax in (("fp32_strassen", S.STARK_FP32, 1, 4), ("fp32_classical", S.STARK_FP32, 0, 0),
                                      ("fp16x3_strassen", S.STARK_FP16X3, 2, 4),
                                      ("bf16x6_strassen", S.STARK_BF16X6, 2, 4),
-                                     ("bf16x3_classical", S.STARK_BF16X3, 0, 0)):
+                                     ("bf16x3_classical", S.STARK_BF16X3, 0, 0),
+                                     ("bf16x3_strassen_depth1", S.STARK_BF16X3, 1, 1)):
             if dmin == dmax:
                 d_ = dmin
                 pts = []
@@ -302,8 +314,10 @@ def main() -> int:
                 d_ = min(okp, key=lambda p: p[1])[0] if okp else min(pts, key=lambda p: p[2])[0]
             m_ = timed(d_, p_, max(3, args.steps // 2), 1)
             compare[name] = {"depth": d_, "ms": m_, "tflops": 2.0 * n ** 3 / (m_ * 1e-3) * 1e-12,
+                             "freivalds": freivalds(),
                              "tune": [{"depth": a, "ms": b, "err": c} for a, b, c in pts]}
-            log(f"  {name}: depth {d_}, {m_:.3f} ms, {compare[name]['tflops']:.1f} TF/s")
+            log(f"  {name}: depth {d_}, {m_:.3f} ms, {compare[name]['tflops']:.1f} TF/s, "
+                f"freivalds {compare[name]['freivalds']:.2e}")
         tt = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(st):
             for _ in range(2):
@@ -314,7 +328,8 @@ def main() -> int:
             tt[1].record(st)
         tt[1].synchronize()
         m_ = tt[0].elapsed_time(tt[1]) / 3
-        compare["torch_matmul_fp32_external"] = {"ms": m_, "tflops": 2.0 * n ** 3 / (m_ * 1e-3) * 1e-12}
+        compare["torch_matmul_fp32_external"] = {"ms": m_, "tflops": 2.0 * n ** 3 / (m_ * 1e-3) * 1e-12,
+                                                 "freivalds": freivalds()}
 
     # -- CPU baseline: the oracle on the sampled rows ---------------------------
     cpu = None

@@ -22,7 +22,7 @@ namespace stk {
 
 namespace {
 
-enum LaunchKind { kPad, kDivide, kAbsmax, kScaleExp, kSplit, kGemm, kCombine };
+enum LaunchKind { kPad, kDivide, kAbsmax, kScaleExp, kSplit, kGemm, kCombine, kCombine2 };
 
 struct BatchLaunch {
     LaunchKind kind;
@@ -74,6 +74,7 @@ stark_status enqueue(stark_ctx* ctx, const BatchEntry& e, hipStream_t st) {
                                     gemm_grid(ctx, e.planes, l.tile, l.total), st));
                 break;
             case kCombine: STK_HIP(launch_combine(src, l.level, l.total, st)); break;
+            case kCombine2: STK_HIP(launch_combine2(src, l.level, l.total, st)); break;
         }
     }
     return STARK_OK;
@@ -147,8 +148,16 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
                 const Plan& p = plans[i];
                 return p.tile == tile ? pow7(p.depth) * gemm_tiles_per_leaf(p.planes, tile, p.leaf) : (int64_t)0;
             });
-        for (int l = max_depth - 1; l >= 0; --l)
-            add_launch(kCombine, l, 0, [&](int i) { return plans[i].depth > l ? blocks_combine(descs[i], l) : 0; });
+        // per problem: the two deepest levels in one pass, then one level at a time
+        for (int l = max_depth - 1; l >= 0; --l) {
+            add_launch(kCombine2, l, 0, [&](int i) {
+                return plans[i].depth >= 2 && plans[i].depth - 2 == l ? blocks_combine2(descs[i], l) : 0;
+            });
+            add_launch(kCombine, l, 0, [&](int i) {
+                const int d = plans[i].depth;
+                return (d == 1 && l == 0) || l <= d - 3 ? blocks_combine(descs[i], l) : 0;
+            });
+        }
         const size_t bytes = sizeof(ProbDesc) * count + sizeof(int64_t) * pre.size();
         STK_HIP(hipMalloc(&e.dev, bytes));
         std::vector<char> host(bytes);

@@ -481,6 +481,83 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine(Src src, int level) 
     }
 }
 
+// Two combine levels in one pass: node P of level l (output m x m) from its
+// 49 grandchildren (g x g, g = m/4) without writing the level-(l+1) outputs.
+// A thread owns one float4 position (r, c) of the grandchild grid: for each
+// child j it forms the child's four quadrant values at (r, c) from its seven
+// products, exactly as k_combine does, and folds them into the parent's
+// sixteen g x g sub-blocks in child order.  That order is the one k_combine
+// uses one level up (C11 = ((N1 + N4) - N5) + N7, ...), so the result equals
+// two k_combine launches bit for bit.
+template <class Src>
+__global__ __launch_bounds__(kStreamThreads) void k_combine2(Src src, int level) {
+    int64_t local;
+    const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
+    const bool crop = (level == 0) && d.bounded0;
+    const int64_t m = d.np >> level, g = m >> 2;
+    const int64_t gq = g >> 2;                 // float4 per grandchild row
+    const int64_t q4 = g * gq;                 // float4 per grandchild
+    const int64_t bpn = (q4 + kStreamThreads - 1) / kStreamThreads;
+    const int64_t node = local / bpn;
+    const int64_t f = (local - node * bpn) * kStreamThreads + threadIdx.x;
+    if (f >= q4) return;
+
+    const float* wsf = reinterpret_cast<const float*>(d.ws);
+    const float4* in = reinterpret_cast<const float4*>(
+        wsf + ((level + 2 == d.depth) ? d.leaf_m : d.comb[level + 2]) + node * 49 * g * g);
+    float* out;
+    int64_t ldo;
+    if (level == 0) {
+        out = d.C;
+        ldo = d.n;
+    } else {
+        out = reinterpret_cast<float*>(d.ws) + d.comb[level] + node * m * m;
+        ldo = m;
+    }
+    // acc[Q][s]: parent quadrant Q (11, 12, 21, 22), sub-block s = 2 qa + qb
+    float4 acc[4][4];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const float4* mj = in + (int64_t)j * 7 * q4 + f;
+        const float4 m1 = mj[0], m2 = mj[q4], m3 = mj[2 * q4], m4 = mj[3 * q4];
+        const float4 m5 = mj[4 * q4], m6 = mj[5 * q4], m7 = mj[6 * q4];
+        float4 nq[4];
+        nq[0] = f4add(f4sub(f4add(m1, m4), m5), m7);
+        nq[1] = f4add(m3, m5);
+        nq[2] = f4add(m2, m4);
+        nq[3] = f4add(f4add(f4sub(m1, m2), m3), m6);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float4 v = nq[s];
+            switch (j) {   // child j = N_{j+1}
+                case 0: acc[0][s] = v; acc[3][s] = v; break;
+                case 1: acc[2][s] = v; acc[3][s] = f4sub(acc[3][s], v); break;
+                case 2: acc[1][s] = v; acc[3][s] = f4add(acc[3][s], v); break;
+                case 3: acc[0][s] = f4add(acc[0][s], v); acc[2][s] = f4add(acc[2][s], v); break;
+                case 4: acc[0][s] = f4sub(acc[0][s], v); acc[1][s] = f4add(acc[1][s], v); break;
+                case 5: acc[3][s] = f4add(acc[3][s], v); break;
+                default: acc[0][s] = f4add(acc[0][s], v); break;
+            }
+        }
+    }
+    const int64_t r = f / gq, c = (f - r * gq) * 4;
+#pragma unroll
+    for (int Q = 0; Q < 4; ++Q)
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) {
+            const int64_t row = (Q >> 1) * 2 * g + (sb >> 1) * g + r;
+            const int64_t col = (Q & 1) * 2 * g + (sb & 1) * g + c;
+            if (crop) {
+                const float* v = &acc[Q][sb].x;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (row < d.n && col + e < d.n) out[row * ldo + col + e] = v[e];
+            } else {
+                *reinterpret_cast<float4*>(out + row * ldo + col) = acc[Q][sb];
+            }
+        }
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
@@ -504,6 +581,11 @@ int64_t blocks_split(const ProbDesc& d) {
     return nodes * tiles;
 }
 int64_t blocks_combine(const ProbDesc& d, int level) { return blocks_divide(d, level); }
+int64_t blocks_combine2(const ProbDesc& d, int level) {
+    const int64_t g = (d.np >> level) >> 2;
+    const int64_t q4 = g * (g / 4);
+    return pow7(level) * ((q4 + kStreamThreads - 1) / kStreamThreads);
+}
 
 template <class Src>
 hipError_t launch_pad(const Src& s, int64_t blocks, hipStream_t st) {
@@ -534,6 +616,11 @@ hipError_t launch_split(const Src& s, int planes, int64_t blocks, hipStream_t st
     return hipGetLastError();
 }
 template <class Src>
+hipError_t launch_combine2(const Src& s, int level, int64_t blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_combine2<Src>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
+    return hipGetLastError();
+}
+template <class Src>
 hipError_t launch_combine(const Src& s, int level, int64_t blocks, hipStream_t st) {
     hipLaunchKernelGGL((k_combine<Src>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
     return hipGetLastError();
@@ -551,5 +638,7 @@ template hipError_t launch_split<OneProb>(const OneProb&, int, int64_t, hipStrea
 template hipError_t launch_split<TableProb>(const TableProb&, int, int64_t, hipStream_t);
 template hipError_t launch_combine<OneProb>(const OneProb&, int, int64_t, hipStream_t);
 template hipError_t launch_combine<TableProb>(const TableProb&, int, int64_t, hipStream_t);
+template hipError_t launch_combine2<OneProb>(const OneProb&, int, int64_t, hipStream_t);
+template hipError_t launch_combine2<TableProb>(const TableProb&, int, int64_t, hipStream_t);
 
 }  // namespace stk

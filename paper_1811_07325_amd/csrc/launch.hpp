@@ -12,6 +12,7 @@ int64_t blocks_pad(const ProbDesc& d);
 int64_t blocks_divide(const ProbDesc& d, int level);
 int64_t blocks_split(const ProbDesc& d);
 int64_t blocks_combine(const ProbDesc& d, int level);
+int64_t blocks_combine2(const ProbDesc& d, int level);
 
 template <class Src> hipError_t launch_pad(const Src& s, int64_t blocks, hipStream_t st);
 // FP16X3 scaling: partial maxima (kScaleParts blocks per problem), then the
@@ -21,6 +22,8 @@ template <class Src> hipError_t launch_scale_exp(const Src& s, int64_t blocks, h
 template <class Src> hipError_t launch_divide(const Src& s, int level, int64_t blocks, hipStream_t st);
 template <class Src> hipError_t launch_split(const Src& s, int planes, int64_t blocks, hipStream_t st);
 template <class Src> hipError_t launch_combine(const Src& s, int level, int64_t blocks, hipStream_t st);
+// Combine levels `level` + 1 and `level` in one pass (depth >= level + 2).
+template <class Src> hipError_t launch_combine2(const Src& s, int level, int64_t blocks, hipStream_t st);
 // f16: the two planes are binary16 (FP16X3) rather than bfloat16.
 template <class Src> hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t tiles, int grid, hipStream_t st);
 

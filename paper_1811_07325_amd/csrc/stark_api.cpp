@@ -8,7 +8,8 @@
 //   divide l = 0..   binary32 operand sums (level 0 zero-pads on the fly)
 //   [split]          bf16 paths: last level, operands split into bf16 planes
 //   leaf GEMM        one grouped persistent launch over all 7^k leaves
-//   combine l = k-1..0  (level 0 writes C, cropping the padding)
+//   combine l = k-1..0  (level 0 writes C, cropping the padding; the two
+//                    deepest levels run as one pass)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,7 +61,12 @@ stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned
         STK_HIP(launch_gemm(src, p.planes, p.tile, d.fp16 != 0, tiles, gemm_grid(ctx, p.planes, p.tile, tiles), st));
     }
     if (mask & STARK_PHASE_COMBINE) {
-        for (int l = p.depth - 1; l >= 0; --l)
+        int l = p.depth - 1;
+        if (p.depth >= 2) {   // the two deepest levels in one pass
+            STK_HIP(launch_combine2(src, p.depth - 2, blocks_combine2(d, p.depth - 2), st));
+            l = p.depth - 3;
+        }
+        for (; l >= 0; --l)
             STK_HIP(launch_combine(src, l, blocks_combine(d, l), st));
     }
     return STARK_OK;

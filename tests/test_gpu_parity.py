@@ -287,8 +287,11 @@ def test_fp16x3_wide_range_inputs_match_model(S, ctx):
     assert rel_f(C, exact) < 5e-6
 
 
-def test_combine_levels_bit_exact(S, ctx, ws):
-    n, depth = 256, 2
+@pytest.mark.parametrize("n,depth", [(256, 2), (512, 3)])
+def test_combine_levels_bit_exact(S, ctx, ws, n, depth):
+    """The two deepest combine levels run as one pass (no level-(k-1)
+    outputs in memory), the others one level at a time: every level written
+    equals the oracle's binary32 combine steps bit for bit."""
     A = inputs.uniform(n, 7)
     B = inputs.uniform(n, 8)
     dA, dB = dev(A), dev(B)
@@ -297,12 +300,18 @@ def test_combine_levels_bit_exact(S, ctx, ws):
     torch.cuda.synchronize()
     d = S.stark_plan_info(n, depth, 0)
     L = d.leaf
-    M = ws_view(ws, d.leaf_m, 49 * L * L, np.float32).reshape(49, L, L)
-    m1 = 2 * L
-    C1 = ws_view(ws, d.comb[1], 7 * m1 * m1, np.float32).reshape(7, m1, m1)
-    for node in range(7):
-        assert np.array_equal(C1[node], oracle.combine_f32(M[7 * node:7 * node + 7])), node
-    assert np.array_equal(dC.cpu().numpy(), oracle.combine_f32(C1))
+    nleaf = 7 ** depth
+    M = ws_view(ws, d.leaf_m, nleaf * L * L, np.float32).reshape(nleaf, L, L)
+    # oracle: one level at a time from the leaf products up
+    levels = {depth: M}
+    for lvl in range(depth - 1, -1, -1):
+        ch = levels[lvl + 1]
+        levels[lvl] = np.stack([oracle.combine_f32(ch[7 * i:7 * i + 7]) for i in range(7 ** lvl)])
+    if depth == 3:   # level 1 is written by the fused pass over levels 2 and 1
+        m1 = n >> 1
+        C1 = ws_view(ws, d.comb[1], 7 * m1 * m1, np.float32).reshape(7, m1, m1)
+        assert np.array_equal(C1, levels[1])
+    assert np.array_equal(dC.cpu().numpy(), levels[0][0])
 
 
 def test_leaf_products_close_to_exact(S, ctx, ws):
