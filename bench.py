@@ -267,24 +267,13 @@ def main() -> int:
     L = plan.leaf
     nleaf = 7 ** depth
     prods = {0: 1, 2: 3, 3: 6}[planes]     # matrix-core products per leaf (FP16X3: 3)
-    leaf_flops = 2.0 * L ** 3 * nleaf * prods        # matrix-core work of one launch
+    leaf_flops = plan.mfma_flops                      # matrix-core work of one launch
+    assert leaf_flops == 2.0 * L ** 3 * nleaf * prods
     unit_peak = PEAK["fp32"] if planes == 0 else PEAK["bf16"]
     achieved = leaf_flops / (t_leaf * 1e-3)
     traffic = read_traffic(args.traffic, f"n{n}_d{depth}_{args.precision}")
-    # divide (+ split) and combine: algorithmic bytes, see the planner
-    Np = plan.n_pad ** 2
-    div_bytes = split_bytes = comb_bytes = 0.0
-    fp32_levels = depth if planes == 0 else max(depth - 1, 0)
-    for l in range(fp32_levels):
-        h = (plan.n_pad >> l) / 2
-        div_bytes += 2 * 7 ** l * (4 + plan.div_slots[l]) * h * h * 4
-    if planes:
-        nodes = 7 ** (depth - 1) if depth else 1
-        ib, ob = (4, 7) if depth else (1, 1)
-        split_bytes = 2 * nodes * (ib * L * L * 4 + ob * planes * L * L * 2)
-    for l in range(depth):
-        h = (plan.n_pad >> l) / 2
-        comb_bytes += 7 ** l * 11 * h * h * 4
+    # divide (+ split) and combine: algorithmic bytes from the planner
+    div_bytes, split_bytes, comb_bytes = plan.divide_bytes, plan.split_bytes, plan.combine_bytes
     phases = {
         "divide_ms": t_div, "divide_gbs": (div_bytes + split_bytes) / (t_div * 1e-3) * 1e-9,
         "leaf_ms": t_leaf, "leaf_tflops": achieved * 1e-12,

@@ -228,12 +228,18 @@ typedef struct {
     int64_t scale;            /* FP16X3: byte offset of the scale region: 2 x 256
                                  binary32 partial maxima, then the two int32
                                  exponents e_A, e_B (-1 otherwise)                 */
+    /* Algorithmic work of one multiply (what the method must move or compute;
+     * views not counted): bytes of the binary32 divide levels, of the split
+     * (16-bit paths; it forms the last one or two divide levels) and of the
+     * combine; useful leaf flops (2 L^3 per leaf) and matrix-core flops
+     * (times 1, 3, 6 or 3 products for FP32, BF16X3, BF16X6, FP16X3). */
+    double divide_bytes, split_bytes, combine_bytes, leaf_flops, mfma_flops;
 } stark_plan_desc;
 
 stark_status stark_plan_info(int64_t n, int depth, stark_precision p, stark_plan_desc* out);
 
 /* Phases for stark_gemm_phases. */
-#define STARK_PHASE_DIVIDE 1u   /* pad, divide levels and the bf16 split          */
+#define STARK_PHASE_DIVIDE 1u   /* pad, divide levels and the 16-bit split        */
 #define STARK_PHASE_LEAF 2u     /* grouped leaf products                          */
 #define STARK_PHASE_COMBINE 4u  /* combine levels (level 0 writes C)              */
 #define STARK_PHASE_ALL 7u

@@ -107,6 +107,15 @@ __device__ __forceinline__ int64_t blk_offset(int64_t r, int64_t k, int64_t L) {
     return ((r / kBlkRows) * (L / kBlkK) + k / kBlkK) * 512 + ((rr * kBlkChunks + (c ^ blk_swz(rr))) << 3) + (k & 7);
 }
 
+// Block b of a G-block grid -> its logical index.  Consecutive blocks go to
+// different XCDs (b mod 8); when G is a multiple of 8 the remap gives the G/8
+// blocks of XCD x the logical indices [x*G/8, (x+1)*G/8), so work items with
+// neighbouring logical indices share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_slot(int64_t b, int64_t G) {
+    if (G % 8) return b;
+    return (b % 8) * (G / 8) + b / 8;
+}
+
 // A launch covers one problem (kernel-argument descriptor) or many (device
 // table).  `first_block` holds, per problem, the first block index of this
 // launch that belongs to it (ascending, first_block[0] == 0).

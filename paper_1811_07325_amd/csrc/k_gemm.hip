@@ -65,13 +65,6 @@ __device__ __forceinline__ void tile_coords(int64_t r, int64_t tm_cnt, int64_t t
     tn = in / rows;
 }
 
-// Block b of a G-block grid (G a multiple of 8) -> its logical slot, so the
-// G/8 blocks of XCD x take slots [x*G/8, (x+1)*G/8).
-__device__ __forceinline__ int64_t xcd_slot(int64_t b, int64_t G) {
-    if (G % 8) return b;
-    return (b % 8) * (G / 8) + b / 8;
-}
-
 // ---------------------------------------------------------------------------
 // binary32 leaf GEMM.
 // ---------------------------------------------------------------------------

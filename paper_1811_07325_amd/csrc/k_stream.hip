@@ -184,6 +184,40 @@ __device__ __forceinline__ float load1(const float* X, int64_t ld, int64_t n, in
     return X[r * ld + c];
 }
 
+__device__ __forceinline__ float4 load4(const float* X, int64_t ld, int64_t n, int64_t r, int64_t c, bool bounded) {
+    if (bounded) return load4_bounded(X, n, r, c);
+    return *reinterpret_cast<const float4*>(X + r * ld + c);
+}
+
+// Elements (r, c..c+3) of the operand of child c1 (c1 = 0..6 for M1..M7) of a
+// node whose operand X has quadrant edge H, formed exactly as k_divide forms
+// them (one binary32 add per element, same operand order), so that operand
+// need not be stored.
+__device__ __forceinline__ float4 child4(const float* X, int64_t ld, int64_t n, int64_t H, int64_t r, int64_t c,
+                                         int side, int c1, bool bounded) {
+    auto q = [&](int a, int b) { return load4(X, ld, n, r + a * H, c + b * H, bounded); };
+    if (side == 0) {
+        switch (c1) {
+            case 0: return f4add(q(0, 0), q(1, 1));
+            case 1: return f4add(q(1, 0), q(1, 1));
+            case 2: return q(0, 0);
+            case 3: return q(1, 1);
+            case 4: return f4add(q(0, 0), q(0, 1));
+            case 5: return f4sub(q(1, 0), q(0, 0));
+            default: return f4sub(q(0, 1), q(1, 1));
+        }
+    }
+    switch (c1) {
+        case 0: return f4add(q(0, 0), q(1, 1));
+        case 1: return q(0, 0);
+        case 2: return f4sub(q(0, 1), q(1, 1));
+        case 3: return f4sub(q(1, 0), q(0, 0));
+        case 4: return q(1, 1);
+        case 5: return f4add(q(0, 0), q(0, 1));
+        default: return f4add(q(1, 0), q(1, 1));
+    }
+}
+
 // Last divide level of the bf16 paths.  NOUT = 7: every node of level
 // depth-1 gives the seven operand pairs of its children (the leaves);
 // NOUT = 1 (depth 0): the root operands themselves.  Each output block (leaf
@@ -204,23 +238,23 @@ constexpr int kSplitLdsRow = kSplitTile + 8;        // bf16 per LDS row (144 B, 
 template <int P> struct SplitRound { static constexpr int R = 2; };
 template <> struct SplitRound<3> { static constexpr int R = 1; };
 
-__device__ __forceinline__ float4 load4(const float* X, int64_t ld, int64_t n, int64_t r, int64_t c, bool bounded) {
-    if (bounded) return load4_bounded(X, n, r, c);
-    return *reinterpret_cast<const float4*>(X + r * ld + c);
-}
-
 // v[o][i][e]: output o at tile row i, column e of this thread's 4 x 4 piece.
-template <int NOUT>
+// FUSED: X is the operand of the grandparent (edge 4L) and the parent's
+// quadrant values are formed on the fly as child c1's operand (child4).
+template <int NOUT, bool FUSED>
 __device__ __forceinline__ void split_values(const float* X, int64_t ld, int64_t n, int64_t L, int64_t r0, int64_t c0,
-                                             int side, bool bounded, float (&v)[NOUT][4][4]) {
+                                             int side, int c1, bool bounded, float (&v)[NOUT][4][4]) {
+    auto quad = [&](int64_t r, int64_t c) {
+        return FUSED ? child4(X, ld, n, 2 * L, r, c, side, c1, bounded) : load4(X, ld, n, r, c, bounded);
+    };
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int64_t r = r0 + i;
         if (NOUT == 7) {
-            const float4 x11 = load4(X, ld, n, r, c0, bounded);
-            const float4 x12 = load4(X, ld, n, r, c0 + L, bounded);
-            const float4 x21 = load4(X, ld, n, r + L, c0, bounded);
-            const float4 x22 = load4(X, ld, n, r + L, c0 + L, bounded);
+            const float4 x11 = quad(r, c0);
+            const float4 x12 = quad(r, c0 + L);
+            const float4 x21 = quad(r + L, c0);
+            const float4 x22 = quad(r + L, c0 + L);
             const float* p11 = &x11.x; const float* p12 = &x12.x;
             const float* p21 = &x21.x; const float* p22 = &x22.x;
 #pragma unroll
@@ -260,7 +294,10 @@ __device__ __forceinline__ void split4(const float (&x)[4], uint2 (&planes)[P], 
     }
 }
 
-template <int NOUT, int P>
+// `node`: the level-(depth-1) node whose seven children's operands are
+// written (FUSED: formed from its parent's operand, node / 7 at level
+// depth-2, as child node % 7).
+template <int NOUT, int P, bool FUSED>
 __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t node, int64_t tile, bool bounded,
                                            uint16_t* lds) {
     const int64_t L = d.leaf;
@@ -268,16 +305,16 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
     const int64_t R0 = (tile / tiles_row) * kSplitTile, C0 = (tile % tiles_row) * kSplitTile;
     const int tid = threadIdx.x;
     const int ri = 4 * (tid >> 4), ci = 4 * (tid & 15);
-    const int plevel = (NOUT == 7) ? d.depth - 1 : 0;
+    const int plevel = FUSED ? d.depth - 2 : (NOUT == 7) ? d.depth - 1 : 0;
     const float* X;
     int64_t ld;
-    resolve(d, side, plevel, node, X, ld);
+    resolve(d, side, plevel, FUSED ? node / 7 : node, X, ld);
     uint16_t* base = reinterpret_cast<uint16_t*>(d.ws) + (side ? d.leaf_b : d.leaf_a) +
                      node * (int64_t)NOUT * P * L * L;
     const int64_t LL = L * L;
 
     float v[NOUT][4][4];
-    split_values<NOUT>(X, ld, d.n, L, R0 + ri, C0 + ci, side, bounded, v);
+    split_values<NOUT, FUSED>(X, ld, d.n, L, R0 + ri, C0 + ci, side, (int)(node % 7), bounded, v);
     const bool fp16 = d.fp16 != 0;
     const float scale =
         fp16 ? ldexpf(1.0f, reinterpret_cast<const int*>(reinterpret_cast<const float*>(d.ws) + d.scale)[2 * kScaleParts + side])
@@ -335,21 +372,30 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
     }
 }
 
-// grid.y = side.  The source is read with bounds when it is the unpadded
-// user matrix (depth <= 1 with padding).
+// grid.y = side.  From depth 2 on, the last two divide levels run here (the
+// level-(depth-2) sums are formed on the fly and never stored): the seven
+// siblings of one tile position are consecutive logical blocks, placed on
+// one XCD, so the grandparent tiles they share are re-read from its L2.  The
+// source is read with bounds when it is the unpadded user matrix.
 template <class Src, int P>
 __global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
     constexpr int R = SplitRound<P>::R;
     __shared__ __attribute__((aligned(16))) uint16_t lds[R * P * kSplitTile * kSplitLdsRow];
     int64_t local;
-    const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
+    const ProbDesc& d = src.get(src.locate(xcd_slot(blockIdx.x, gridDim.x), local));
     const int side = blockIdx.y;
     const int64_t L = d.leaf;
     const int64_t tiles = (L / kSplitTile) * (L / kSplitTile);
+    if (d.depth >= 2) {
+        const int64_t c1 = local % 7, rest = local / 7;
+        const int64_t tile = rest % tiles, node = 7 * (rest / tiles) + c1;
+        split_body<7, P, true>(d, side, node, tile, d.bounded0 && d.depth == 2, lds);
+        return;
+    }
     const int64_t node = local / tiles, tile = local - node * tiles;
-    const bool bounded = d.bounded0 && d.depth <= 1;
-    if (d.depth == 0) split_body<1, P>(d, side, node, tile, bounded, lds);
-    else split_body<7, P>(d, side, node, tile, bounded, lds);
+    const bool bounded = d.bounded0 != 0;
+    if (d.depth == 0) split_body<1, P, false>(d, side, node, tile, bounded, lds);
+    else split_body<7, P, false>(d, side, node, tile, bounded, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -6,8 +6,9 @@
 //                       level l: 5 per node (the other two operands are views
 //                       of the parent's quadrants), 7 at level 0 when the user
 //                       matrix must be zero-padded on the fly;
-//   leaf_a, leaf_b      bf16 paths: the split leaf operands (P planes each,
-//                       B side transposed), written by the last divide level;
+//   leaf_a, leaf_b      16-bit paths: the split leaf operands (P planes each,
+//                       B side transposed), written by the split, which forms
+//                       the last divide level (the last two from depth 2 on);
 //   leaf_m              the 7^k leaf products;
 //   comb[l]             combine output of level l >= 1.  These reuse the
 //                       front of the workspace: the divide outputs are dead
@@ -108,7 +109,9 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
         p.bytes = (size_t)(off > 0 ? off : 256);
         return "";
     }
-    p.fp32_levels = planes == 0 ? depth : depth - 1;
+    // 16-bit paths: the split forms the last level (from depth 2 on, the last
+    // two) on the fly, so only the levels above are stored in binary32
+    p.fp32_levels = planes == 0 ? depth : depth >= 2 ? depth - 2 : 0;
     for (int l = 0; l < p.fp32_levels; ++l) {
         const int slots = (l == 0 && p.padded) ? 7 : 5;
         const int64_t h = (p.np >> l) >> 1;
@@ -167,30 +170,35 @@ ProbDesc make_desc(const Plan& p, const float* A, const float* B, float* C, void
 
 Work plan_work(const Plan& p) {
     Work w{};
-    const double L = (double)p.leaf;
+    const double L = (double)p.leaf, E = 4.0;
     const double leaves = (double)pow7(p.depth);
     w.leaf_flops = 2.0 * L * L * L * leaves;
     const int prods = p.planes == 0 ? 1 : p.planes == 2 ? 3 : 6;
     w.mfma_flops = w.leaf_flops * prods;
     for (int l = 0; l < p.fp32_levels; ++l) {
         const double h = (double)(p.np >> l) / 2.0;
-        const double nodes = (double)pow7(l);
         // read 4 quadrants per side, write `slots` blocks per side
-        w.divide_bytes += 2.0 * nodes * (4.0 + p.div_slots[l]) * h * h * 4.0;
+        w.divide_bytes += 2.0 * (double)pow7(l) * (4.0 + p.div_slots[l]) * h * h * E;
     }
     if (p.planes > 0) {
-        // last level: read the parent's 4 quadrants (binary32), write 7 x P
-        // bf16 planes per side; depth 0 reads and writes the whole operands
-        const double nodes = p.depth > 0 ? (double)pow7(p.depth - 1) : 1.0;
-        const double in_blocks = p.depth > 0 ? 4.0 : 1.0, out_blocks = p.depth > 0 ? 7.0 : 1.0;
-        w.split_bytes = 2.0 * nodes * (in_blocks * L * L * 4.0 + out_blocks * p.planes * L * L * 2.0);
+        // per side: read the source operand once (depth >= 2: the level-
+        // (depth-2) operand of edge 4L; depth 1: the matrix, 4 L^2; depth 0:
+        // L^2), write every leaf operand as P 16-bit planes
+        const double src = p.depth >= 2 ? (double)pow7(p.depth - 2) * 16.0 : p.depth == 1 ? 4.0 : 1.0;
+        w.split_bytes = 2.0 * (src * L * L * E + leaves * p.planes * L * L * 2.0);
     }
-    for (int l = p.depth - 1; l >= 0; --l) {
+    // combine: the two deepest levels in one pass (read the 49 grandchildren,
+    // write the level-(depth-2) output), the others one level at a time
+    int l = p.depth - 1;
+    if (p.depth >= 2) {
+        w.combine_bytes += (double)pow7(p.depth - 2) * (49.0 + 16.0) * L * L * E;
+        l = p.depth - 3;
+    }
+    for (; l >= 0; --l) {
         const double h = (double)(p.np >> l) / 2.0;
-        const double nodes = (double)pow7(l);
-        w.combine_bytes += nodes * (7.0 + 4.0) * h * h * 4.0;
+        w.combine_bytes += (double)pow7(l) * (7.0 + 4.0) * h * h * E;
     }
-    if (p.pad_a >= 0) w.pad_bytes = 2.0 * ((double)p.n * p.n * 4.0 + (double)p.np * p.np * 4.0);
+    if (p.pad_a >= 0) w.pad_bytes = 2.0 * ((double)p.n * p.n * E + (double)p.np * p.np * E);
     return w;
 }
 

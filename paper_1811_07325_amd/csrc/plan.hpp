@@ -41,8 +41,9 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& out);
 // Descriptor of the plan with user/workspace pointers filled in.
 ProbDesc make_desc(const Plan& p, const float* A, const float* B, float* C, void* ws);
 
-// Algorithmic work of one multiply (for reports): leaf flops (useful, 2 L^3
-// per leaf) and the bytes the divide / split / combine phases must move.
+// Algorithmic work of one multiply (stark_plan_info): leaf flops (useful,
+// 2 L^3 per leaf; matrix-core flops count every split product) and the bytes
+// the divide / split / combine phases must move.
 struct Work {
     double leaf_flops, mfma_flops;
     double divide_bytes, split_bytes, combine_bytes, pad_bytes;

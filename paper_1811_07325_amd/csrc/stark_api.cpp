@@ -221,6 +221,12 @@ stark_status stark_plan_info(int64_t n, int depth, stark_precision prec, stark_p
     out->bytes = p.bytes;
     out->gemm_tile = p.tile;
     out->scale = p.scale;
+    const Work w = plan_work(p);
+    out->divide_bytes = w.divide_bytes + w.pad_bytes;
+    out->split_bytes = w.split_bytes;
+    out->combine_bytes = w.combine_bytes;
+    out->leaf_flops = w.leaf_flops;
+    out->mfma_flops = w.mfma_flops;
     return STARK_OK;
 }
 

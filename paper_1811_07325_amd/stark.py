@@ -84,7 +84,10 @@ class stark_plan_desc(ctypes.Structure):
                 ("leaf_a", ctypes.c_int64), ("leaf_b", ctypes.c_int64), ("leaf_m", ctypes.c_int64),
                 ("comb", ctypes.c_int64 * STARK_MAX_DEPTH),
                 ("pad_a", ctypes.c_int64), ("pad_b", ctypes.c_int64), ("bytes", ctypes.c_size_t),
-                ("gemm_tile", ctypes.c_int), ("scale", ctypes.c_int64)]
+                ("gemm_tile", ctypes.c_int), ("scale", ctypes.c_int64),
+                ("divide_bytes", ctypes.c_double), ("split_bytes", ctypes.c_double),
+                ("combine_bytes", ctypes.c_double), ("leaf_flops", ctypes.c_double),
+                ("mfma_flops", ctypes.c_double)]
 
 
 def _load() -> ctypes.CDLL:

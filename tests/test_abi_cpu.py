@@ -62,7 +62,8 @@ def test_plan_layout(S, n, depth, prec):
     L, h = d.leaf, None
     # sizes of every region, from the layout rules
     size = {}
-    fp32_levels = depth if planes == 0 else max(depth - 1, 0)
+    # 16-bit paths: the split forms the last level (the last two from depth 2)
+    fp32_levels = depth if planes == 0 else max(depth - 2, 0)
     for l in range(depth):
         if l < fp32_levels:
             h = (np_ >> l) // 2
@@ -151,3 +152,25 @@ def test_tile_class_choice(S):
     assert S.stark_plan_info(512, 2, 1).gemm_tile == 64    # 49 leaves of 128: more, smaller tiles
     assert S.stark_plan_info(2048, 1, 0).gemm_tile == 128
     assert S.stark_plan_info(384, 1, 1).gemm_tile == 64
+
+
+def test_plan_work_figures(S):
+    """Algorithmic work reported by the planner against the formulas written
+    out: BF16X3 depth 2 at n = 16384 (no binary32 level; the split reads A and
+    B once and writes 49 leaf operands as two planes; one two-level combine
+    pass) and FP32 depth 3 (three divide levels; combine levels 2 and 1 in one
+    pass, then level 0)."""
+    E, n = 4.0, 16384
+    d = S.stark_plan_info(n, 2, 1)
+    L = n // 4
+    assert d.divide_bytes == 0
+    assert d.split_bytes == 2 * (n * n * E + 49 * 2 * L * L * 2)
+    assert d.combine_bytes == (49 + 16) * L * L * E
+    assert d.leaf_flops == 49 * 2.0 * L ** 3 and d.mfma_flops == 3 * d.leaf_flops
+    d = S.stark_plan_info(n, 3, 0)
+    L = n // 8
+    div = sum(2 * 7 ** l * (4 + 5) * ((n >> l) // 2) ** 2 * E for l in range(3))
+    assert d.divide_bytes == div                       # 28.1 GB
+    assert d.split_bytes == 0
+    assert d.combine_bytes == 7 * (49 + 16) * L * L * E + 11 * (n // 2) ** 2 * E
+    assert d.mfma_flops == d.leaf_flops == 343 * 2.0 * L ** 3

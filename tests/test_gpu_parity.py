@@ -211,7 +211,8 @@ def unblock(x, L, BR=16):
 
 
 @pytest.mark.parametrize("prec,depth,n", [("bf16x3", 1, 256), ("bf16x6", 2, 256), ("bf16x3", 0, 128),
-                                          ("bf16x3", 1, 200)])
+                                          ("bf16x3", 1, 200), ("bf16x3", 2, 250), ("bf16x3", 3, 512),
+                                          ("bf16x6", 3, 500)])
 def test_split_leaf_operands_bit_exact(S, ctx, ws, prec, depth, n):
     P = {"bf16x3": 2, "bf16x6": 3}[prec]
     A = inputs.normal(n, 5)
