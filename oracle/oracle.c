@@ -32,8 +32,9 @@
  *     50).  The oracle uses C22 = M1 - M2 + M3 + M6.
  *   - Algorithm 2 recurses on (A, B); the recursion must act on the divided
  *     pairs D.  The oracle recurses on the seven (S_i, T_i) pairs.
- *   - The base case "n = threshold" / "n = 1 block" is read as: recurse
- *     exactly `depth` times; the leaf size is n_pad / 2^depth.
+ *   - The base case (size equal to a threshold in Algorithm 1, a single
+ *     block in Algorithm 2) is read as: recurse exactly `depth` times; the
+ *     leaf size is n_pad / 2^depth.
  *   - Sizes that are not 2^p (the paper defers to partitioning) are
  *     zero-padded to n_pad, a multiple of 2^depth, and the product cropped.
  *     Padding is exact: the extra rows/columns contribute only zeros.
@@ -153,14 +154,14 @@ static void strassen_rec(const double* X, int64_t ldx, const double* Y, int64_t 
                          oracle_counts* cnt)
 {
     if (levels == 0) {
-        /* Base case: "multiply A and B using naive approach". */
+        /* Base case: the classical product of the two leaf blocks. */
         classical_f64(X, ldx, Y, ldy, Z, ldz, m, top);
         cnt->leaf_products += 1;
         return;
     }
     const int64_t h = m / 2;
     const size_t hh = (size_t)h * (size_t)h;
-    /* Quadrants of the operands ("Compute A11, B11, ..., A22, B22"). */
+    /* The four quadrants of each operand (views, no copies). */
     const double *A11 = X, *A12 = X + h, *A21 = X + h * ldx, *A22 = X + h * ldx + h;
     const double *B11 = Y, *B12 = Y + h, *B21 = Y + h * ldy, *B22 = Y + h * ldy + h;
 

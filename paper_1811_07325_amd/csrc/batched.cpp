@@ -137,7 +137,9 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
         }
         add_launch(kPad, 0, 0, [&](int i) { return plans[i].pad_a >= 0 ? blocks_pad(descs[i]) : 0; });
         for (int l = 0; l < max_fp32; ++l)
-            add_launch(kDivide, l, 0, [&](int i) { return plans[i].fp32_levels > l ? blocks_divide(descs[i], l) : 0; });
+            add_launch(kDivide, l, 0, [&](int i) {
+                return plans[i].fp32_levels > l && plans[i].div_slots[l] > 0 ? blocks_divide(descs[i], l) : 0;
+            });
         if (e.fp16) {
             add_launch(kAbsmax, 0, 0, [&](int) { return (int64_t)kScaleParts; });
             add_launch(kScaleExp, 0, 0, [&](int) { return (int64_t)1; });

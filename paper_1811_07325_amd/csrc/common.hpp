@@ -74,6 +74,11 @@ __device__ __forceinline__ void resolve(const ProbDesc& d, int side, int level, 
         pw /= 7;
         const int64_t h = m >> 1;
         const int slots = d.div_slots[j];
+        if (slots == 0) {   // level j is not stored: level j+1 stores all seven operands
+            prefix = prefix * 7 + c;
+            m = h;
+            continue;
+        }
         const int s = (slots == 7) ? c : slot_of(side, c);
         if (s >= 0) {
             ptr = wsf + (side ? d.div_b[j] : d.div_a[j]) + (prefix * slots + s) * h * h;

@@ -38,6 +38,60 @@ __device__ __forceinline__ float4 load4_bounded(const float* X, int64_t n, int64
     return make_float4(v[0], v[1], v[2], v[3]);
 }
 
+__device__ __forceinline__ float4 load4(const float* X, int64_t ld, int64_t n, int64_t r, int64_t c, bool bounded) {
+    if (bounded) return load4_bounded(X, n, r, c);
+    return *reinterpret_cast<const float4*>(X + r * ld + c);
+}
+
+// Elements (r, c..c+3) of the operand of child c1 (c1 = 0..6 for M1..M7) of a
+// node whose operand X has quadrant edge H, formed exactly as k_divide forms
+// them (one binary32 add per element, same operand order), so that operand
+// need not be stored.
+__device__ __forceinline__ float4 child4(const float* X, int64_t ld, int64_t n, int64_t H, int64_t r, int64_t c,
+                                         int side, int c1, bool bounded) {
+    auto q = [&](int a, int b) { return load4(X, ld, n, r + a * H, c + b * H, bounded); };
+    if (side == 0) {
+        switch (c1) {
+            case 0: return f4add(q(0, 0), q(1, 1));
+            case 1: return f4add(q(1, 0), q(1, 1));
+            case 2: return q(0, 0);
+            case 3: return q(1, 1);
+            case 4: return f4add(q(0, 0), q(0, 1));
+            case 5: return f4sub(q(1, 0), q(0, 0));
+            default: return f4sub(q(0, 1), q(1, 1));
+        }
+    }
+    switch (c1) {
+        case 0: return f4add(q(0, 0), q(1, 1));
+        case 1: return q(0, 0);
+        case 2: return f4sub(q(0, 1), q(1, 1));
+        case 3: return f4sub(q(1, 0), q(0, 0));
+        case 4: return q(1, 1);
+        case 5: return f4add(q(0, 0), q(0, 1));
+        default: return f4add(q(1, 0), q(1, 1));
+    }
+}
+
+// Last divide level of the bf16 paths.  NOUT = 7: every node of level
+// depth-1 gives the seven operand pairs of its children (the leaves);
+// NOUT = 1 (depth 0): the root operands themselves.  Each output block (leaf
+// edge L) is written as P bf16 planes in the blocked layout of blk_offset
+// (common.hpp): A side with rows = rows of S, B side with rows = columns of T
+// (transposed), so the leaf GEMM reads both k-contiguous.
+//
+// A block covers a 64 x 64 tile of output positions; thread t owns rows
+// 4*(t/16)..+3 and columns 4*(t%16)..+3 of it, read as float4 (16 threads
+// cover a 256-byte row segment).  A side: each thread stores 8-byte pieces;
+// a tile fills 8 whole 1 KB blocks per output and plane.  B side: the tile of
+// each output and plane is transposed through LDS (rows of 64 bf16 + 8 pad)
+// and written back in 16-byte chunks of T^T rows, kSplitRound outputs at a
+// time.
+constexpr int kSplitTile = 64;
+constexpr int kSplitLdsRow = kSplitTile + 8;        // bf16 per LDS row (144 B, 16-byte aligned)
+
+template <int P> struct SplitRound { static constexpr int R = 2; };
+template <> struct SplitRound<3> { static constexpr int R = 1; };
+
 // ---------------------------------------------------------------------------
 // Zero-padded copies A -> pad_a, B -> pad_b (np x np).  grid.y = side.
 // ---------------------------------------------------------------------------
@@ -62,25 +116,43 @@ __global__ __launch_bounds__(kStreamThreads) void k_pad(Src src) {
 
 // ---------------------------------------------------------------------------
 // Divide, level l: for every node of the level, read its four quadrants once
-// and write the materialised operand blocks (5 per side, or all 7 when the
-// level-0 source is the unpadded user matrix, read with bounds so the padding
-// is formed on the fly).  grid.y = side (0: A, 1: B).
+// and write the materialised operand blocks: 5 per side, or all 7 (a) when
+// the level-0 source is the unpadded user matrix, read with bounds so the
+// padding is formed on the fly, and (b) when the level above is not stored
+// (binary32 path from depth 2 on: the last two levels in one pass), since
+// the two view operands would point into that level.  grid.y = side (0: A,
+// 1: B).
 // ---------------------------------------------------------------------------
 template <class Src>
 __global__ __launch_bounds__(kStreamThreads) void k_divide(Src src, int level) {
     int64_t local;
-    const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
+    const ProbDesc& d = src.get(src.locate(xcd_slot(blockIdx.x, gridDim.x), local));
     const int side = blockIdx.y;
     const bool bounded = (level == 0) && d.bounded0;
     const int64_t m = d.np >> level, h = m >> 1;
     const int64_t hq = h >> 2;               // float4 per quadrant row
     const int64_t q4 = h * hq;               // float4 per quadrant
     const int64_t bpn = (q4 + kStreamPerBlock - 1) / kStreamPerBlock;
-    const int64_t node = local / bpn, chunk = local - node * bpn;
-
+    // A level whose parent level is not stored forms the node's operand on
+    // the fly from the grandparent's, as child node % 7 (child4); the seven
+    // siblings of one chunk are consecutive logical blocks (one XCD, shared
+    // grandparent reads in its L2).
+    const bool fused = level > 0 && d.div_slots[level - 1] == 0;
+    int64_t node, chunk;
+    if (fused) {
+        const int64_t rest = local / 7;
+        chunk = rest % bpn;
+        node = 7 * (rest / bpn) + local % 7;
+    } else {
+        node = local / bpn;
+        chunk = local - node * bpn;
+    }
     const float* X;
     int64_t ld;
-    resolve(d, side, level, node, X, ld);
+    if (fused) resolve(d, side, level - 1, node / 7, X, ld);
+    else resolve(d, side, level, node, X, ld);
+    const bool fbounded = fused && level == 1 && d.bounded0;
+    const int c1 = (int)(node % 7);
     const int slots = d.div_slots[level];
     float4* out = reinterpret_cast<float4*>(reinterpret_cast<float*>(d.ws) +
                                             (side ? d.div_b[level] : d.div_a[level]) +
@@ -94,7 +166,12 @@ __global__ __launch_bounds__(kStreamThreads) void k_divide(Src src, int level) {
         fs[u] = f;
         if (f < q4) {
             const int64_t r = f / hq, c = (f - r * hq) * 4;
-            if (bounded) {
+            if (fused) {
+                q11[u] = child4(X, ld, d.n, 2 * h, r, c, side, c1, fbounded);
+                q12[u] = child4(X, ld, d.n, 2 * h, r, c + h, side, c1, fbounded);
+                q21[u] = child4(X, ld, d.n, 2 * h, r + h, c, side, c1, fbounded);
+                q22[u] = child4(X, ld, d.n, 2 * h, r + h, c + h, side, c1, fbounded);
+            } else if (bounded) {
                 q11[u] = load4_bounded(X, d.n, r, c);
                 q12[u] = load4_bounded(X, d.n, r, c + h);
                 q21[u] = load4_bounded(X, d.n, r + h, c);
@@ -183,60 +260,6 @@ __device__ __forceinline__ float load1(const float* X, int64_t ld, int64_t n, in
     if (bounded) return (r < n && c < n) ? X[r * n + c] : 0.0f;
     return X[r * ld + c];
 }
-
-__device__ __forceinline__ float4 load4(const float* X, int64_t ld, int64_t n, int64_t r, int64_t c, bool bounded) {
-    if (bounded) return load4_bounded(X, n, r, c);
-    return *reinterpret_cast<const float4*>(X + r * ld + c);
-}
-
-// Elements (r, c..c+3) of the operand of child c1 (c1 = 0..6 for M1..M7) of a
-// node whose operand X has quadrant edge H, formed exactly as k_divide forms
-// them (one binary32 add per element, same operand order), so that operand
-// need not be stored.
-__device__ __forceinline__ float4 child4(const float* X, int64_t ld, int64_t n, int64_t H, int64_t r, int64_t c,
-                                         int side, int c1, bool bounded) {
-    auto q = [&](int a, int b) { return load4(X, ld, n, r + a * H, c + b * H, bounded); };
-    if (side == 0) {
-        switch (c1) {
-            case 0: return f4add(q(0, 0), q(1, 1));
-            case 1: return f4add(q(1, 0), q(1, 1));
-            case 2: return q(0, 0);
-            case 3: return q(1, 1);
-            case 4: return f4add(q(0, 0), q(0, 1));
-            case 5: return f4sub(q(1, 0), q(0, 0));
-            default: return f4sub(q(0, 1), q(1, 1));
-        }
-    }
-    switch (c1) {
-        case 0: return f4add(q(0, 0), q(1, 1));
-        case 1: return q(0, 0);
-        case 2: return f4sub(q(0, 1), q(1, 1));
-        case 3: return f4sub(q(1, 0), q(0, 0));
-        case 4: return q(1, 1);
-        case 5: return f4add(q(0, 0), q(0, 1));
-        default: return f4add(q(1, 0), q(1, 1));
-    }
-}
-
-// Last divide level of the bf16 paths.  NOUT = 7: every node of level
-// depth-1 gives the seven operand pairs of its children (the leaves);
-// NOUT = 1 (depth 0): the root operands themselves.  Each output block (leaf
-// edge L) is written as P bf16 planes in the blocked layout of blk_offset
-// (common.hpp): A side with rows = rows of S, B side with rows = columns of T
-// (transposed), so the leaf GEMM reads both k-contiguous.
-//
-// A block covers a 64 x 64 tile of output positions; thread t owns rows
-// 4*(t/16)..+3 and columns 4*(t%16)..+3 of it, read as float4 (16 threads
-// cover a 256-byte row segment).  A side: each thread stores 8-byte pieces;
-// a tile fills 8 whole 1 KB blocks per output and plane.  B side: the tile of
-// each output and plane is transposed through LDS (rows of 64 bf16 + 8 pad)
-// and written back in 16-byte chunks of T^T rows, kSplitRound outputs at a
-// time.
-constexpr int kSplitTile = 64;
-constexpr int kSplitLdsRow = kSplitTile + 8;        // bf16 per LDS row (144 B, 16-byte aligned)
-
-template <int P> struct SplitRound { static constexpr int R = 2; };
-template <> struct SplitRound<3> { static constexpr int R = 1; };
 
 // v[o][i][e]: output o at tile row i, column e of this thread's 4 x 4 piece.
 // FUSED: X is the operand of the grandparent (edge 4L) and the parent's

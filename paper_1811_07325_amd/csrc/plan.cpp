@@ -5,12 +5,16 @@
 //   div_a[l], div_b[l]  binary32 operand blocks written by the divide of
 //                       level l: 5 per node (the other two operands are views
 //                       of the parent's quadrants), 7 at level 0 when the user
-//                       matrix must be zero-padded on the fly;
+//                       matrix must be zero-padded on the fly and 7 at the
+//                       last level of the binary32 path from depth 2 on,
+//                       whose divide also forms level depth-2 (not stored);
 //   leaf_a, leaf_b      16-bit paths: the split leaf operands (P planes each,
 //                       B side transposed), written by the split, which forms
 //                       the last divide level (the last two from depth 2 on);
 //   leaf_m              the 7^k leaf products;
-//   comb[l]             combine output of level l >= 1.  These reuse the
+//   comb[l]             combine output of level 1 <= l <= depth-2 (level
+//                       depth-1 is folded into the pass of level depth-2).
+//                       These reuse the
 //                       front of the workspace: the divide outputs are dead
 //                       once the leaf products are formed, and comb[l] never
 //                       overlaps comb[l+1] (read while comb[l] is written).
@@ -113,7 +117,11 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
     // two) on the fly, so only the levels above are stored in binary32
     p.fp32_levels = planes == 0 ? depth : depth >= 2 ? depth - 2 : 0;
     for (int l = 0; l < p.fp32_levels; ++l) {
-        const int slots = (l == 0 && p.padded) ? 7 : 5;
+        // binary32 path from depth 2 on: level depth-2 is formed on the fly by
+        // the divide of level depth-1, which then stores all seven operands
+        if (planes == 0 && depth >= 2 && l == depth - 2) continue;
+        const bool all7 = (l == 0 && p.padded) || (planes == 0 && depth >= 2 && l == depth - 1);
+        const int slots = all7 ? 7 : 5;
         const int64_t h = (p.np >> l) >> 1;
         const int64_t sz = (int64_t)slots * pow7(l) * h * h * 4;
         p.div_slots[l] = slots;
@@ -129,7 +137,8 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
     p.leaf_m = off;
     off = align256(off + pow7(depth) * p.leaf * p.leaf * 4);
     int64_t c = p.scale >= 0 ? align256(p.scale + (2 * kScaleParts + 2) * 4) : 0;
-    for (int l = depth - 1; l >= 1; --l) {
+    // level depth-1 is combined together with depth-2 and never stored
+    for (int l = depth - 2; l >= 1; --l) {
         const int64_t m = p.np >> l;
         p.comb[l] = c;
         c = align256(c + pow7(l) * m * m * 4);
@@ -176,9 +185,14 @@ Work plan_work(const Plan& p) {
     const int prods = p.planes == 0 ? 1 : p.planes == 2 ? 3 : 6;
     w.mfma_flops = w.leaf_flops * prods;
     for (int l = 0; l < p.fp32_levels; ++l) {
+        if (p.div_slots[l] == 0) continue;
         const double h = (double)(p.np >> l) / 2.0;
-        // read 4 quadrants per side, write `slots` blocks per side
-        w.divide_bytes += 2.0 * (double)pow7(l) * (4.0 + p.div_slots[l]) * h * h * E;
+        // per side: read the 4 quadrants of every node (a level formed from
+        // the unstored level above reads each grandparent operand once
+        // instead), write `slots` blocks per node
+        const double reads = (l > 0 && p.div_slots[l - 1] == 0) ? (double)pow7(l - 1) * 16.0 * h * h
+                                                                : (double)pow7(l) * 4.0 * h * h;
+        w.divide_bytes += 2.0 * (reads + (double)pow7(l) * p.div_slots[l] * h * h) * E;
     }
     if (p.planes > 0) {
         // per side: read the source operand once (depth >= 2: the level-

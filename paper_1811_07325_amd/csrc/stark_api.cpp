@@ -49,7 +49,7 @@ stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned
     if (mask & STARK_PHASE_DIVIDE) {
         if (p.pad_a >= 0) STK_HIP(launch_pad(src, blocks_pad(d), st));
         for (int l = 0; l < p.fp32_levels; ++l)
-            STK_HIP(launch_divide(src, l, blocks_divide(d, l), st));
+            if (p.div_slots[l] > 0) STK_HIP(launch_divide(src, l, blocks_divide(d, l), st));
         if (p.scale >= 0) {
             STK_HIP(launch_absmax(src, kScaleParts, st));
             STK_HIP(launch_scale_exp(src, 1, st));

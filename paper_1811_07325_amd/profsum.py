@@ -8,6 +8,7 @@
 * `traffic`: leaf-GEMM HBM bytes per launch from FETCH_SIZE and WRITE_SIZE
   runs, each scaled by what the same counter reads for a plain copy of known
   size (the counters report KiB per dispatch);
+* `mfma_md`: matrix-core busy fraction, hardware flops and clock of a kernel;
 * `source_digest`: SHA-256 of the kernel source the counters were taken on,
   so a reader can tell when they are stale.
 
@@ -15,6 +16,7 @@ Command line:
   python -m paper_1811_07325_amd.profsum stats <kernel_stats.csv> <title> <command>
   python -m paper_1811_07325_amd.profsum traffic <key> <copy_fetch.csv> <copy_write.csv>
       <copy_bytes> <gemm_fetch.csv> <gemm_write.csv> <kernel substring> <command...>
+  python -m paper_1811_07325_amd.profsum mfma <counters.csv> <kernel substring> <title> <command lines...>
   python -m paper_1811_07325_amd.profsum table <copy_fetch.csv> <copy_write.csv> <copy_bytes>
       <run_fetch.csv> <run_write.csv> <kernel,substrings> <title> <command lines...>
 """
@@ -104,6 +106,28 @@ def traffic_table_md(copy_fetch: str, copy_write: str, copy_bytes: float, run_fe
     return "\n".join(out) + "\n"
 
 
+def mfma_md(path: str, name_part: str, simds: int, xccs: int, title: str, commands: list[str]) -> str:
+    """Matrix-core counters of one kernel per dispatch: hardware flops
+    (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512), MFMA busy fraction
+    (SQ_VALU_MFMA_BUSY_CYCLES summed over SIMDs / (active cycles per XCC x
+    SIMDs); GRBM_GUI_ACTIVE is reported summed over the XCCs) and the average
+    shader clock over the dispatch (active cycles per XCC / duration)."""
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if name_part in r["Kernel_Name"]:
+            e = per.setdefault(int(r["Dispatch_Id"]), {})
+            e[r["Counter_Name"]] = float(r["Counter_Value"])
+            e["ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    out = [f"# {title}", "", "Commands (from the repository root, on one MI355X):", "", "```"] + commands + [
+        "```", "", "| dispatch | ms | MFMA flops | MFMA busy | clock (GHz) |", "|---:|---:|---:|---:|---:|"]
+    for k in sorted(per):
+        e = per[k]
+        cyc = e["GRBM_GUI_ACTIVE"] / xccs
+        out.append(f"| {k} | {e['ns'] / 1e6:.3f} | {e['SQ_INSTS_VALU_MFMA_MOPS_BF16'] * 512:.4e} | "
+                   f"{e['SQ_VALU_MFMA_BUSY_CYCLES'] / (cyc * simds):.3f} | {cyc / e['ns']:.2f} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv: list[str]) -> int:
     if argv[0] == "stats":
         sys.stdout.write(kernel_stats_md(argv[1], argv[2], argv[3]))
@@ -115,6 +139,10 @@ def main(argv: list[str]) -> int:
         print(f"# command: {' '.join(argv[8:])}")
         print("# key fetch_bytes write_bytes factor_fetch factor_write")
         print(f"{key} {t['fetch_bytes']:.6e} {t['write_bytes']:.6e} {t['factor_fetch']:.4f} {t['factor_write']:.4f}")
+        return 0
+    if argv[0] == "mfma":
+        path, part, title = argv[1:4]
+        sys.stdout.write(mfma_md(path, part, 1024, 8, title, argv[4:]))
         return 0
     if argv[0] == "table":
         cfe, cwr, cb, rfe, rwr, kernels, title = argv[1:8]

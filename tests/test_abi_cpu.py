@@ -64,14 +64,17 @@ def test_plan_layout(S, n, depth, prec):
     size = {}
     # 16-bit paths: the split forms the last level (the last two from depth 2)
     fp32_levels = depth if planes == 0 else max(depth - 2, 0)
+    # binary32 from depth 2 on: level depth-2 is formed on the fly by the
+    # divide of level depth-1, which stores all seven operands
+    unstored = depth - 2 if (planes == 0 and depth >= 2) else None
     for l in range(depth):
-        if l < fp32_levels:
+        if l < fp32_levels and l != unstored:
             h = (np_ >> l) // 2
-            slots = 7 if (l == 0 and np_ != n) else 5
+            slots = 7 if (l == 0 and np_ != n) or (unstored is not None and l == depth - 1) else 5
             assert d.div_slots[l] == slots
             size["div_a%d" % l] = size["div_b%d" % l] = slots * 7 ** l * h * h * 4
         else:
-            assert d.div_a[l] == -1
+            assert d.div_a[l] == -1 and d.div_slots[l] == 0
     if planes:
         nodes_out = 7 ** depth
         size["leaf_a"] = size["leaf_b"] = nodes_out * planes * L * L * 2
@@ -95,7 +98,9 @@ def test_plan_layout(S, n, depth, prec):
     if last:
         assert last[1] + size[last[0]] <= d.bytes
     # combine outputs: disjoint from each other and from the leaf products
-    comb = [(l, d.comb[l]) for l in range(1, depth)]
+    comb = [(l, d.comb[l]) for l in range(1, depth - 1)]
+    if depth >= 2:
+        assert d.comb[depth - 1] == -1      # combined together with level depth-2
     ends = []
     for l, off in comb:
         m = np_ >> l
@@ -110,11 +115,12 @@ def test_plan_layout(S, n, depth, prec):
 
 
 def test_workspace_formula_fp32(S):
-    """Unpadded binary32: 2.5 S_k N + (7/4)^k N floats (S_k = sum_{l<k} (7/4)^l)."""
+    """Unpadded binary32, depth k >= 2: levels 0..k-3 store 5 blocks per node
+    and side, (5/4)(7/4)^l N floats each; level k-2 is not stored; level k-1
+    stores 7, (7/4)^k N; plus the (7/4)^k N leaf products."""
     for n, k in [(4096, 3), (16384, 2), (8192, 4)]:
         N = n * n
-        Sk = sum((7 / 4) ** l for l in range(k))
-        expect = (2.5 * Sk + (7 / 4) ** k) * N * 4
+        expect = (2 * sum(1.25 * (7 / 4) ** l for l in range(k - 2)) + 2 * (7 / 4) ** k + (7 / 4) ** k) * N * 4
         got = S.stark_workspace_size(n, k, 0)
         assert abs(got - expect) <= 256 * (4 * k + 2)
 
@@ -158,8 +164,8 @@ def test_plan_work_figures(S):
     """Algorithmic work reported by the planner against the formulas written
     out: BF16X3 depth 2 at n = 16384 (no binary32 level; the split reads A and
     B once and writes 49 leaf operands as two planes; one two-level combine
-    pass) and FP32 depth 3 (three divide levels; combine levels 2 and 1 in one
-    pass, then level 0)."""
+    pass) and FP32 depth 3 (divide level 0, then levels 1 and 2 in one pass;
+    combine levels 2 and 1 in one pass, then level 0)."""
     E, n = 4.0, 16384
     d = S.stark_plan_info(n, 2, 1)
     L = n // 4
@@ -169,8 +175,10 @@ def test_plan_work_figures(S):
     assert d.leaf_flops == 49 * 2.0 * L ** 3 and d.mfma_flops == 3 * d.leaf_flops
     d = S.stark_plan_info(n, 3, 0)
     L = n // 8
-    div = sum(2 * 7 ** l * (4 + 5) * ((n >> l) // 2) ** 2 * E for l in range(3))
-    assert d.divide_bytes == div                       # 28.1 GB
+    # level 0 as usual; level 2 formed from the level-1 operands read once
+    # (7 of edge n/2), all seven of its operands stored
+    div = 2 * (4 + 5) * (n // 2) ** 2 * E + 2 * (7 * (n // 2) ** 2 + 49 * 7 * (n // 8) ** 2) * E
+    assert d.divide_bytes == div                       # 20.1 GB
     assert d.split_bytes == 0
     assert d.combine_bytes == 7 * (49 + 16) * L * L * E + 11 * (n // 2) ** 2 * E
     assert d.mfma_flops == d.leaf_flops == 343 * 2.0 * L ** 3

@@ -164,9 +164,11 @@ def ws_view(ws, offset, count, dtype):
     return ws[offset:offset + count * itemsize].cpu().numpy().view(dtype)
 
 
-@pytest.mark.parametrize("n", [256, 250])
-def test_divide_levels_bit_exact(S, ctx, ws, n):
-    depth = 2
+@pytest.mark.parametrize("n,depth", [(256, 2), (250, 2), (512, 3), (500, 3)])
+def test_divide_levels_bit_exact(S, ctx, ws, n, depth):
+    """Every stored binary32 divide level against the oracle's divide steps.
+    From depth 2 on the level above the last is formed on the fly and not
+    stored, and the last level stores all seven operands."""
     A = inputs.uniform(n, 3)
     B = inputs.uniform(n, 4)
     dA, dB = dev(A), dev(B)
@@ -178,22 +180,24 @@ def test_divide_levels_bit_exact(S, ctx, ws, n):
     Ap = np.zeros((np_, np_), np.float32); Ap[:n, :n] = A
     Bp = np.zeros((np_, np_), np.float32); Bp[:n, :n] = B
     sA5, sB5 = [0, 1, 4, 5, 6], [0, 2, 3, 5, 6]
-    # level 0
-    S0, T0 = oracle.divide_f32(Ap, Bp)
-    h0 = np_ // 2
-    slots0 = d.div_slots[0]
-    ga = ws_view(ws, d.div_a[0], slots0 * h0 * h0, np.float32).reshape(slots0, h0, h0)
-    gb = ws_view(ws, d.div_b[0], slots0 * h0 * h0, np.float32).reshape(slots0, h0, h0)
-    ia, ib = (list(range(7)), list(range(7))) if slots0 == 7 else (sA5, sB5)
-    assert np.array_equal(ga, S0[ia]) and np.array_equal(gb, T0[ib])
-    # level 1: node c has operands (S0[c], T0[c])
-    h1 = h0 // 2
-    ga1 = ws_view(ws, d.div_a[1], 7 * 5 * h1 * h1, np.float32).reshape(7, 5, h1, h1)
-    gb1 = ws_view(ws, d.div_b[1], 7 * 5 * h1 * h1, np.float32).reshape(7, 5, h1, h1)
-    for c in range(7):
-        S1, T1 = oracle.divide_f32(S0[c], T0[c])
-        assert np.array_equal(ga1[c], S1[sA5]), c
-        assert np.array_equal(gb1[c], T1[sB5]), c
+    assert d.div_slots[depth - 2] == 0 and d.div_slots[depth - 1] == 7
+    Xs, Ys = [Ap], [Bp]           # operands of the nodes of level l, in node order
+    for lvl in range(depth):
+        nx, ny = [], []
+        slots = d.div_slots[lvl]
+        h = (np_ >> lvl) // 2
+        if slots:
+            ga = ws_view(ws, d.div_a[lvl], 7 ** lvl * slots * h * h, np.float32).reshape(-1, slots, h, h)
+            gb = ws_view(ws, d.div_b[lvl], 7 ** lvl * slots * h * h, np.float32).reshape(-1, slots, h, h)
+        ia, ib = (list(range(7)), list(range(7))) if slots == 7 else (sA5, sB5)
+        for node, (X, Y) in enumerate(zip(Xs, Ys)):
+            Sx, Ty = oracle.divide_f32(X, Y)
+            if slots:
+                assert np.array_equal(ga[node], Sx[ia]), (lvl, node)
+                assert np.array_equal(gb[node], Ty[ib]), (lvl, node)
+            nx.extend(Sx)
+            ny.extend(Ty)
+        Xs, Ys = nx, ny
 
 
 def unblock(x, L, BR=16):
