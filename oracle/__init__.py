@@ -73,6 +73,12 @@ def _load():
     lib.oracle_set_mutation.argtypes = [ctypes.c_int]
     lib.oracle_strassen_model_f32.argtypes = [P, P, P, I64, ctypes.c_int, I64, ctypes.c_int]
     lib.oracle_strassen_model_f32.restype = ctypes.c_int
+    lib.oracle_model_f32.argtypes = [P, P, P, I64, ctypes.c_int, I64, ctypes.c_int, ctypes.c_int]
+    lib.oracle_model_f32.restype = ctypes.c_int
+    lib.oracle_winograd_f64.argtypes = [P, P, P, I64, ctypes.c_int, I64, ctypes.POINTER(Counts)]
+    lib.oracle_winograd_f64.restype = ctypes.c_int
+    lib.oracle_divide_f32_w.argtypes = [P, I64, P, I64, I64, P, P]
+    lib.oracle_combine_f32_w.argtypes = [P, I64, P, I64]
     lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_f16_scale_exp.argtypes = [P, I64, ctypes.c_int]
     lib.oracle_f16_scale_exp.restype = ctypes.c_int
@@ -153,7 +159,28 @@ def strassen_f64(A, B, depth: int, n_pad: int | None = None, with_counts: bool =
     return C
 
 
-def divide_f32(X, Y):
+VARIANTS = ("strassen", "winograd")
+
+
+def winograd_f64(A, B, depth: int, n_pad: int | None = None, with_counts: bool = False):
+    """C = A B by `depth` levels of Winograd's variant (15 additions per
+    node) on zero-padded operands, FP64."""
+    A, B = _f64(A), _f64(B)
+    n = A.shape[0]
+    assert A.shape == (n, n) and B.shape == (n, n)
+    if n_pad is None:
+        n_pad = padded_size(n, depth)
+    C = np.empty((n, n), dtype=np.float64)
+    cnt = Counts()
+    rc = _load().oracle_winograd_f64(_ptr(A), _ptr(B), _ptr(C), n, depth, n_pad, ctypes.byref(cnt))
+    if rc != 0:
+        raise ValueError(f"oracle_winograd_f64: bad arguments n={n} depth={depth} n_pad={n_pad}")
+    if with_counts:
+        return C, cnt
+    return C
+
+
+def divide_f32(X, Y, variant: str = "strassen"):
     """Operand pairs (S_i, T_i), i = 1..7, of one node in binary32 -> (7,h,h) x2."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     Y = np.ascontiguousarray(Y, dtype=np.float32)
@@ -162,17 +189,21 @@ def divide_f32(X, Y):
     h = m // 2
     S = np.empty((7, h, h), dtype=np.float32)
     T = np.empty((7, h, h), dtype=np.float32)
-    _load().oracle_divide_f32(_ptr(X), m, _ptr(Y), m, m, _ptr(S), _ptr(T))
+    fn = _load().oracle_divide_f32_w if variant == "winograd" else _load().oracle_divide_f32
+    assert variant in VARIANTS
+    fn(_ptr(X), m, _ptr(Y), m, m, _ptr(S), _ptr(T))
     return S, T
 
 
-def combine_f32(M) -> np.ndarray:
+def combine_f32(M, variant: str = "strassen") -> np.ndarray:
     """C (2h x 2h) from the seven products M (7,h,h) in binary32."""
     M = np.ascontiguousarray(M, dtype=np.float32)
     assert M.ndim == 3 and M.shape[0] == 7 and M.shape[1] == M.shape[2]
+    assert variant in VARIANTS
     h = M.shape[1]
     C = np.empty((2 * h, 2 * h), dtype=np.float32)
-    _load().oracle_combine_f32(_ptr(M), h, _ptr(C), 2 * h)
+    fn = _load().oracle_combine_f32_w if variant == "winograd" else _load().oracle_combine_f32
+    fn(_ptr(M), h, _ptr(C), 2 * h)
     return C
 
 
@@ -207,17 +238,20 @@ def split_f16(x, e: int) -> np.ndarray:
     return out
 
 
-def strassen_model_f32(A, B, depth: int, mode: str, n_pad: int | None = None) -> np.ndarray:
-    """Arithmetic model of the GPU path: binary32 divide/combine, leaf products
-    exact in binary64 from the leaf operands as seen by `mode` ("fp32",
-    "bf16x3", "bf16x6", "fp16x3"), rounded to binary32.  Returns float32 n x n."""
+def strassen_model_f32(A, B, depth: int, mode: str, n_pad: int | None = None,
+                       variant: str = "strassen") -> np.ndarray:
+    """Arithmetic model of the GPU path: binary32 divide/combine (Algorithm 1
+    or Winograd's variant), leaf products exact in binary64 from the leaf
+    operands as seen by `mode` ("fp32", "bf16x3", "bf16x6", "fp16x3"),
+    rounded to binary32.  Returns float32 n x n."""
     A = np.ascontiguousarray(A, dtype=np.float32)
     B = np.ascontiguousarray(B, dtype=np.float32)
     n = A.shape[0]
     if n_pad is None:
         n_pad = padded_size(n, depth)
     C = np.empty((n, n), dtype=np.float32)
-    rc = _load().oracle_strassen_model_f32(_ptr(A), _ptr(B), _ptr(C), n, depth, n_pad, MODEL_MODES[mode])
+    rc = _load().oracle_model_f32(_ptr(A), _ptr(B), _ptr(C), n, depth, n_pad, MODEL_MODES[mode],
+                                  VARIANTS.index(variant))
     if rc != 0:
         raise ValueError("oracle_strassen_model_f32: bad arguments")
     return C

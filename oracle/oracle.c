@@ -41,6 +41,19 @@
  *   - The order of the combine additions is left to right as printed:
  *     C11 = ((M1 + M4) - M5) + M7, C22 = ((M1 - M2) + M3) + M6.
  *
+ * Winograd's variant (not in the paper; the "next" variant of the hot path):
+ * the same seven-product recursion with 15 block additions per node instead
+ * of 18, in the form published by S. Winograd (1971) and used by Douglas et
+ * al. (1994) and Boyer et al. (2009):
+ *   S1 = A21 + A22, S2 = S1 - A11, S3 = A11 - A21, S4 = A12 - S2,
+ *   T1 = B12 - B11, T2 = B22 - T1, T3 = B22 - B12, T4 = T2 - B21,
+ *   M1 = A11 B11, M2 = A12 B21, M3 = S4 B22, M4 = A22 T4,
+ *   M5 = S1 T1, M6 = S2 T2, M7 = S3 T3,
+ *   U2 = M1 + M6, U3 = U2 + M7,
+ *   C11 = M1 + M2, C12 = (U2 + M5) + M3, C21 = U3 - M4, C22 = U3 + M5.
+ * Its pins are the same kinds: brute force, a hand-computed 2x2 example,
+ * 15 additions per node, planted mistakes.
+ *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math:
  * every operation below is a plain IEEE operation in the written order).
  */
@@ -267,6 +280,93 @@ int oracle_strassen_f64(const double* A, const double* B, double* C, int64_t n,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Winograd's variant in binary64 (definitions in the header).              */
+/* ------------------------------------------------------------------------ */
+static void winograd_rec(const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                         double* Z, int64_t ldz, int64_t m, int levels, int top,
+                         oracle_counts* cnt)
+{
+    if (levels == 0) {
+        classical_f64(X, ldx, Y, ldy, Z, ldz, m, top);
+        cnt->leaf_products += 1;
+        return;
+    }
+    const int64_t h = m / 2;
+    const size_t hh = (size_t)h * (size_t)h;
+    const double *A11 = X, *A12 = X + h, *A21 = X + h * ldx, *A22 = X + h * ldx + h;
+    const double *B11 = Y, *B12 = Y + h, *B21 = Y + h * ldy, *B22 = Y + h * ldy + h;
+    double* S = (double*)malloc(4 * hh * sizeof(double));   /* S1..S4 */
+    double* T = (double*)malloc(4 * hh * sizeof(double));   /* T1..T4 */
+    double* M = (double*)malloc(7 * hh * sizeof(double));
+    double *S1 = S, *S2 = S + hh, *S3 = S + 2 * hh, *S4 = S + 3 * hh;
+    double *T1 = T, *T2 = T + hh, *T3 = T + 2 * hh, *T4 = T + 3 * hh;
+    const int lv = levels - 1;
+    cnt->internal_nodes += 1;
+
+    block_addsub(S1, A21, ldx, A22, ldx, +1, h);
+    block_addsub(S2, S1, h, A11, ldx, -1, h);
+    block_addsub(S3, A11, ldx, A21, ldx, -1, h);
+    if (g_mutation == 5) /* mistake: S4 taken from S1 instead of S2 */
+        block_addsub(S4, A12, ldx, S1, h, -1, h);
+    else
+        block_addsub(S4, A12, ldx, S2, h, -1, h);
+    block_addsub(T1, B12, ldy, B11, ldy, -1, h);
+    block_addsub(T2, B22, ldy, T1, h, -1, h);
+    block_addsub(T3, B22, ldy, B12, ldy, -1, h);
+    block_addsub(T4, T2, h, B21, ldy, -1, h);
+
+    winograd_rec(A11, ldx, B11, ldy, M, h, h, lv, 0, cnt);
+    winograd_rec(A12, ldx, B21, ldy, M + hh, h, h, lv, 0, cnt);
+    winograd_rec(S4, h, B22, ldy, M + 2 * hh, h, h, lv, 0, cnt);
+    winograd_rec(A22, ldx, T4, h, M + 3 * hh, h, h, lv, 0, cnt);
+    winograd_rec(S1, h, T1, h, M + 4 * hh, h, h, lv, 0, cnt);
+    winograd_rec(S2, h, T2, h, M + 5 * hh, h, h, lv, 0, cnt);
+    winograd_rec(S3, h, T3, h, M + 6 * hh, h, h, lv, 0, cnt);
+    cnt->uses_a[0] += 1; cnt->uses_a[1] += 1; cnt->uses_a[3] += 1;   /* direct operands */
+    cnt->uses_b[0] += 1; cnt->uses_b[2] += 1; cnt->uses_b[3] += 1;
+
+    /* 8 operand additions above, 7 below: 15 per node. */
+    cnt->block_additions += 15;
+    double *C11 = Z, *C12 = Z + h, *C21 = Z + h * ldz, *C22 = Z + h * ldz + h;
+    for (int64_t i = 0; i < h; ++i) {
+        for (int64_t j = 0; j < h; ++j) {
+            const size_t q = (size_t)i * h + j;
+            const double m1 = M[q], m2 = M[hh + q], m3 = M[2 * hh + q], m4 = M[3 * hh + q];
+            const double m5 = M[4 * hh + q], m6 = M[5 * hh + q], m7 = M[6 * hh + q];
+            const double u2 = m1 + m6, u3 = u2 + m7;
+            C11[i * ldz + j] = m1 + m2;
+            C12[i * ldz + j] = (u2 + m5) + m3;
+            C21[i * ldz + j] = (g_mutation == 6) ? u3 + m4 : u3 - m4;   /* mistake 6: sign of M4 */
+            C22[i * ldz + j] = u3 + m5;
+        }
+    }
+    free(S); free(T); free(M);
+}
+
+/* As oracle_strassen_f64, with Winograd's variant at every level. */
+int oracle_winograd_f64(const double* A, const double* B, double* C, int64_t n,
+                        int depth, int64_t n_pad, oracle_counts* cnt)
+{
+    oracle_counts local;
+    if (!cnt) cnt = &local;
+    memset(cnt, 0, sizeof(*cnt));
+    if (n <= 0 || depth < 0 || depth > 20 || n_pad < n || (n_pad % ((int64_t)1 << depth)) != 0)
+        return -1;
+    const size_t N = (size_t)n_pad * (size_t)n_pad;
+    double* Ap = (double*)calloc(N, sizeof(double));
+    double* Bp = (double*)calloc(N, sizeof(double));
+    double* Cp = (double*)calloc(N, sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        memcpy(Ap + i * n_pad, A + i * n, (size_t)n * sizeof(double));
+        memcpy(Bp + i * n_pad, B + i * n, (size_t)n * sizeof(double));
+    }
+    winograd_rec(Ap, n_pad, Bp, n_pad, Cp, n_pad, n_pad, depth, 1, cnt);
+    for (int64_t i = 0; i < n; ++i) memcpy(C + i * n, Cp + i * n_pad, (size_t)n * sizeof(double));
+    free(Ap); free(Bp); free(Cp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One divide step and one combine step in binary32, for bit-exact checks    */
 /* of the GPU's per-level kernels.                                           */
 /* ------------------------------------------------------------------------ */
@@ -313,6 +413,52 @@ void oracle_combine_f32(const float* M, int64_t h, float* C, int64_t ldc)
             C[i * ldc + j + h] = m3 + m5;
             C[(i + h) * ldc + j] = m2 + m4;
             C[(i + h) * ldc + j + h] = ((m1 - m2) + m3) + m6;
+        }
+    }
+}
+
+/* Winograd's variant, one divide step in binary32: S[i], T[i] the operands
+ * of M_{i+1} in product order (A11, A12, S4, A22, S1, S2, S3 and B11, B21,
+ * B22, T4, T1, T2, T3), each sum rounded once in the order of the header. */
+void oracle_divide_f32_w(const float* X, int64_t ldx, const float* Y, int64_t ldy, int64_t m,
+                         float* S, float* T)
+{
+    const int64_t h = m / 2;
+    const size_t hh = (size_t)h * (size_t)h;
+    for (int64_t i = 0; i < h; ++i) {
+        for (int64_t j = 0; j < h; ++j) {
+            const float a11 = X[i * ldx + j], a12 = X[i * ldx + j + h];
+            const float a21 = X[(i + h) * ldx + j], a22 = X[(i + h) * ldx + j + h];
+            const float b11 = Y[i * ldy + j], b12 = Y[i * ldy + j + h];
+            const float b21 = Y[(i + h) * ldy + j], b22 = Y[(i + h) * ldy + j + h];
+            const float s1 = a21 + a22, s2 = s1 - a11, s3 = a11 - a21, s4 = a12 - s2;
+            const float t1 = b12 - b11, t2 = b22 - t1, t3 = b22 - b12, t4 = t2 - b21;
+            const size_t q = (size_t)i * h + j;
+            S[0 * hh + q] = a11;  T[0 * hh + q] = b11;   /* M1 */
+            S[1 * hh + q] = a12;  T[1 * hh + q] = b21;   /* M2 */
+            S[2 * hh + q] = s4;   T[2 * hh + q] = b22;   /* M3 */
+            S[3 * hh + q] = a22;  T[3 * hh + q] = t4;    /* M4 */
+            S[4 * hh + q] = s1;   T[4 * hh + q] = t1;    /* M5 */
+            S[5 * hh + q] = s2;   T[5 * hh + q] = t2;    /* M6 */
+            S[6 * hh + q] = s3;   T[6 * hh + q] = t3;    /* M7 */
+        }
+    }
+}
+
+/* Winograd's variant, one combine step in binary32 (order of the header). */
+void oracle_combine_f32_w(const float* M, int64_t h, float* C, int64_t ldc)
+{
+    const size_t hh = (size_t)h * (size_t)h;
+    for (int64_t i = 0; i < h; ++i) {
+        for (int64_t j = 0; j < h; ++j) {
+            const size_t q = (size_t)i * h + j;
+            const float m1 = M[q], m2 = M[hh + q], m3 = M[2 * hh + q], m4 = M[3 * hh + q];
+            const float m5 = M[4 * hh + q], m6 = M[5 * hh + q], m7 = M[6 * hh + q];
+            const float u2 = m1 + m6, u3 = u2 + m7;
+            C[i * ldc + j] = m1 + m2;
+            C[i * ldc + j + h] = (u2 + m5) + m3;
+            C[(i + h) * ldc + j] = u3 - m4;
+            C[(i + h) * ldc + j + h] = u3 + m5;
         }
     }
 }
@@ -462,7 +608,7 @@ static void leaf_model(const float* X, int64_t ldx, const float* Y, int64_t ldy,
 }
 
 static void model_rec(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* Z, int64_t ldz,
-                      int64_t m, int levels, int mode)
+                      int64_t m, int levels, int mode, int variant)
 {
     if (levels == 0) {
         leaf_model(X, ldx, Y, ldy, Z, ldz, m, mode);
@@ -473,19 +619,23 @@ static void model_rec(const float* X, int64_t ldx, const float* Y, int64_t ldy, 
     float* S = (float*)malloc(7 * hh * sizeof(float));
     float* T = (float*)malloc(7 * hh * sizeof(float));
     float* M = (float*)malloc(7 * hh * sizeof(float));
-    oracle_divide_f32(X, ldx, Y, ldy, m, S, T);
-    for (int i = 0; i < 7; ++i) model_rec(S + i * hh, h, T + i * hh, h, M + i * hh, h, h, levels - 1, mode);
-    oracle_combine_f32(M, h, Z, ldz);
+    if (variant) oracle_divide_f32_w(X, ldx, Y, ldy, m, S, T);
+    else oracle_divide_f32(X, ldx, Y, ldy, m, S, T);
+    for (int i = 0; i < 7; ++i)
+        model_rec(S + i * hh, h, T + i * hh, h, M + i * hh, h, h, levels - 1, mode, variant);
+    if (variant) oracle_combine_f32_w(M, h, Z, ldz);
+    else oracle_combine_f32(M, h, Z, ldz);
     free(S); free(T); free(M);
 }
 
-/* C (n x n, binary32) from binary32 A, B: zero-pad to n_pad, `depth` levels,
- * leaf arithmetic `mode` (0, 2, 3, 4), crop.  Returns 0 or -1. */
-int oracle_strassen_model_f32(const float* A, const float* B, float* C, int64_t n, int depth, int64_t n_pad,
-                              int mode)
+/* C (n x n, binary32) from binary32 A, B: zero-pad to n_pad, `depth` levels
+ * of Algorithm 1 (variant 0) or of Winograd's variant (1), leaf arithmetic
+ * `mode` (0, 2, 3, 4), crop.  Returns 0 or -1. */
+int oracle_model_f32(const float* A, const float* B, float* C, int64_t n, int depth, int64_t n_pad,
+                     int mode, int variant)
 {
     if (n <= 0 || depth < 0 || depth > 20 || n_pad < n || (n_pad % ((int64_t)1 << depth)) != 0 ||
-        (mode != 0 && mode != 2 && mode != 3 && mode != 4))
+        (mode != 0 && mode != 2 && mode != 3 && mode != 4) || (variant != 0 && variant != 1))
         return -1;
     if (mode == 4) {
         g_model_ex = oracle_f16_scale_exp(A, n * n, depth);
@@ -499,10 +649,16 @@ int oracle_strassen_model_f32(const float* A, const float* B, float* C, int64_t 
         memcpy(Ap + i * n_pad, A + i * n, (size_t)n * sizeof(float));
         memcpy(Bp + i * n_pad, B + i * n, (size_t)n * sizeof(float));
     }
-    model_rec(Ap, n_pad, Bp, n_pad, Cp, n_pad, n_pad, depth, mode);
+    model_rec(Ap, n_pad, Bp, n_pad, Cp, n_pad, n_pad, depth, mode, variant);
     for (int64_t i = 0; i < n; ++i) memcpy(C + i * n, Cp + i * n_pad, (size_t)n * sizeof(float));
     free(Ap); free(Bp); free(Cp);
     return 0;
+}
+
+int oracle_strassen_model_f32(const float* A, const float* B, float* C, int64_t n, int depth, int64_t n_pad,
+                              int mode)
+{
+    return oracle_model_f32(A, B, C, n, depth, n_pad, mode, 0);
 }
 
 /* x * 2^e ~= hi + lo with binary16 terms (RNE), as binary32 values. */
