@@ -43,7 +43,9 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--n", type=int, default=16384)
-    p.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "bf16x6", "fp16x3"])
+    p.add_argument("--precision", default="bf16x3",
+                   choices=["fp32", "bf16x3", "bf16x6", "fp16x3", "fp32_winograd", "bf16x3_winograd",
+                            "bf16x6_winograd", "fp16x3_winograd"])
     p.add_argument("--min-depth", type=int, default=2)
     p.add_argument("--max-depth", type=int, default=4)
     p.add_argument("--depth", type=int, default=None, help="fixed depth (skips the autotuner)")
@@ -293,7 +295,10 @@ def main() -> int:
                                      ("fp16x3_strassen", S.STARK_FP16X3, 2, 4),
                                      ("bf16x6_strassen", S.STARK_BF16X6, 2, 4),
                                      ("bf16x3_classical", S.STARK_BF16X3, 0, 0),
-                                     ("bf16x3_strassen_depth1", S.STARK_BF16X3, 1, 1)):
+                                     ("bf16x3_strassen_depth1", S.STARK_BF16X3, 1, 1),
+                                     ("bf16x3_winograd", S.STARK_BF16X3 | S.STARK_WINOGRAD, 2, 4),
+                                     ("fp16x3_winograd", S.STARK_FP16X3 | S.STARK_WINOGRAD, 2, 4),
+                                     ("fp32_winograd", S.STARK_FP32 | S.STARK_WINOGRAD, 1, 4)):
             if dmin == dmax:
                 d_ = dmin
                 pts = []

@@ -63,8 +63,17 @@ typedef enum {
     STARK_FP32 = 0,
     STARK_BF16X3 = 1,
     STARK_BF16X6 = 2,
-    STARK_FP16X3 = 3
+    STARK_FP16X3 = 3,
+    /* Flag, OR-ed into any of the above wherever a precision is passed:
+     * Winograd's variant of the recursion (the same seven products at every
+     * level, formed with 15 block additions per node instead of 18:
+     * S1 = A21+A22, S2 = S1-A11, S3 = A11-A21, S4 = A12-S2, T1 = B12-B11,
+     * T2 = B22-T1, T3 = B22-B12, T4 = T2-B21; M1..M7 = A11 B11, A12 B21,
+     * S4 B22, A22 T4, S1 T1, S2 T2, S3 T3; C11 = M1+M2, U2 = M1+M6,
+     * U3 = U2+M7, C12 = (U2+M5)+M3, C21 = U3-M4, C22 = U3+M5). */
+    STARK_WINOGRAD = 16
 } stark_precision;
+#define STARK_PRECISION_MASK 15
 
 #define STARK_DEPTH_AUTO (-1)    /* let the autotuner choose the depth        */
 #define STARK_MAX_DEPTH 8
@@ -234,6 +243,7 @@ typedef struct {
      * combine; useful leaf flops (2 L^3 per leaf) and matrix-core flops
      * (times 1, 3, 6 or 3 products for FP32, BF16X3, BF16X6, FP16X3). */
     double divide_bytes, split_bytes, combine_bytes, leaf_flops, mfma_flops;
+    int variant;              /* 0: Algorithm 1, 1: Winograd's variant           */
 } stark_plan_desc;
 
 stark_status stark_plan_info(int64_t n, int depth, stark_precision p, stark_plan_desc* out);

@@ -511,7 +511,9 @@ static float f16_round(float x)
 /* Power-of-two scale exponent of the FP16X3 leaf operands of one matrix:
  * with max|X| = m * 2^E (m in [0.5, 1)), the leaf operands after `depth`
  * levels are at most 2^depth max|X|, so scaling by 2^(14 - depth - E)
- * keeps them below 2^14 (binary16's largest finite value is 65504). */
+ * keeps them below 2^14 (binary16's largest finite value is 65504).  In
+ * Winograd's variant an operand sums up to four blocks per level (S4, T4),
+ * so its callers pass 2 * depth. */
 int oracle_f16_scale_exp(const float* X, int64_t count, int depth)
 {
     float m = 0.0f;
@@ -637,9 +639,9 @@ int oracle_model_f32(const float* A, const float* B, float* C, int64_t n, int de
     if (n <= 0 || depth < 0 || depth > 20 || n_pad < n || (n_pad % ((int64_t)1 << depth)) != 0 ||
         (mode != 0 && mode != 2 && mode != 3 && mode != 4) || (variant != 0 && variant != 1))
         return -1;
-    if (mode == 4) {
-        g_model_ex = oracle_f16_scale_exp(A, n * n, depth);
-        g_model_ey = oracle_f16_scale_exp(B, n * n, depth);
+    if (mode == 4) {   /* growth per level: 2 blocks (Algorithm 1), 4 (Winograd) */
+        g_model_ex = oracle_f16_scale_exp(A, n * n, variant ? 2 * depth : depth);
+        g_model_ey = oracle_f16_scale_exp(B, n * n, variant ? 2 * depth : depth);
     }
     const size_t N = (size_t)n_pad * (size_t)n_pad;
     float* Ap = (float*)calloc(N, sizeof(float));

@@ -37,6 +37,7 @@ struct BatchEntry {
     int count = 0;
     int planes = 0;
     bool fp16 = false;
+    int variant = 0;
     std::vector<BatchLaunch> launches;
     hipGraphExec_t exec = nullptr;
     int uses = 0;
@@ -65,16 +66,16 @@ stark_status enqueue(stark_ctx* ctx, const BatchEntry& e, hipStream_t st) {
         const TableProb src{table, pre + l.prefix, e.count};
         switch (l.kind) {
             case kPad: STK_HIP(launch_pad(src, l.total, st)); break;
-            case kDivide: STK_HIP(launch_divide(src, l.level, l.total, st)); break;
+            case kDivide: STK_HIP(launch_divide(src, l.level, e.variant, l.total, st)); break;
             case kAbsmax: STK_HIP(launch_absmax(src, l.total, st)); break;
             case kScaleExp: STK_HIP(launch_scale_exp(src, l.total, st)); break;
-            case kSplit: STK_HIP(launch_split(src, e.planes, l.total, st)); break;
+            case kSplit: STK_HIP(launch_split(src, e.planes, e.variant, l.total, st)); break;
             case kGemm:
                 STK_HIP(launch_gemm(src, e.planes, l.tile, e.fp16, l.total,
                                     gemm_grid(ctx, e.planes, l.tile, l.total), st));
                 break;
-            case kCombine: STK_HIP(launch_combine(src, l.level, l.total, st)); break;
-            case kCombine2: STK_HIP(launch_combine2(src, l.level, l.total, st)); break;
+            case kCombine: STK_HIP(launch_combine(src, l.level, e.variant, l.total, st)); break;
+            case kCombine2: STK_HIP(launch_combine2(src, l.level, e.variant, l.total, st)); break;
         }
     }
     return STARK_OK;
@@ -115,6 +116,7 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
         e.count = count;
         e.planes = plans[0].planes;
         e.fp16 = plans[0].scale >= 0;
+        e.variant = plans[0].variant;
         std::vector<ProbDesc> descs(count);
         for (int i = 0; i < count; ++i)
             descs[i] = make_desc(plans[i], A[i], B[i], C[i], static_cast<char*>(ctx->ws) + off[i]);

@@ -34,22 +34,28 @@ struct ProbDesc {
     int64_t pad_a, pad_b;                      // float offsets of padded copies (-1)
     int fp16;                                  // leaf planes are binary16 (FP16X3)
     int64_t scale;                             // float offset of the FP16X3 scale region (-1)
+    int variant;                               // 0: Algorithm 1, 1: Winograd's variant
 };
 
 constexpr int kScaleParts = 256;               // partial maxima per matrix (FP16X3)
 
-// Where the operand blocks of the seven products live after one divide step
-// (Algorithm 1): a materialised slot index, or a view of the parent's
-// quadrant X11 (-1) / X22 (-2).  A side: S1=X11+X22, S2=X21+X22, S3=X11,
-// S4=X22, S5=X11+X12, S6=X21-X11, S7=X12-X22 stored as slots [S1,S2,S5,S6,S7].
-// B side: T1=Y11+Y22, T2=Y11, T3=Y12-Y22, T4=Y21-Y11, T5=Y22, T6=Y11+Y12,
-// T7=Y21+Y22 stored as slots [T1,T3,T4,T6,T7].
-__device__ __forceinline__ int slot_of(int side, int c) {
-    // packed 3-bit fields: value+2 so views -2,-1 map to 0,1
-    const uint32_t a = (2u) | (3u << 3) | (1u << 6) | (0u << 9) | (4u << 12) | (5u << 15) | (6u << 18);
-    const uint32_t b = (2u) | (1u << 3) | (3u << 6) | (4u << 9) | (0u << 12) | (5u << 15) | (6u << 18);
-    const uint32_t t = side ? b : a;
-    return (int)((t >> (3 * c)) & 7u) - 2;
+// Where the operand blocks of the seven products live after one divide step:
+// a materialised slot index, or a view of the parent's quadrant X11 (-1),
+// X22 (-2), X12 (-3) or X21 (-4).
+// Algorithm 1, A side: S1=X11+X22, S2=X21+X22, S3=X11, S4=X22, S5=X11+X12,
+// S6=X21-X11, S7=X12-X22 stored as slots [S1,S2,S5,S6,S7]; B side:
+// T1=Y11+Y22, T2=Y11, T3=Y12-Y22, T4=Y21-Y11, T5=Y22, T6=Y11+Y12, T7=Y21+Y22
+// stored as slots [T1,T3,T4,T6,T7].
+// Winograd's variant, products M1..M7 = X11 Y11, X12 Y21, S4 Y22, X22 T4,
+// S1 T1, S2 T2, S3 T3 with S1=X21+X22, S2=S1-X11, S3=X11-X21, S4=X12-S2,
+// T1=Y12-Y11, T2=Y22-T1, T3=Y22-Y12, T4=T2-Y21, stored as slots
+// [S1,S2,S3,S4] and [T1,T2,T3,T4].
+__device__ __forceinline__ int slot_of(int side, int c, int variant) {
+    // 4-bit field c holds the value + 4:
+    //   A [0, 1, -1, -2, 2, 3, 4], B [0, -1, 1, 2, -2, 3, 4] (Algorithm 1),
+    //   A [-1, -3, 3, -2, 0, 1, 2], B [-1, -4, -2, 3, 0, 1, 2] (Winograd)
+    const uint32_t t = variant ? (side ? 0x6547203u : 0x6542713u) : (side ? 0x8726534u : 0x8762354u);
+    return (int)((t >> (4 * c)) & 15u) - 4;
 }
 
 // Resolve the binary32 operand (pointer, leading dimension) of node `id` at
@@ -79,12 +85,16 @@ __device__ __forceinline__ void resolve(const ProbDesc& d, int side, int level, 
             m = h;
             continue;
         }
-        const int s = (slots == 7) ? c : slot_of(side, c);
+        const int s = (slots == 7) ? c : slot_of(side, c, d.variant);
         if (s >= 0) {
             ptr = wsf + (side ? d.div_b[j] : d.div_a[j]) + (prefix * slots + s) * h * h;
             ld = h;
         } else if (s == -2) {
             ptr += h * ld + h;
+        } else if (s == -3) {
+            ptr += h;
+        } else if (s == -4) {
+            ptr += h * ld;
         }
         prefix = prefix * 7 + c;
         m = h;

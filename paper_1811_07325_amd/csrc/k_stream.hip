@@ -2,11 +2,14 @@
 //   k_pad      zero-padded copy of A and B (classical product of a padded size)
 //   k_divide   one recursion level of the divide step: the operand sums of
 //              all 7^l nodes of level l (Algorithm 1; Section III-C-1)
-//   k_split    last divide level of the bf16 paths: the seven operand pairs of
-//              every level-(k-1) node, split into bf16 planes; B-side planes
-//              are written transposed (k contiguous) for the leaf products
+//   k_split    last divide level(s) of the 16-bit paths: the seven operand
+//              pairs of every level-(k-1) node, split into 16-bit planes;
+//              B-side planes are written transposed (k contiguous) for the
+//              leaf products
 //   k_combine  one recursion level of the combine step (Algorithm 1;
 //              Section III-C-3): C11..C22 of every node from M1..M7
+//   k_combine2 the two deepest combine levels in one pass
+// Each takes the variant (Algorithm 1 or Winograd's) as a template argument.
 //
 // All are memory-bound streams: each thread moves 16-byte vectors, issues all
 // of its loads before any store, and the block -> (node, chunk) map keeps a
@@ -45,11 +48,35 @@ __device__ __forceinline__ float4 load4(const float* X, int64_t ld, int64_t n, i
 
 // Elements (r, c..c+3) of the operand of child c1 (c1 = 0..6 for M1..M7) of a
 // node whose operand X has quadrant edge H, formed exactly as k_divide forms
-// them (one binary32 add per element, same operand order), so that operand
-// need not be stored.
+// them (one binary32 add per element, same operand order, and for Winograd's
+// variant the same chain: S2 from the rounded S1, ...), so that operand need
+// not be stored.  W: 0 Algorithm 1, 1 Winograd's variant.
+template <int W>
 __device__ __forceinline__ float4 child4(const float* X, int64_t ld, int64_t n, int64_t H, int64_t r, int64_t c,
                                          int side, int c1, bool bounded) {
     auto q = [&](int a, int b) { return load4(X, ld, n, r + a * H, c + b * H, bounded); };
+    if (W) {
+        if (side == 0) {
+            switch (c1) {
+                case 0: return q(0, 0);
+                case 1: return q(0, 1);
+                case 2: return f4sub(q(0, 1), f4sub(f4add(q(1, 0), q(1, 1)), q(0, 0)));   // S4
+                case 3: return q(1, 1);
+                case 4: return f4add(q(1, 0), q(1, 1));                                   // S1
+                case 5: return f4sub(f4add(q(1, 0), q(1, 1)), q(0, 0));                   // S2
+                default: return f4sub(q(0, 0), q(1, 0));                                  // S3
+            }
+        }
+        switch (c1) {
+            case 0: return q(0, 0);
+            case 1: return q(1, 0);
+            case 2: return q(1, 1);
+            case 3: return f4sub(f4sub(q(1, 1), f4sub(q(0, 1), q(0, 0))), q(1, 0));       // T4
+            case 4: return f4sub(q(0, 1), q(0, 0));                                       // T1
+            case 5: return f4sub(q(1, 1), f4sub(q(0, 1), q(0, 0)));                       // T2
+            default: return f4sub(q(1, 1), q(0, 1));                                      // T3
+        }
+    }
     if (side == 0) {
         switch (c1) {
             case 0: return f4add(q(0, 0), q(1, 1));
@@ -71,26 +98,6 @@ __device__ __forceinline__ float4 child4(const float* X, int64_t ld, int64_t n, 
         default: return f4add(q(1, 0), q(1, 1));
     }
 }
-
-// Last divide level of the bf16 paths.  NOUT = 7: every node of level
-// depth-1 gives the seven operand pairs of its children (the leaves);
-// NOUT = 1 (depth 0): the root operands themselves.  Each output block (leaf
-// edge L) is written as P bf16 planes in the blocked layout of blk_offset
-// (common.hpp): A side with rows = rows of S, B side with rows = columns of T
-// (transposed), so the leaf GEMM reads both k-contiguous.
-//
-// A block covers a 64 x 64 tile of output positions; thread t owns rows
-// 4*(t/16)..+3 and columns 4*(t%16)..+3 of it, read as float4 (16 threads
-// cover a 256-byte row segment).  A side: each thread stores 8-byte pieces;
-// a tile fills 8 whole 1 KB blocks per output and plane.  B side: the tile of
-// each output and plane is transposed through LDS (rows of 64 bf16 + 8 pad)
-// and written back in 16-byte chunks of T^T rows, kSplitRound outputs at a
-// time.
-constexpr int kSplitTile = 64;
-constexpr int kSplitLdsRow = kSplitTile + 8;        // bf16 per LDS row (144 B, 16-byte aligned)
-
-template <int P> struct SplitRound { static constexpr int R = 2; };
-template <> struct SplitRound<3> { static constexpr int R = 1; };
 
 // ---------------------------------------------------------------------------
 // Zero-padded copies A -> pad_a, B -> pad_b (np x np).  grid.y = side.
@@ -116,14 +123,75 @@ __global__ __launch_bounds__(kStreamThreads) void k_pad(Src src) {
 
 // ---------------------------------------------------------------------------
 // Divide, level l: for every node of the level, read its four quadrants once
-// and write the materialised operand blocks: 5 per side, or all 7 (a) when
-// the level-0 source is the unpadded user matrix, read with bounds so the
-// padding is formed on the fly, and (b) when the level above is not stored
-// (binary32 path from depth 2 on: the last two levels in one pass), since
-// the two view operands would point into that level.  grid.y = side (0: A,
-// 1: B).
+// and write the materialised operand blocks: 5 per side (Algorithm 1) or 4
+// (Winograd's variant), or all 7 in product order (a) when the level-0
+// source is the unpadded user matrix, read with bounds so the padding is
+// formed on the fly, and (b) when the level above is not stored (binary32
+// path from depth 2 on: the last two levels in one pass), since the view
+// operands would point into that level.  grid.y = side (0: A, 1: B).
 // ---------------------------------------------------------------------------
-template <class Src>
+
+// Operand blocks of one node at one float4 position: slot order (5 or 4
+// blocks) or product order (7), as listed with slot_of (common.hpp).
+template <int W>
+__device__ __forceinline__ void divide_store(float4* o, int64_t q4, int side, int slots, float4 x11, float4 x12,
+                                             float4 x21, float4 x22) {
+    if (W) {
+        if (side == 0) {
+            const float4 s1 = f4add(x21, x22), s2 = f4sub(s1, x11), s3 = f4sub(x11, x21), s4 = f4sub(x12, s2);
+            if (slots == 7) {
+                o[0] = x11; o[q4] = x12; o[2 * q4] = s4; o[3 * q4] = x22;
+                o[4 * q4] = s1; o[5 * q4] = s2; o[6 * q4] = s3;
+            } else {
+                o[0] = s1; o[q4] = s2; o[2 * q4] = s3; o[3 * q4] = s4;
+            }
+        } else {
+            const float4 t1 = f4sub(x12, x11), t2 = f4sub(x22, t1), t3 = f4sub(x22, x12), t4 = f4sub(t2, x21);
+            if (slots == 7) {
+                o[0] = x11; o[q4] = x21; o[2 * q4] = x22; o[3 * q4] = t4;
+                o[4 * q4] = t1; o[5 * q4] = t2; o[6 * q4] = t3;
+            } else {
+                o[0] = t1; o[q4] = t2; o[2 * q4] = t3; o[3 * q4] = t4;
+            }
+        }
+        return;
+    }
+    if (side == 0) {
+        if (slots == 7) {                       // S1..S7
+            o[0] = f4add(x11, x22);
+            o[q4] = f4add(x21, x22);
+            o[2 * q4] = x11;
+            o[3 * q4] = x22;
+            o[4 * q4] = f4add(x11, x12);
+            o[5 * q4] = f4sub(x21, x11);
+            o[6 * q4] = f4sub(x12, x22);
+        } else {                                // S1, S2, S5, S6, S7
+            o[0] = f4add(x11, x22);
+            o[q4] = f4add(x21, x22);
+            o[2 * q4] = f4add(x11, x12);
+            o[3 * q4] = f4sub(x21, x11);
+            o[4 * q4] = f4sub(x12, x22);
+        }
+    } else {
+        if (slots == 7) {                       // T1..T7
+            o[0] = f4add(x11, x22);
+            o[q4] = x11;
+            o[2 * q4] = f4sub(x12, x22);
+            o[3 * q4] = f4sub(x21, x11);
+            o[4 * q4] = x22;
+            o[5 * q4] = f4add(x11, x12);
+            o[6 * q4] = f4add(x21, x22);
+        } else {                                // T1, T3, T4, T6, T7
+            o[0] = f4add(x11, x22);
+            o[q4] = f4sub(x12, x22);
+            o[2 * q4] = f4sub(x21, x11);
+            o[3 * q4] = f4add(x11, x12);
+            o[4 * q4] = f4add(x21, x22);
+        }
+    }
+}
+
+template <class Src, int W>
 __global__ __launch_bounds__(kStreamThreads) void k_divide(Src src, int level) {
     int64_t local;
     const ProbDesc& d = src.get(src.locate(xcd_slot(blockIdx.x, gridDim.x), local));
@@ -167,10 +235,10 @@ __global__ __launch_bounds__(kStreamThreads) void k_divide(Src src, int level) {
         if (f < q4) {
             const int64_t r = f / hq, c = (f - r * hq) * 4;
             if (fused) {
-                q11[u] = child4(X, ld, d.n, 2 * h, r, c, side, c1, fbounded);
-                q12[u] = child4(X, ld, d.n, 2 * h, r, c + h, side, c1, fbounded);
-                q21[u] = child4(X, ld, d.n, 2 * h, r + h, c, side, c1, fbounded);
-                q22[u] = child4(X, ld, d.n, 2 * h, r + h, c + h, side, c1, fbounded);
+                q11[u] = child4<W>(X, ld, d.n, 2 * h, r, c, side, c1, fbounded);
+                q12[u] = child4<W>(X, ld, d.n, 2 * h, r, c + h, side, c1, fbounded);
+                q21[u] = child4<W>(X, ld, d.n, 2 * h, r + h, c, side, c1, fbounded);
+                q22[u] = child4<W>(X, ld, d.n, 2 * h, r + h, c + h, side, c1, fbounded);
             } else if (bounded) {
                 q11[u] = load4_bounded(X, d.n, r, c);
                 q12[u] = load4_bounded(X, d.n, r, c + h);
@@ -189,40 +257,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_divide(Src src, int level) {
     for (int u = 0; u < kStreamUnroll; ++u) {
         const int64_t f = fs[u];
         if (f >= q4) continue;
-        float4* o = out + f;
-        if (side == 0) {
-            if (slots == 7) {                       // S1..S7
-                o[0] = f4add(q11[u], q22[u]);
-                o[q4] = f4add(q21[u], q22[u]);
-                o[2 * q4] = q11[u];
-                o[3 * q4] = q22[u];
-                o[4 * q4] = f4add(q11[u], q12[u]);
-                o[5 * q4] = f4sub(q21[u], q11[u]);
-                o[6 * q4] = f4sub(q12[u], q22[u]);
-            } else {                                // S1, S2, S5, S6, S7
-                o[0] = f4add(q11[u], q22[u]);
-                o[q4] = f4add(q21[u], q22[u]);
-                o[2 * q4] = f4add(q11[u], q12[u]);
-                o[3 * q4] = f4sub(q21[u], q11[u]);
-                o[4 * q4] = f4sub(q12[u], q22[u]);
-            }
-        } else {
-            if (slots == 7) {                       // T1..T7
-                o[0] = f4add(q11[u], q22[u]);
-                o[q4] = q11[u];
-                o[2 * q4] = f4sub(q12[u], q22[u]);
-                o[3 * q4] = f4sub(q21[u], q11[u]);
-                o[4 * q4] = q22[u];
-                o[5 * q4] = f4add(q11[u], q12[u]);
-                o[6 * q4] = f4add(q21[u], q22[u]);
-            } else {                                // T1, T3, T4, T6, T7
-                o[0] = f4add(q11[u], q22[u]);
-                o[q4] = f4sub(q12[u], q22[u]);
-                o[2 * q4] = f4sub(q21[u], q11[u]);
-                o[3 * q4] = f4add(q11[u], q12[u]);
-                o[4 * q4] = f4add(q21[u], q22[u]);
-            }
-        }
+        divide_store<W>(out + f, q4, side, slots, q11[u], q12[u], q21[u], q22[u]);
     }
 }
 
@@ -245,30 +280,57 @@ __device__ __forceinline__ float bf16_value(uint16_t b) {
     return __uint_as_float(((uint32_t)b) << 16);
 }
 
-// Seven operand values of the products of one node at one position
-// (Algorithm 1), A side: S1..S7; B side: T1..T7.
-__device__ __forceinline__ void seven_a(float a11, float a12, float a21, float a22, float* s) {
-    s[0] = a11 + a22; s[1] = a21 + a22; s[2] = a11; s[3] = a22;
-    s[4] = a11 + a12; s[5] = a21 - a11; s[6] = a12 - a22;
-}
-__device__ __forceinline__ void seven_b(float b11, float b12, float b21, float b22, float* t) {
-    t[0] = b11 + b22; t[1] = b11; t[2] = b12 - b22; t[3] = b21 - b11;
-    t[4] = b22; t[5] = b11 + b12; t[6] = b21 + b22;
+// Seven operand values of the products of one node at one position, in
+// product order: Algorithm 1 (W = 0) or Winograd's variant (W = 1).
+template <int W>
+__device__ __forceinline__ void seven(int side, float x11, float x12, float x21, float x22, float* o) {
+    if (W) {
+        if (side == 0) {
+            const float s1 = x21 + x22, s2 = s1 - x11, s3 = x11 - x21, s4 = x12 - s2;
+            o[0] = x11; o[1] = x12; o[2] = s4; o[3] = x22; o[4] = s1; o[5] = s2; o[6] = s3;
+        } else {
+            const float t1 = x12 - x11, t2 = x22 - t1, t3 = x22 - x12, t4 = t2 - x21;
+            o[0] = x11; o[1] = x21; o[2] = x22; o[3] = t4; o[4] = t1; o[5] = t2; o[6] = t3;
+        }
+        return;
+    }
+    if (side == 0) {
+        o[0] = x11 + x22; o[1] = x21 + x22; o[2] = x11; o[3] = x22;
+        o[4] = x11 + x12; o[5] = x21 - x11; o[6] = x12 - x22;
+    } else {
+        o[0] = x11 + x22; o[1] = x11; o[2] = x12 - x22; o[3] = x21 - x11;
+        o[4] = x22; o[5] = x11 + x12; o[6] = x21 + x22;
+    }
 }
 
-__device__ __forceinline__ float load1(const float* X, int64_t ld, int64_t n, int64_t r, int64_t c, bool bounded) {
-    if (bounded) return (r < n && c < n) ? X[r * n + c] : 0.0f;
-    return X[r * ld + c];
-}
+// Last divide level of the bf16 paths.  NOUT = 7: every node of level
+// depth-1 gives the seven operand pairs of its children (the leaves);
+// NOUT = 1 (depth 0): the root operands themselves.  Each output block (leaf
+// edge L) is written as P bf16 planes in the blocked layout of blk_offset
+// (common.hpp): A side with rows = rows of S, B side with rows = columns of T
+// (transposed), so the leaf GEMM reads both k-contiguous.
+//
+// A block covers a 64 x 64 tile of output positions; thread t owns rows
+// 4*(t/16)..+3 and columns 4*(t%16)..+3 of it, read as float4 (16 threads
+// cover a 256-byte row segment).  A side: each thread stores 8-byte pieces;
+// a tile fills 8 whole 1 KB blocks per output and plane.  B side: the tile of
+// each output and plane is transposed through LDS (rows of 64 bf16 + 8 pad)
+// and written back in 16-byte chunks of T^T rows, kSplitRound outputs at a
+// time.
+constexpr int kSplitTile = 64;
+constexpr int kSplitLdsRow = kSplitTile + 8;        // bf16 per LDS row (144 B, 16-byte aligned)
+
+template <int P> struct SplitRound { static constexpr int R = 2; };
+template <> struct SplitRound<3> { static constexpr int R = 1; };
 
 // v[o][i][e]: output o at tile row i, column e of this thread's 4 x 4 piece.
 // FUSED: X is the operand of the grandparent (edge 4L) and the parent's
 // quadrant values are formed on the fly as child c1's operand (child4).
-template <int NOUT, bool FUSED>
+template <int NOUT, bool FUSED, int W>
 __device__ __forceinline__ void split_values(const float* X, int64_t ld, int64_t n, int64_t L, int64_t r0, int64_t c0,
                                              int side, int c1, bool bounded, float (&v)[NOUT][4][4]) {
     auto quad = [&](int64_t r, int64_t c) {
-        return FUSED ? child4(X, ld, n, 2 * L, r, c, side, c1, bounded) : load4(X, ld, n, r, c, bounded);
+        return FUSED ? child4<W>(X, ld, n, 2 * L, r, c, side, c1, bounded) : load4(X, ld, n, r, c, bounded);
     };
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -283,8 +345,7 @@ __device__ __forceinline__ void split_values(const float* X, int64_t ld, int64_t
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 float s7[7];
-                if (side == 0) seven_a(p11[e], p12[e], p21[e], p22[e], s7);
-                else seven_b(p11[e], p12[e], p21[e], p22[e], s7);
+                seven<W>(side, p11[e], p12[e], p21[e], p22[e], s7);
 #pragma unroll
                 for (int o = 0; o < NOUT; ++o) v[o][i][e] = s7[o];
             }
@@ -320,7 +381,7 @@ __device__ __forceinline__ void split4(const float (&x)[4], uint2 (&planes)[P], 
 // `node`: the level-(depth-1) node whose seven children's operands are
 // written (FUSED: formed from its parent's operand, node / 7 at level
 // depth-2, as child node % 7).
-template <int NOUT, int P, bool FUSED>
+template <int NOUT, int P, bool FUSED, int W>
 __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t node, int64_t tile, bool bounded,
                                            uint16_t* lds) {
     const int64_t L = d.leaf;
@@ -337,7 +398,7 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
     const int64_t LL = L * L;
 
     float v[NOUT][4][4];
-    split_values<NOUT, FUSED>(X, ld, d.n, L, R0 + ri, C0 + ci, side, (int)(node % 7), bounded, v);
+    split_values<NOUT, FUSED, W>(X, ld, d.n, L, R0 + ri, C0 + ci, side, (int)(node % 7), bounded, v);
     const bool fp16 = d.fp16 != 0;
     const float scale =
         fp16 ? ldexpf(1.0f, reinterpret_cast<const int*>(reinterpret_cast<const float*>(d.ws) + d.scale)[2 * kScaleParts + side])
@@ -400,7 +461,7 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
 // siblings of one tile position are consecutive logical blocks, placed on
 // one XCD, so the grandparent tiles they share are re-read from its L2.  The
 // source is read with bounds when it is the unpadded user matrix.
-template <class Src, int P>
+template <class Src, int P, int W>
 __global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
     constexpr int R = SplitRound<P>::R;
     __shared__ __attribute__((aligned(16))) uint16_t lds[R * P * kSplitTile * kSplitLdsRow];
@@ -412,13 +473,13 @@ __global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
     if (d.depth >= 2) {
         const int64_t c1 = local % 7, rest = local / 7;
         const int64_t tile = rest % tiles, node = 7 * (rest / tiles) + c1;
-        split_body<7, P, true>(d, side, node, tile, d.bounded0 && d.depth == 2, lds);
+        split_body<7, P, true, W>(d, side, node, tile, d.bounded0 && d.depth == 2, lds);
         return;
     }
     const int64_t node = local / tiles, tile = local - node * tiles;
     const bool bounded = d.bounded0 != 0;
-    if (d.depth == 0) split_body<1, P, false>(d, side, node, tile, bounded, lds);
-    else split_body<7, P, false>(d, side, node, tile, bounded, lds);
+    if (d.depth == 0) split_body<1, P, false, W>(d, side, node, tile, bounded, lds);
+    else split_body<7, P, false, W>(d, side, node, tile, bounded, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,7 +487,8 @@ __global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
 // magnitude of a contiguous chunk of A (grid.y = 0) or B (1).  k_scale_exp:
 // one block per problem reduces the partial maxima and stores the exponents
 // e = 14 - depth - E, with max = m 2^E (m in [0.5, 1)): multiplying by 2^e
-// keeps every leaf operand (at most 2^depth max) below 2^14.
+// keeps every leaf operand (at most 2^depth max) below 2^14; Winograd's
+// variant sums up to 4 blocks per level, so there e = 14 - 2 depth - E.
 // ---------------------------------------------------------------------------
 template <class Src>
 __global__ __launch_bounds__(kStreamThreads) void k_absmax(Src src) {
@@ -485,8 +547,10 @@ __global__ __launch_bounds__(kScaleParts) void k_scale_exp(Src src) {
         const float m = part[threadIdx.x][0];
         int E = 0;
         if (m > 0.0f) frexpf(m, &E);
+        // a leaf operand sums at most 2 blocks per level (4 in Winograd's variant)
+        const int growth = d.variant ? 2 * d.depth : d.depth;
         reinterpret_cast<int*>(reinterpret_cast<float*>(d.ws) + d.scale)[2 * kScaleParts + threadIdx.x] =
-            m > 0.0f ? 14 - d.depth - E : 0;
+            m > 0.0f ? 14 - growth - E : 0;
     }
 }
 
@@ -495,7 +559,28 @@ __global__ __launch_bounds__(kScaleParts) void k_scale_exp(Src src) {
 // (Algorithm 1 with C22 = M1 - M2 + M3 + M6), additions left to right.
 // Level 0 writes the user's C, cropping to n x n when padded.
 // ---------------------------------------------------------------------------
-template <class Src>
+// The four quadrants of a node from its seven products, in the fixed order
+// of Algorithm 1 (W = 0; C22 with +M3) or of Winograd's variant (W = 1:
+// U2 = M1 + M6, U3 = U2 + M7, C11 = M1 + M2, C12 = (U2 + M5) + M3,
+// C21 = U3 - M4, C22 = U3 + M5).
+template <int W>
+__device__ __forceinline__ void combine_quads(float4 m1, float4 m2, float4 m3, float4 m4, float4 m5, float4 m6,
+                                              float4 m7, float4 (&c)[4]) {
+    if (W) {
+        const float4 u2 = f4add(m1, m6), u3 = f4add(u2, m7);
+        c[0] = f4add(m1, m2);
+        c[1] = f4add(f4add(u2, m5), m3);
+        c[2] = f4sub(u3, m4);
+        c[3] = f4add(u3, m5);
+    } else {
+        c[0] = f4add(f4sub(f4add(m1, m4), m5), m7);
+        c[1] = f4add(m3, m5);
+        c[2] = f4add(m2, m4);
+        c[3] = f4add(f4add(f4sub(m1, m2), m3), m6);
+    }
+}
+
+template <class Src, int W>
 __global__ __launch_bounds__(kStreamThreads) void k_combine(Src src, int level) {
     int64_t local;
     const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
@@ -524,10 +609,9 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine(Src src, int level) 
         if (f >= q4) continue;
         const float4 m1 = in[f], m2 = in[q4 + f], m3 = in[2 * q4 + f], m4 = in[3 * q4 + f];
         const float4 m5 = in[4 * q4 + f], m6 = in[5 * q4 + f], m7 = in[6 * q4 + f];
-        const float4 c11 = f4add(f4sub(f4add(m1, m4), m5), m7);
-        const float4 c12 = f4add(m3, m5);
-        const float4 c21 = f4add(m2, m4);
-        const float4 c22 = f4add(f4add(f4sub(m1, m2), m3), m6);
+        float4 cq[4];
+        combine_quads<W>(m1, m2, m3, m4, m5, m6, m7, cq);
+        const float4 c11 = cq[0], c12 = cq[1], c21 = cq[2], c22 = cq[3];
         const int64_t r = f / hq, c = (f - r * hq) * 4;
         if (crop) {
             const float* v11 = &c11.x; const float* v12 = &c12.x;
@@ -555,10 +639,12 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine(Src src, int level) 
 // A thread owns one float4 position (r, c) of the grandchild grid: for each
 // child j it forms the child's four quadrant values at (r, c) from its seven
 // products, exactly as k_combine does, and folds them into the parent's
-// sixteen g x g sub-blocks in child order.  That order is the one k_combine
-// uses one level up (C11 = ((N1 + N4) - N5) + N7, ...), so the result equals
-// two k_combine launches bit for bit.
-template <class Src>
+// sixteen g x g sub-blocks as the children arrive.  Algorithm 1's order one
+// level up (C11 = ((N1 + N4) - N5) + N7, ...) is child order, so running
+// sums suffice; Winograd's (U2 = N1 + N6, ...) keeps N3, N4, N5 until N7.
+// Either way the additions are those of two k_combine launches, in the same
+// order, so the result equals them bit for bit.
+template <class Src, int W>
 __global__ __launch_bounds__(kStreamThreads) void k_combine2(Src src, int level) {
     int64_t local;
     const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
@@ -585,19 +671,33 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine2(Src src, int level)
     }
     // acc[Q][s]: parent quadrant Q (11, 12, 21, 22), sub-block s = 2 qa + qb
     float4 acc[4][4];
+    float4 keep[3][4];   // Winograd: N3, N4, N5 (Algorithm 1 leaves it unused)
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
         const float4* mj = in + (int64_t)j * 7 * q4 + f;
-        const float4 m1 = mj[0], m2 = mj[q4], m3 = mj[2 * q4], m4 = mj[3 * q4];
-        const float4 m5 = mj[4 * q4], m6 = mj[5 * q4], m7 = mj[6 * q4];
         float4 nq[4];
-        nq[0] = f4add(f4sub(f4add(m1, m4), m5), m7);
-        nq[1] = f4add(m3, m5);
-        nq[2] = f4add(m2, m4);
-        nq[3] = f4add(f4add(f4sub(m1, m2), m3), m6);
+        combine_quads<W>(mj[0], mj[q4], mj[2 * q4], mj[3 * q4], mj[4 * q4], mj[5 * q4], mj[6 * q4], nq);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const float4 v = nq[s];
+            if (W) {       // acc[1] holds U2 until the end
+                switch (j) {
+                    case 0: acc[0][s] = v; acc[1][s] = v; break;
+                    case 1: acc[0][s] = f4add(acc[0][s], v); break;
+                    case 2: keep[0][s] = v; break;
+                    case 3: keep[1][s] = v; break;
+                    case 4: keep[2][s] = v; break;
+                    case 5: acc[1][s] = f4add(acc[1][s], v); break;
+                    default: {
+                        const float4 u3 = f4add(acc[1][s], v);
+                        acc[1][s] = f4add(f4add(acc[1][s], keep[2][s]), keep[0][s]);
+                        acc[2][s] = f4sub(u3, keep[1][s]);
+                        acc[3][s] = f4add(u3, keep[2][s]);
+                        break;
+                    }
+                }
+                continue;
+            }
             switch (j) {   // child j = N_{j+1}
                 case 0: acc[0][s] = v; acc[3][s] = v; break;
                 case 1: acc[2][s] = v; acc[3][s] = f4sub(acc[3][s], v); break;
@@ -672,26 +772,36 @@ hipError_t launch_scale_exp(const Src& s, int64_t blocks, hipStream_t st) {
     return hipGetLastError();
 }
 template <class Src>
-hipError_t launch_divide(const Src& s, int level, int64_t blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_divide<Src>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s, level);
-    return hipGetLastError();
-}
-template <class Src>
-hipError_t launch_split(const Src& s, int planes, int64_t blocks, hipStream_t st) {
-    if (planes == 2)
-        hipLaunchKernelGGL((k_split<Src, 2>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s);
+hipError_t launch_divide(const Src& s, int level, int variant, int64_t blocks, hipStream_t st) {
+    if (variant)
+        hipLaunchKernelGGL((k_divide<Src, 1>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s, level);
     else
-        hipLaunchKernelGGL((k_split<Src, 3>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s);
+        hipLaunchKernelGGL((k_divide<Src, 0>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s, level);
     return hipGetLastError();
 }
 template <class Src>
-hipError_t launch_combine2(const Src& s, int level, int64_t blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_combine2<Src>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
+hipError_t launch_split(const Src& s, int planes, int variant, int64_t blocks, hipStream_t st) {
+    const dim3 grid((unsigned)blocks, 2), block(kStreamThreads);
+    if (planes == 2 && !variant) hipLaunchKernelGGL((k_split<Src, 2, 0>), grid, block, 0, st, s);
+    else if (planes == 2) hipLaunchKernelGGL((k_split<Src, 2, 1>), grid, block, 0, st, s);
+    else if (!variant) hipLaunchKernelGGL((k_split<Src, 3, 0>), grid, block, 0, st, s);
+    else hipLaunchKernelGGL((k_split<Src, 3, 1>), grid, block, 0, st, s);
     return hipGetLastError();
 }
 template <class Src>
-hipError_t launch_combine(const Src& s, int level, int64_t blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_combine<Src>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
+hipError_t launch_combine2(const Src& s, int level, int variant, int64_t blocks, hipStream_t st) {
+    if (variant)
+        hipLaunchKernelGGL((k_combine2<Src, 1>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
+    else
+        hipLaunchKernelGGL((k_combine2<Src, 0>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
+    return hipGetLastError();
+}
+template <class Src>
+hipError_t launch_combine(const Src& s, int level, int variant, int64_t blocks, hipStream_t st) {
+    if (variant)
+        hipLaunchKernelGGL((k_combine<Src, 1>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
+    else
+        hipLaunchKernelGGL((k_combine<Src, 0>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
     return hipGetLastError();
 }
 
@@ -701,13 +811,13 @@ template hipError_t launch_absmax<OneProb>(const OneProb&, int64_t, hipStream_t)
 template hipError_t launch_absmax<TableProb>(const TableProb&, int64_t, hipStream_t);
 template hipError_t launch_scale_exp<OneProb>(const OneProb&, int64_t, hipStream_t);
 template hipError_t launch_scale_exp<TableProb>(const TableProb&, int64_t, hipStream_t);
-template hipError_t launch_divide<OneProb>(const OneProb&, int, int64_t, hipStream_t);
-template hipError_t launch_divide<TableProb>(const TableProb&, int, int64_t, hipStream_t);
-template hipError_t launch_split<OneProb>(const OneProb&, int, int64_t, hipStream_t);
-template hipError_t launch_split<TableProb>(const TableProb&, int, int64_t, hipStream_t);
-template hipError_t launch_combine<OneProb>(const OneProb&, int, int64_t, hipStream_t);
-template hipError_t launch_combine<TableProb>(const TableProb&, int, int64_t, hipStream_t);
-template hipError_t launch_combine2<OneProb>(const OneProb&, int, int64_t, hipStream_t);
-template hipError_t launch_combine2<TableProb>(const TableProb&, int, int64_t, hipStream_t);
+template hipError_t launch_divide<OneProb>(const OneProb&, int, int, int64_t, hipStream_t);
+template hipError_t launch_divide<TableProb>(const TableProb&, int, int, int64_t, hipStream_t);
+template hipError_t launch_split<OneProb>(const OneProb&, int, int, int64_t, hipStream_t);
+template hipError_t launch_split<TableProb>(const TableProb&, int, int, int64_t, hipStream_t);
+template hipError_t launch_combine<OneProb>(const OneProb&, int, int, int64_t, hipStream_t);
+template hipError_t launch_combine<TableProb>(const TableProb&, int, int, int64_t, hipStream_t);
+template hipError_t launch_combine2<OneProb>(const OneProb&, int, int, int64_t, hipStream_t);
+template hipError_t launch_combine2<TableProb>(const TableProb&, int, int, int64_t, hipStream_t);
 
 }  // namespace stk

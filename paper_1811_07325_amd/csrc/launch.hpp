@@ -19,11 +19,13 @@ template <class Src> hipError_t launch_pad(const Src& s, int64_t blocks, hipStre
 // exponents (1 block per problem).
 template <class Src> hipError_t launch_absmax(const Src& s, int64_t blocks, hipStream_t st);
 template <class Src> hipError_t launch_scale_exp(const Src& s, int64_t blocks, hipStream_t st);
-template <class Src> hipError_t launch_divide(const Src& s, int level, int64_t blocks, hipStream_t st);
-template <class Src> hipError_t launch_split(const Src& s, int planes, int64_t blocks, hipStream_t st);
-template <class Src> hipError_t launch_combine(const Src& s, int level, int64_t blocks, hipStream_t st);
+// variant: 0 Algorithm 1, 1 Winograd's variant (same for every problem of
+// a launch).
+template <class Src> hipError_t launch_divide(const Src& s, int level, int variant, int64_t blocks, hipStream_t st);
+template <class Src> hipError_t launch_split(const Src& s, int planes, int variant, int64_t blocks, hipStream_t st);
+template <class Src> hipError_t launch_combine(const Src& s, int level, int variant, int64_t blocks, hipStream_t st);
 // Combine levels `level` + 1 and `level` in one pass (depth >= level + 2).
-template <class Src> hipError_t launch_combine2(const Src& s, int level, int64_t blocks, hipStream_t st);
+template <class Src> hipError_t launch_combine2(const Src& s, int level, int variant, int64_t blocks, hipStream_t st);
 // f16: the two planes are binary16 (FP16X3) rather than bfloat16.
 template <class Src> hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t tiles, int grid, hipStream_t st);
 

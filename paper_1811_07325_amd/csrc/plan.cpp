@@ -4,7 +4,8 @@
 // the leaf size is n_pad / 2^k).  Workspace regions, in order:
 //   div_a[l], div_b[l]  binary32 operand blocks written by the divide of
 //                       level l: 5 per node (the other two operands are views
-//                       of the parent's quadrants), 7 at level 0 when the user
+//                       of the parent's quadrants; 4 and three views for
+//                       Winograd's variant), 7 at level 0 when the user
 //                       matrix must be zero-padded on the fly and 7 at the
 //                       last level of the binary32 path from depth 2 on,
 //                       whose divide also forms level depth-2 (not stored);
@@ -51,7 +52,8 @@ int max_depth_for(int64_t n) {
 }
 
 int planes_for(int precision) {
-    switch (precision) {
+    if (precision & ~(STARK_PRECISION_MASK | STARK_WINOGRAD)) return -1;
+    switch (precision & STARK_PRECISION_MASK) {
         case STARK_FP32: return 0;
         case STARK_BF16X3: return 2;
         case STARK_BF16X6: return 3;
@@ -72,6 +74,7 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
     p.n = n;
     p.depth = depth;
     p.precision = precision;
+    p.variant = (precision & STARK_WINOGRAD) ? 1 : 0;
     p.planes = planes;
     p.np = padded_size(n, depth);
     p.leaf = p.np >> depth;
@@ -92,7 +95,7 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
     }
     const int64_t N = p.np * p.np;
     int64_t off = 0;
-    if (precision == STARK_FP16X3) {
+    if ((precision & STARK_PRECISION_MASK) == STARK_FP16X3) {
         // 2 x kScaleParts partial maxima, then e_A, e_B (kept apart from the
         // regions the combine outputs reuse)
         p.scale = off;
@@ -121,7 +124,7 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
         // the divide of level depth-1, which then stores all seven operands
         if (planes == 0 && depth >= 2 && l == depth - 2) continue;
         const bool all7 = (l == 0 && p.padded) || (planes == 0 && depth >= 2 && l == depth - 1);
-        const int slots = all7 ? 7 : 5;
+        const int slots = all7 ? 7 : p.variant ? 4 : 5;
         const int64_t h = (p.np >> l) >> 1;
         const int64_t sz = (int64_t)slots * pow7(l) * h * h * 4;
         p.div_slots[l] = slots;
@@ -172,7 +175,8 @@ ProbDesc make_desc(const Plan& p, const float* A, const float* B, float* C, void
     d.leaf_m = p.leaf_m >= 0 ? p.leaf_m / 4 : -1;
     d.pad_a = p.pad_a >= 0 ? p.pad_a / 4 : -1;
     d.pad_b = p.pad_b >= 0 ? p.pad_b / 4 : -1;
-    d.fp16 = p.precision == STARK_FP16X3 ? 1 : 0;
+    d.fp16 = (p.precision & STARK_PRECISION_MASK) == STARK_FP16X3 ? 1 : 0;
+    d.variant = p.variant;
     d.scale = p.scale >= 0 ? p.scale / 4 : -1;
     return d;
 }

@@ -15,7 +15,8 @@ constexpr int64_t kLeafGranule = 64;   // leaf edge is a multiple of this
 struct Plan {
     int64_t n = 0, np = 0, leaf = 0;
     int depth = 0;
-    int precision = 0;   // stark_precision
+    int precision = 0;   // stark_precision as passed (may carry STARK_WINOGRAD)
+    int variant = 0;     // 0: Algorithm 1, 1: Winograd's variant
     int planes = 0;      // 0, 2, 3
     int tile = 128;      // leaf GEMM tile edge
     bool padded = false;
@@ -33,7 +34,7 @@ struct Plan {
 int64_t pow7(int l);
 int64_t padded_size(int64_t n, int depth);
 int max_depth_for(int64_t n);
-int planes_for(int precision);  // -1 if unknown
+int planes_for(int precision);  // -1 if unknown (STARK_WINOGRAD may be set)
 
 // Returns "" on success, else the reason the plan is invalid.
 std::string make_plan(int64_t n, int depth, int precision, Plan& out);

@@ -76,7 +76,7 @@ int default_serving_depth(int64_t n, int precision) {
     // binary32 leaves: one level per doubling above 2048; bf16 split leaves
     // keep their error budget at one level at most
     int d;
-    if (precision == STARK_FP32) d = n >= 8192 ? 2 : n >= 4096 ? 1 : 0;
+    if ((precision & STARK_PRECISION_MASK) == STARK_FP32) d = n >= 8192 ? 2 : n >= 4096 ? 1 : 0;
     else d = n >= 4096 ? 1 : 0;
     return std::min(d, max_depth_for(n));
 }

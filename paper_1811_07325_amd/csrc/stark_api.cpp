@@ -49,12 +49,12 @@ stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned
     if (mask & STARK_PHASE_DIVIDE) {
         if (p.pad_a >= 0) STK_HIP(launch_pad(src, blocks_pad(d), st));
         for (int l = 0; l < p.fp32_levels; ++l)
-            if (p.div_slots[l] > 0) STK_HIP(launch_divide(src, l, blocks_divide(d, l), st));
+            if (p.div_slots[l] > 0) STK_HIP(launch_divide(src, l, p.variant, blocks_divide(d, l), st));
         if (p.scale >= 0) {
             STK_HIP(launch_absmax(src, kScaleParts, st));
             STK_HIP(launch_scale_exp(src, 1, st));
         }
-        if (p.planes > 0) STK_HIP(launch_split(src, p.planes, blocks_split(d), st));
+        if (p.planes > 0) STK_HIP(launch_split(src, p.planes, p.variant, blocks_split(d), st));
     }
     if (mask & STARK_PHASE_LEAF) {
         const int64_t tiles = pow7(p.depth) * gemm_tiles_per_leaf(p.planes, p.tile, p.leaf);
@@ -63,11 +63,11 @@ stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned
     if (mask & STARK_PHASE_COMBINE) {
         int l = p.depth - 1;
         if (p.depth >= 2) {   // the two deepest levels in one pass
-            STK_HIP(launch_combine2(src, p.depth - 2, blocks_combine2(d, p.depth - 2), st));
+            STK_HIP(launch_combine2(src, p.depth - 2, p.variant, blocks_combine2(d, p.depth - 2), st));
             l = p.depth - 3;
         }
         for (; l >= 0; --l)
-            STK_HIP(launch_combine(src, l, blocks_combine(d, l), st));
+            STK_HIP(launch_combine(src, l, p.variant, blocks_combine(d, l), st));
     }
     return STARK_OK;
 }
@@ -227,6 +227,7 @@ stark_status stark_plan_info(int64_t n, int depth, stark_precision prec, stark_p
     out->combine_bytes = w.combine_bytes;
     out->leaf_flops = w.leaf_flops;
     out->mfma_flops = w.mfma_flops;
+    out->variant = p.variant;
     return STARK_OK;
 }
 

@@ -51,12 +51,15 @@ def _regions(d, depth):
     return sorted(regs, key=lambda r: r[1])
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 16, 17, 19])
 @pytest.mark.parametrize("n,depth", [(512, 2), (4096, 3), (1000, 2), (384, 1), (16384, 4), (65, 0), (3000, 3)])
 def test_plan_layout(S, n, depth, prec):
     d = S.stark_plan_info(n, depth, prec)
     np_ = d.n_pad
     assert np_ >= n and np_ % (64 << depth) == 0 and d.leaf == np_ >> depth
+    winograd = bool(prec & S.STARK_WINOGRAD)
+    assert d.variant == int(winograd)
+    prec &= 15
     planes = {0: 0, 1: 2, 2: 3, 3: 2}[prec]
     assert d.planes == planes
     L, h = d.leaf, None
@@ -70,7 +73,7 @@ def test_plan_layout(S, n, depth, prec):
     for l in range(depth):
         if l < fp32_levels and l != unstored:
             h = (np_ >> l) // 2
-            slots = 7 if (l == 0 and np_ != n) or (unstored is not None and l == depth - 1) else 5
+            slots = 7 if (l == 0 and np_ != n) or (unstored is not None and l == depth - 1) else 4 if winograd else 5
             assert d.div_slots[l] == slots
             size["div_a%d" % l] = size["div_b%d" % l] = slots * 7 ** l * h * h * 4
         else:
@@ -123,6 +126,20 @@ def test_workspace_formula_fp32(S):
         expect = (2 * sum(1.25 * (7 / 4) ** l for l in range(k - 2)) + 2 * (7 / 4) ** k + (7 / 4) ** k) * N * 4
         got = S.stark_workspace_size(n, k, 0)
         assert abs(got - expect) <= 256 * (4 * k + 2)
+
+
+def test_winograd_flag_and_unknown_bits(S):
+    """The Winograd flag combines with every precision; other bits are
+    rejected.  Winograd stores 4 operand blocks per node and side, not 5."""
+    for prec in (0, 1, 2, 3):
+        d = S.stark_plan_info(4096, 3, prec | S.STARK_WINOGRAD)
+        assert d.variant == 1 and d.precision == prec | S.STARK_WINOGRAD
+    d5, d4 = S.stark_plan_info(4096, 3, 1), S.stark_plan_info(4096, 3, 1 | S.STARK_WINOGRAD)
+    assert d5.div_slots[0] == 5 and d4.div_slots[0] == 4
+    assert d4.divide_bytes < d5.divide_bytes and d4.split_bytes == d5.split_bytes
+    for bad in (32, 4, 15, 48 | 1):
+        with pytest.raises(S.StarkError):
+            S.stark_workspace_size(512, 1, bad)
 
 
 def test_invalid_arguments_are_rejected(S):

@@ -44,7 +44,7 @@ def single(S, ctx, dA, dB, n, depth, prec):
 # ---------------------------------------------------------------------------
 # Batched
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 16, 17])   # 16: Winograd's variant flag
 def test_batched_integer_exact_and_equal_to_single(S, ctx, prec):
     sizes = [256, 384, 1000, 65, 300, 1024, 448, 128, 129, 512]
     depth = 2

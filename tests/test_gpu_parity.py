@@ -20,6 +20,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "fp16x3": 3}
+PREC.update({k + "_winograd": v | 16 for k, v in list(PREC.items())})   # Winograd's variant flag
+
+
+def base(prec):
+    """(leaf precision name, recursion variant) of a test precision name."""
+    return (prec[:-9], "winograd") if prec.endswith("_winograd") else (prec, "strassen")
 
 
 @pytest.fixture(scope="module")
@@ -79,11 +85,20 @@ INT_CASES = [(512, 2, "fp32"), (512, 2, "bf16x3"), (512, 2, "bf16x6"),
              (512, 2, "fp16x3"), (1000, 2, "fp16x3"), (65, 0, "fp16x3"), (300, 1, "fp16x3"), (512, 3, "fp16x3")]
 
 
+# Winograd's operand chains grow by up to 4x per level (S4, T4 sum four
+# blocks): integers in [-8, 8] keep every intermediate below 2^24 to depth 2,
+# integers in [-2, 2] to depth 3.
+INT_CASES += [(512, 2, "fp32_winograd"), (512, 2, "bf16x3_winograd"), (1000, 2, "bf16x6_winograd"),
+              (300, 1, "fp16x3_winograd"), (65, 0, "fp32_winograd"), (200, 2, "fp32_winograd"),
+              (512, 3, "fp32_winograd"), (512, 3, "bf16x3_winograd"), (500, 3, "fp16x3_winograd")]
+
+
 @pytest.mark.parametrize("n,depth,prec", INT_CASES)
 def test_integer_inputs_bit_exact(S, ctx, n, depth, prec):
     print(f"case n={n} depth={depth} prec={prec}", flush=True)
-    A = inputs.integers(n, 0)
-    B = inputs.integers(n, 1)
+    r = 2 if (prec.endswith("_winograd") and depth >= 3) else 8
+    A = inputs.integers(n, 0, -r, r)
+    B = inputs.integers(n, 1, -r, r)
     exact = A.astype(np.int64) @ B.astype(np.int64)
     C = run(S, ctx, A, B, depth, prec)
     assert np.all(np.isfinite(C))
@@ -93,7 +108,8 @@ def test_integer_inputs_bit_exact(S, ctx, n, depth, prec):
 
 @pytest.mark.parametrize("n,depth,prec", [(4096, 1, "bf16x3"), (4096, 0, "bf16x6"), (4096, 1, "bf16x6"),
                                           (4032, 1, "bf16x3"), (4096, 1, "fp16x3"), (4096, 0, "fp32"),
-                                          (4096, 1, "fp32"), (4032, 1, "fp32")])
+                                          (4096, 1, "fp32"), (4032, 1, "fp32"), (4096, 1, "bf16x3_winograd"),
+                                          (4032, 1, "fp32_winograd")])
 def test_integer_inputs_bit_exact_large_tiles(S, ctx_big, n, depth, prec):
     """Leaves wide enough for the 256-wide tile class."""
     print(f"case n={n} depth={depth} prec={prec}", flush=True)
@@ -115,6 +131,10 @@ FLOAT_CASES = [(512, 2, "fp32"), (512, 2, "bf16x3"), (512, 2, "bf16x6"), (256, 1
                (512, 0, "fp16x3"), (384, 1, "fp16x3")]
 
 
+FLOAT_CASES += [(512, 2, "fp32_winograd"), (1000, 2, "bf16x3_winograd"), (512, 3, "bf16x6_winograd"),
+                (384, 1, "fp16x3_winograd"), (512, 0, "bf16x3_winograd")]
+
+
 @pytest.mark.parametrize("n,depth,prec", FLOAT_CASES)
 def test_float_inputs_match_model(S, ctx, n, depth, prec):
     print(f"case n={n} depth={depth} prec={prec}", flush=True)
@@ -122,7 +142,8 @@ def test_float_inputs_match_model(S, ctx, n, depth, prec):
     B = inputs.uniform(n, 1)
     C = run(S, ctx, A, B, depth, prec)
     # same zero padding as the library (multiple of 2^depth * 64)
-    model = oracle.strassen_model_f32(A, B, depth, prec, oracle.padded_size(n, depth, 64))
+    mode, variant = base(prec)
+    model = oracle.strassen_model_f32(A, B, depth, mode, oracle.padded_size(n, depth, 64), variant)
     exact = oracle.gemm_f64(A, B)
     e_gpu, e_model = rel_f(C, exact), rel_f(model, exact)
     d = rel_f(C, model)
@@ -133,7 +154,7 @@ def test_float_inputs_match_model(S, ctx, n, depth, prec):
     assert e_gpu <= 1.5 * e_model + 1e-6
 
 
-@pytest.mark.parametrize("n,depth,prec", [(4096, 1, "fp32"), (4096, 1, "bf16x3")])
+@pytest.mark.parametrize("n,depth,prec", [(4096, 1, "fp32"), (4096, 1, "bf16x3"), (4096, 1, "fp32_winograd")])
 def test_float_large_tiles_match_model(S, ctx_big, n, depth, prec):
     """The 256-wide tile kernels on float inputs: against the arithmetic
     model on every element, against the FP64 product on sampled rows."""
@@ -142,7 +163,8 @@ def test_float_large_tiles_match_model(S, ctx_big, n, depth, prec):
     A = inputs.uniform(n, 0)
     B = inputs.uniform(n, 1)
     C = run(S, ctx_big, A, B, depth, prec)
-    model = oracle.strassen_model_f32(A, B, depth, prec, oracle.padded_size(n, depth, 64))
+    mode, variant = base(prec)
+    model = oracle.strassen_model_f32(A, B, depth, mode, oracle.padded_size(n, depth, 64), variant)
     rows = inputs.sample_rows(n, 64, 2)
     ref = oracle.rows_f64(A, B, rows)
     e_gpu, e_model = rel_f(C[rows], ref), rel_f(model[rows], ref)
@@ -164,8 +186,9 @@ def ws_view(ws, offset, count, dtype):
     return ws[offset:offset + count * itemsize].cpu().numpy().view(dtype)
 
 
+@pytest.mark.parametrize("variant", ["strassen", "winograd"])
 @pytest.mark.parametrize("n,depth", [(256, 2), (250, 2), (512, 3), (500, 3)])
-def test_divide_levels_bit_exact(S, ctx, ws, n, depth):
+def test_divide_levels_bit_exact(S, ctx, ws, n, depth, variant):
     """Every stored binary32 divide level against the oracle's divide steps.
     From depth 2 on the level above the last is formed on the fly and not
     stored, and the last level stores all seven operands."""
@@ -173,13 +196,15 @@ def test_divide_levels_bit_exact(S, ctx, ws, n, depth):
     B = inputs.uniform(n, 4)
     dA, dB = dev(A), dev(B)
     dC = torch.zeros((n, n), dtype=torch.float32, device="cuda")
-    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, 0, S.STARK_PHASE_DIVIDE, None)
+    prec = 16 if variant == "winograd" else 0
+    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, prec, S.STARK_PHASE_DIVIDE, None)
     torch.cuda.synchronize()
-    d = S.stark_plan_info(n, depth, 0)
+    d = S.stark_plan_info(n, depth, prec)
     np_ = d.n_pad
     Ap = np.zeros((np_, np_), np.float32); Ap[:n, :n] = A
     Bp = np.zeros((np_, np_), np.float32); Bp[:n, :n] = B
-    sA5, sB5 = [0, 1, 4, 5, 6], [0, 2, 3, 5, 6]
+    # stored operand blocks, as indices of the products they feed
+    sA5, sB5 = ([4, 5, 6, 2], [4, 5, 6, 3]) if variant == "winograd" else ([0, 1, 4, 5, 6], [0, 2, 3, 5, 6])
     assert d.div_slots[depth - 2] == 0 and d.div_slots[depth - 1] == 7
     Xs, Ys = [Ap], [Bp]           # operands of the nodes of level l, in node order
     for lvl in range(depth):
@@ -191,7 +216,7 @@ def test_divide_levels_bit_exact(S, ctx, ws, n, depth):
             gb = ws_view(ws, d.div_b[lvl], 7 ** lvl * slots * h * h, np.float32).reshape(-1, slots, h, h)
         ia, ib = (list(range(7)), list(range(7))) if slots == 7 else (sA5, sB5)
         for node, (X, Y) in enumerate(zip(Xs, Ys)):
-            Sx, Ty = oracle.divide_f32(X, Y)
+            Sx, Ty = oracle.divide_f32(X, Y, variant)
             if slots:
                 assert np.array_equal(ga[node], Sx[ia]), (lvl, node)
                 assert np.array_equal(gb[node], Ty[ib]), (lvl, node)
@@ -216,9 +241,11 @@ def unblock(x, L, BR=16):
 
 @pytest.mark.parametrize("prec,depth,n", [("bf16x3", 1, 256), ("bf16x6", 2, 256), ("bf16x3", 0, 128),
                                           ("bf16x3", 1, 200), ("bf16x3", 2, 250), ("bf16x3", 3, 512),
-                                          ("bf16x6", 3, 500)])
+                                          ("bf16x6", 3, 500), ("bf16x3_winograd", 1, 200),
+                                          ("bf16x3_winograd", 2, 250), ("bf16x6_winograd", 3, 512)])
 def test_split_leaf_operands_bit_exact(S, ctx, ws, prec, depth, n):
-    P = {"bf16x3": 2, "bf16x6": 3}[prec]
+    P = {"bf16x3": 2, "bf16x6": 3}[base(prec)[0]]
+    variant = base(prec)[1]
     A = inputs.normal(n, 5)
     B = inputs.normal(n, 6)
     dA, dB = dev(A), dev(B)
@@ -234,7 +261,7 @@ def test_split_leaf_operands_bit_exact(S, ctx, ws, prec, depth, n):
     for _ in range(depth):
         nx, ny = [], []
         for X, Y in zip(Xs, Ys):
-            Sx, Ty = oracle.divide_f32(X, Y)
+            Sx, Ty = oracle.divide_f32(X, Y, variant)
             nx.extend(Sx)
             ny.extend(Ty)
         Xs, Ys = nx, ny
@@ -247,19 +274,24 @@ def test_split_leaf_operands_bit_exact(S, ctx, ws, prec, depth, n):
         assert np.array_equal(gb[i], oracle.split_bf16(Ys[i], P).transpose(0, 2, 1)), i
 
 
-@pytest.mark.parametrize("depth,n,scale_a", [(1, 256, 1.0), (2, 256, 1e-3), (0, 128, 300.0), (1, 200, 1.0)])
-def test_fp16_split_and_scale_bit_exact(S, ctx, ws, depth, n, scale_a):
-    """FP16X3: the per-matrix exponents and the binary16 planes of every leaf."""
+@pytest.mark.parametrize("depth,n,scale_a,variant", [(1, 256, 1.0, "strassen"), (2, 256, 1e-3, "strassen"),
+                                                    (0, 128, 300.0, "strassen"), (1, 200, 1.0, "strassen"),
+                                                    (2, 256, 1e-3, "winograd"), (3, 512, 7.0, "winograd")])
+def test_fp16_split_and_scale_bit_exact(S, ctx, ws, depth, n, scale_a, variant):
+    """FP16X3: the per-matrix exponents and the binary16 planes of every leaf
+    (Winograd's operands grow by up to 4 per level, its exponent uses 2 depth)."""
     A = (inputs.normal(n, 15) * np.float32(scale_a)).astype(np.float32)
     B = inputs.normal(n, 16)
     dA, dB = dev(A), dev(B)
     dC = torch.zeros((n, n), dtype=torch.float32, device="cuda")
-    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, 3, S.STARK_PHASE_DIVIDE, None)
+    prec = 3 | (16 if variant == "winograd" else 0)
+    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, prec, S.STARK_PHASE_DIVIDE, None)
     torch.cuda.synchronize()
-    d = S.stark_plan_info(n, depth, 3)
+    d = S.stark_plan_info(n, depth, prec)
     np_, L = d.n_pad, d.leaf
     ex = ws_view(ws, d.scale + 4 * 512, 2, np.int32)
-    ea, eb = oracle.f16_scale_exp(A, depth), oracle.f16_scale_exp(B, depth)
+    growth = 2 * depth if variant == "winograd" else depth
+    ea, eb = oracle.f16_scale_exp(A, growth), oracle.f16_scale_exp(B, growth)
     assert (int(ex[0]), int(ex[1])) == (ea, eb)
     Ap = np.zeros((np_, np_), np.float32); Ap[:n, :n] = A
     Bp = np.zeros((np_, np_), np.float32); Bp[:n, :n] = B
@@ -267,7 +299,7 @@ def test_fp16_split_and_scale_bit_exact(S, ctx, ws, depth, n, scale_a):
     for _ in range(depth):
         nx, ny = [], []
         for X, Y in zip(Xs, Ys):
-            Sx, Ty = oracle.divide_f32(X, Y)
+            Sx, Ty = oracle.divide_f32(X, Y, variant)
             nx.extend(Sx)
             ny.extend(Ty)
         Xs, Ys = nx, ny
@@ -292,8 +324,9 @@ def test_fp16x3_wide_range_inputs_match_model(S, ctx):
     assert rel_f(C, exact) < 5e-6
 
 
-@pytest.mark.parametrize("n,depth", [(256, 2), (512, 3)])
-def test_combine_levels_bit_exact(S, ctx, ws, n, depth):
+@pytest.mark.parametrize("variant", ["strassen", "winograd"])
+@pytest.mark.parametrize("n,depth", [(256, 2), (512, 3), (256, 1)])
+def test_combine_levels_bit_exact(S, ctx, ws, n, depth, variant):
     """The two deepest combine levels run as one pass (no level-(k-1)
     outputs in memory), the others one level at a time: every level written
     equals the oracle's binary32 combine steps bit for bit."""
@@ -301,9 +334,10 @@ def test_combine_levels_bit_exact(S, ctx, ws, n, depth):
     B = inputs.uniform(n, 8)
     dA, dB = dev(A), dev(B)
     dC = torch.zeros((n, n), dtype=torch.float32, device="cuda")
-    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, 0, S.STARK_PHASE_ALL, None)
+    prec = 16 if variant == "winograd" else 0
+    S.stark_gemm_phases(ctx, dA, dB, dC, n, depth, prec, S.STARK_PHASE_ALL, None)
     torch.cuda.synchronize()
-    d = S.stark_plan_info(n, depth, 0)
+    d = S.stark_plan_info(n, depth, prec)
     L = d.leaf
     nleaf = 7 ** depth
     M = ws_view(ws, d.leaf_m, nleaf * L * L, np.float32).reshape(nleaf, L, L)
@@ -311,7 +345,7 @@ def test_combine_levels_bit_exact(S, ctx, ws, n, depth):
     levels = {depth: M}
     for lvl in range(depth - 1, -1, -1):
         ch = levels[lvl + 1]
-        levels[lvl] = np.stack([oracle.combine_f32(ch[7 * i:7 * i + 7]) for i in range(7 ** lvl)])
+        levels[lvl] = np.stack([oracle.combine_f32(ch[7 * i:7 * i + 7], variant) for i in range(7 ** lvl)])
     if depth == 3:   # level 1 is written by the fused pass over levels 2 and 1
         m1 = n >> 1
         C1 = ws_view(ws, d.comb[1], 7 * m1 * m1, np.float32).reshape(7, m1, m1)
