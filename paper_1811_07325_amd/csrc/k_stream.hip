@@ -15,6 +15,8 @@
 // of its loads before any store, and the block -> (node, chunk) map keeps a
 // block inside one node so the walk that finds the node's operands runs once
 // per block.
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -46,56 +48,64 @@ __device__ __forceinline__ float4 load4(const float* X, int64_t ld, int64_t n, i
     return *reinterpret_cast<const float4*>(X + r * ld + c);
 }
 
-// Elements (r, c..c+3) of the operand of child c1 (c1 = 0..6 for M1..M7) of a
+// Elements (r, c..c+3) of the operand of child C1 (0..6 for M1..M7) of a
 // node whose operand X has quadrant edge H, formed exactly as k_divide forms
 // them (one binary32 add per element, same operand order, and for Winograd's
 // variant the same chain: S2 from the rounded S1, ...), so that operand need
-// not be stored.  W: 0 Algorithm 1, 1 Winograd's variant.
-template <int W>
+// not be stored.  W: 0 Algorithm 1, 1 Winograd's variant.  C1 is a template
+// argument so that every load is unconditional and can be issued early.
+template <int W, int C1>
 __device__ __forceinline__ float4 child4(const float* X, int64_t ld, int64_t n, int64_t H, int64_t r, int64_t c,
-                                         int side, int c1, bool bounded) {
+                                         int side, bool bounded) {
     auto q = [&](int a, int b) { return load4(X, ld, n, r + a * H, c + b * H, bounded); };
     if (W) {
         if (side == 0) {
-            switch (c1) {
-                case 0: return q(0, 0);
-                case 1: return q(0, 1);
-                case 2: return f4sub(q(0, 1), f4sub(f4add(q(1, 0), q(1, 1)), q(0, 0)));   // S4
-                case 3: return q(1, 1);
-                case 4: return f4add(q(1, 0), q(1, 1));                                   // S1
-                case 5: return f4sub(f4add(q(1, 0), q(1, 1)), q(0, 0));                   // S2
-                default: return f4sub(q(0, 0), q(1, 0));                                  // S3
-            }
+            if (C1 == 0) return q(0, 0);
+            if (C1 == 1) return q(0, 1);
+            if (C1 == 2) return f4sub(q(0, 1), f4sub(f4add(q(1, 0), q(1, 1)), q(0, 0)));   // S4
+            if (C1 == 3) return q(1, 1);
+            if (C1 == 4) return f4add(q(1, 0), q(1, 1));                                   // S1
+            if (C1 == 5) return f4sub(f4add(q(1, 0), q(1, 1)), q(0, 0));                   // S2
+            return f4sub(q(0, 0), q(1, 0));                                                // S3
         }
-        switch (c1) {
-            case 0: return q(0, 0);
-            case 1: return q(1, 0);
-            case 2: return q(1, 1);
-            case 3: return f4sub(f4sub(q(1, 1), f4sub(q(0, 1), q(0, 0))), q(1, 0));       // T4
-            case 4: return f4sub(q(0, 1), q(0, 0));                                       // T1
-            case 5: return f4sub(q(1, 1), f4sub(q(0, 1), q(0, 0)));                       // T2
-            default: return f4sub(q(1, 1), q(0, 1));                                      // T3
-        }
+        if (C1 == 0) return q(0, 0);
+        if (C1 == 1) return q(1, 0);
+        if (C1 == 2) return q(1, 1);
+        if (C1 == 3) return f4sub(f4sub(q(1, 1), f4sub(q(0, 1), q(0, 0))), q(1, 0));      // T4
+        if (C1 == 4) return f4sub(q(0, 1), q(0, 0));                                      // T1
+        if (C1 == 5) return f4sub(q(1, 1), f4sub(q(0, 1), q(0, 0)));                      // T2
+        return f4sub(q(1, 1), q(0, 1));                                                   // T3
     }
     if (side == 0) {
-        switch (c1) {
-            case 0: return f4add(q(0, 0), q(1, 1));
-            case 1: return f4add(q(1, 0), q(1, 1));
-            case 2: return q(0, 0);
-            case 3: return q(1, 1);
-            case 4: return f4add(q(0, 0), q(0, 1));
-            case 5: return f4sub(q(1, 0), q(0, 0));
-            default: return f4sub(q(0, 1), q(1, 1));
-        }
+        if (C1 == 0) return f4add(q(0, 0), q(1, 1));
+        if (C1 == 1) return f4add(q(1, 0), q(1, 1));
+        if (C1 == 2) return q(0, 0);
+        if (C1 == 3) return q(1, 1);
+        if (C1 == 4) return f4add(q(0, 0), q(0, 1));
+        if (C1 == 5) return f4sub(q(1, 0), q(0, 0));
+        return f4sub(q(0, 1), q(1, 1));
     }
-    switch (c1) {
-        case 0: return f4add(q(0, 0), q(1, 1));
-        case 1: return q(0, 0);
-        case 2: return f4sub(q(0, 1), q(1, 1));
-        case 3: return f4sub(q(1, 0), q(0, 0));
-        case 4: return q(1, 1);
-        case 5: return f4add(q(0, 0), q(0, 1));
-        default: return f4add(q(1, 0), q(1, 1));
+    if (C1 == 0) return f4add(q(0, 0), q(1, 1));
+    if (C1 == 1) return q(0, 0);
+    if (C1 == 2) return f4sub(q(0, 1), q(1, 1));
+    if (C1 == 3) return f4sub(q(1, 0), q(0, 0));
+    if (C1 == 4) return q(1, 1);
+    if (C1 == 5) return f4add(q(0, 0), q(0, 1));
+    return f4add(q(1, 0), q(1, 1));
+}
+
+// Calls f(std::integral_constant<int, c>) for a runtime c in 0..6, so the
+// callee sees the child index as a constant.
+template <class F>
+__device__ __forceinline__ void with_child(int c, F&& f) {
+    switch (c) {
+        case 0: f(std::integral_constant<int, 0>{}); break;
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 3: f(std::integral_constant<int, 3>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 5: f(std::integral_constant<int, 5>{}); break;
+        default: f(std::integral_constant<int, 6>{}); break;
     }
 }
 
@@ -226,20 +236,35 @@ __global__ __launch_bounds__(kStreamThreads) void k_divide(Src src, int level) {
                                             (side ? d.div_b[level] : d.div_a[level]) +
                                             node * slots * h * h);
 
+    if (fused) {
+        with_child(c1, [&](auto C1) {
+            float4 q11[kStreamUnroll], q12[kStreamUnroll], q21[kStreamUnroll], q22[kStreamUnroll];
+#pragma unroll
+            for (int u = 0; u < kStreamUnroll; ++u) {
+                const int64_t f = chunk * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
+                if (f < q4) {
+                    const int64_t r = f / hq, c = (f - r * hq) * 4;
+                    q11[u] = child4<W, C1>(X, ld, d.n, 2 * h, r, c, side, fbounded);
+                    q12[u] = child4<W, C1>(X, ld, d.n, 2 * h, r, c + h, side, fbounded);
+                    q21[u] = child4<W, C1>(X, ld, d.n, 2 * h, r + h, c, side, fbounded);
+                    q22[u] = child4<W, C1>(X, ld, d.n, 2 * h, r + h, c + h, side, fbounded);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kStreamUnroll; ++u) {
+                const int64_t f = chunk * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
+                if (f < q4) divide_store<W>(out + f, q4, side, slots, q11[u], q12[u], q21[u], q22[u]);
+            }
+        });
+        return;
+    }
     float4 q11[kStreamUnroll], q12[kStreamUnroll], q21[kStreamUnroll], q22[kStreamUnroll];
-    int64_t fs[kStreamUnroll];
 #pragma unroll
     for (int u = 0; u < kStreamUnroll; ++u) {
         const int64_t f = chunk * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
-        fs[u] = f;
         if (f < q4) {
             const int64_t r = f / hq, c = (f - r * hq) * 4;
-            if (fused) {
-                q11[u] = child4<W>(X, ld, d.n, 2 * h, r, c, side, c1, fbounded);
-                q12[u] = child4<W>(X, ld, d.n, 2 * h, r, c + h, side, c1, fbounded);
-                q21[u] = child4<W>(X, ld, d.n, 2 * h, r + h, c, side, c1, fbounded);
-                q22[u] = child4<W>(X, ld, d.n, 2 * h, r + h, c + h, side, c1, fbounded);
-            } else if (bounded) {
+            if (bounded) {
                 q11[u] = load4_bounded(X, d.n, r, c);
                 q12[u] = load4_bounded(X, d.n, r, c + h);
                 q21[u] = load4_bounded(X, d.n, r + h, c);
@@ -255,9 +280,8 @@ __global__ __launch_bounds__(kStreamThreads) void k_divide(Src src, int level) {
     }
 #pragma unroll
     for (int u = 0; u < kStreamUnroll; ++u) {
-        const int64_t f = fs[u];
-        if (f >= q4) continue;
-        divide_store<W>(out + f, q4, side, slots, q11[u], q12[u], q21[u], q22[u]);
+        const int64_t f = chunk * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
+        if (f < q4) divide_store<W>(out + f, q4, side, slots, q11[u], q12[u], q21[u], q22[u]);
     }
 }
 
@@ -326,11 +350,11 @@ template <> struct SplitRound<3> { static constexpr int R = 1; };
 // v[o][i][e]: output o at tile row i, column e of this thread's 4 x 4 piece.
 // FUSED: X is the operand of the grandparent (edge 4L) and the parent's
 // quadrant values are formed on the fly as child c1's operand (child4).
-template <int NOUT, bool FUSED, int W>
+template <int NOUT, bool FUSED, int W, int C1>
 __device__ __forceinline__ void split_values(const float* X, int64_t ld, int64_t n, int64_t L, int64_t r0, int64_t c0,
-                                             int side, int c1, bool bounded, float (&v)[NOUT][4][4]) {
+                                             int side, bool bounded, float (&v)[NOUT][4][4]) {
     auto quad = [&](int64_t r, int64_t c) {
-        return FUSED ? child4<W>(X, ld, n, 2 * L, r, c, side, c1, bounded) : load4(X, ld, n, r, c, bounded);
+        return FUSED ? child4<W, C1>(X, ld, n, 2 * L, r, c, side, bounded) : load4(X, ld, n, r, c, bounded);
     };
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -381,7 +405,7 @@ __device__ __forceinline__ void split4(const float (&x)[4], uint2 (&planes)[P], 
 // `node`: the level-(depth-1) node whose seven children's operands are
 // written (FUSED: formed from its parent's operand, node / 7 at level
 // depth-2, as child node % 7).
-template <int NOUT, int P, bool FUSED, int W>
+template <int NOUT, int P, bool FUSED, int W, int C1>
 __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t node, int64_t tile, bool bounded,
                                            uint16_t* lds) {
     const int64_t L = d.leaf;
@@ -398,7 +422,7 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
     const int64_t LL = L * L;
 
     float v[NOUT][4][4];
-    split_values<NOUT, FUSED, W>(X, ld, d.n, L, R0 + ri, C0 + ci, side, (int)(node % 7), bounded, v);
+    split_values<NOUT, FUSED, W, C1>(X, ld, d.n, L, R0 + ri, C0 + ci, side, bounded, v);
     const bool fp16 = d.fp16 != 0;
     const float scale =
         fp16 ? ldexpf(1.0f, reinterpret_cast<const int*>(reinterpret_cast<const float*>(d.ws) + d.scale)[2 * kScaleParts + side])
@@ -473,13 +497,15 @@ __global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
     if (d.depth >= 2) {
         const int64_t c1 = local % 7, rest = local / 7;
         const int64_t tile = rest % tiles, node = 7 * (rest / tiles) + c1;
-        split_body<7, P, true, W>(d, side, node, tile, d.bounded0 && d.depth == 2, lds);
+        with_child((int)c1, [&](auto C1) {
+            split_body<7, P, true, W, C1>(d, side, node, tile, d.bounded0 && d.depth == 2, lds);
+        });
         return;
     }
     const int64_t node = local / tiles, tile = local - node * tiles;
     const bool bounded = d.bounded0 != 0;
-    if (d.depth == 0) split_body<1, P, false, W>(d, side, node, tile, bounded, lds);
-    else split_body<7, P, false, W>(d, side, node, tile, bounded, lds);
+    if (d.depth == 0) split_body<1, P, false, W, 0>(d, side, node, tile, bounded, lds);
+    else split_body<7, P, false, W, 0>(d, side, node, tile, bounded, lds);
 }
 
 // ---------------------------------------------------------------------------
