@@ -63,6 +63,7 @@ def _load():
     I64 = ctypes.c_int64
     lib.oracle_gemm_f64.argtypes = [P, P, P, I64]
     lib.oracle_gemm_i64.argtypes = [P, P, P, I64]
+    lib.oracle_gemm_rect_f64.argtypes = [P, P, P, I64, I64, I64]
     lib.oracle_rows_f64.argtypes = [P, P, I64, P, I64, P]
     lib.oracle_gemv_f64.argtypes = [P, P, P, I64]
     lib.oracle_strassen_f64.argtypes = [P, P, P, I64, ctypes.c_int, I64, ctypes.POINTER(Counts)]
@@ -255,6 +256,49 @@ def strassen_model_f32(A, B, depth: int, mode: str, n_pad: int | None = None,
     if rc != 0:
         raise ValueError("oracle_strassen_model_f32: bad arguments")
     return C
+
+
+def gemm_rect_f64(A, B) -> np.ndarray:
+    """Rectangular classical product in FP64: C (m x n) = A (m x k) B (k x n)."""
+    A, B = _f64(A), _f64(B)
+    m, k = A.shape
+    k2, n = B.shape
+    assert k == k2
+    C = np.empty((m, n), dtype=np.float64)
+    _load().oracle_gemm_rect_f64(_ptr(A), _ptr(B), _ptr(C), m, k, n)
+    return C
+
+
+def rect_blocks(m: int, k: int, n: int, s: int):
+    """Block counts of the square partition of C (m x n) = A (m x k) B (k x n)
+    into s x s blocks: (row blocks, inner blocks, column blocks)."""
+    return -(-m // s), -(-k // s), -(-n // s)
+
+
+def rect_model_f32(A, B, s: int, depth: int, mode: str, variant: str = "strassen",
+                   n_pad: int | None = None) -> np.ndarray:
+    """Rectangular product by partitioning into square problems (the paper
+    defers sizes other than 2^p to partitioning, Section III-A): A and B are
+    zero-padded to whole s x s blocks, C_ij = sum over p of A_ip B_pj, every
+    block product by the arithmetic model of the square path (padded to
+    n_pad), the sum over p in binary32 in ascending p, then cropped."""
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    m, k = A.shape
+    _, n = B.shape
+    MB, KB, NB = rect_blocks(m, k, n, s)
+    Ap = np.zeros((MB * s, KB * s), np.float32); Ap[:m, :k] = A
+    Bp = np.zeros((KB * s, NB * s), np.float32); Bp[:k, :n] = B
+    C = np.empty((MB * s, NB * s), np.float32)
+    for i in range(MB):
+        for j in range(NB):
+            acc = None
+            for p in range(KB):
+                blk = strassen_model_f32(Ap[i * s:(i + 1) * s, p * s:(p + 1) * s],
+                                         Bp[p * s:(p + 1) * s, j * s:(j + 1) * s], depth, mode, n_pad, variant)
+                acc = blk if acc is None else (acc + blk).astype(np.float32)
+            C[i * s:(i + 1) * s, j * s:(j + 1) * s] = acc
+    return C[:m, :n]
 
 
 def threads() -> int:

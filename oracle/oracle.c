@@ -103,6 +103,22 @@ void oracle_gemm_f64(const double* A, const double* B, double* C, int64_t n)
     classical_f64(A, n, B, n, C, n, n, 1);
 }
 
+/* Rectangular classical product C (m x n) = A (m x k) B (k x n), row-major,
+ * FP64, the same i-t-j order. */
+void oracle_gemm_rect_f64(const double* A, const double* B, double* C, int64_t m, int64_t k, int64_t n)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        double* c = C + i * n;
+        for (int64_t j = 0; j < n; ++j) c[j] = 0.0;
+        for (int64_t t = 0; t < k; ++t) {
+            const double a = A[i * k + t];
+            const double* b = B + t * n;
+            for (int64_t j = 0; j < n; ++j) c[j] += a * b[j];
+        }
+    }
+}
+
 void oracle_gemm_i64(const int64_t* A, const int64_t* B, int64_t* C, int64_t n)
 {
     for (int64_t i = 0; i < n; ++i)
