@@ -116,6 +116,24 @@ int stark_max_depth(int64_t n);
 stark_status stark_gemm(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n,
                         int depth, stark_precision p, void* stream);
 
+/* Rectangular product C (m x n) = A (m x k) B (k x n): row-major binary32
+ * with leading dimensions k, n and n, 16-byte aligned base pointers (rows
+ * need not be aligned).  The paper treats n = 2^p and defers other shapes to
+ * partitioning (Section III-A): A and B are packed into zero-padded square
+ * s x s blocks, s = stark_rect_block_edge(m, k, n, depth); every block
+ * product A_ip B_pj runs at `depth` as one problem of a grouped launch (as
+ * stark_gemm_batched); C_ij = sum over p of the products in binary32, in
+ * ascending p, cropped to m x n.  The context keeps the packed blocks and
+ * products (grown on demand).  Errors: EINVAL (null or misaligned pointer,
+ * m, k or n <= 0, depth out of range, C overlapping A or B, more than 4096
+ * block products), EUNSUPPORTED, ENOMEM, EDEVICE. */
+stark_status stark_gemm_rect(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t m, int64_t k,
+                             int64_t n, int depth, stark_precision p, void* stream);
+
+/* Block edge s of stark_gemm_rect: the smallest multiple of 64 * 2^depth not
+ * below min(m, k, n); -1 for invalid arguments. */
+int64_t stark_rect_block_edge(int64_t m, int64_t k, int64_t n, int depth);
+
 /* One measured point of the autotuner: depth, median time of three runs
  * (ms) and the relative error estimated by Freivalds' check in binary64. */
 typedef struct {

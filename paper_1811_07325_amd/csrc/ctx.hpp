@@ -61,6 +61,9 @@ struct stark_ctx {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     bool ws_owned = false;
+    // rectangular products: packed operand blocks and block products (grown on demand)
+    void* rect = nullptr;
+    size_t rect_bytes = 0;
     // graph cache (keyed by plan + pointers + stream), LRU
     std::map<stk::GraphKey, hipGraphExec_t> graphs;
     std::list<stk::GraphKey> graph_lru;

@@ -754,6 +754,57 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine2(Src src, int level)
 }
 
 // ---------------------------------------------------------------------------
+// Rectangular products by square partition (the paper defers shapes other
+// than n = 2^p to partitioning, Section III-A).
+//   k_pack_blocks    rows x cols of X (leading dimension ld) into nbr x nbc
+//                    contiguous s x s blocks, block (bi, bj) at
+//                    (bi * nbc + bj) s^2, zero outside the matrix;
+//   k_reduce_blocks  C (m x n, leading dimension n) from the block products
+//                    P[(i NB + j) KB + p] (s x s each): C_ij = sum over p in
+//                    ascending order, in binary32, cropped.
+// The user matrices need not have 16-byte-aligned rows (k, n arbitrary), so
+// they are read and written element by element; the blocks are float4.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kStreamThreads) void k_pack_blocks(const float* X, int64_t rows, int64_t cols,
+                                                                int64_t ld, float* dst, int64_t s, int64_t nblocks) {
+    const int64_t per = s * s / 4;                // float4 per block
+    const int64_t nbc = (cols + s - 1) / s;
+#pragma unroll
+    for (int u = 0; u < kStreamUnroll; ++u) {
+        const int64_t f = (int64_t)blockIdx.x * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
+        if (f >= nblocks * per) continue;
+        const int64_t b = f / per, e = f - b * per;
+        const int64_t r = e / (s / 4), c = (e - r * (s / 4)) * 4;
+        const int64_t R = (b / nbc) * s + r, Cc = (b % nbc) * s + c;
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (R < rows && Cc + q < cols) ? X[R * ld + Cc + q] : 0.0f;
+        reinterpret_cast<float4*>(dst)[f] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+__global__ __launch_bounds__(kStreamThreads) void k_reduce_blocks(const float* P, float* C, int64_t m, int64_t n,
+                                                                  int64_t s, int64_t MB, int64_t NB, int64_t KB) {
+    const int64_t per = s * s / 4;
+    const float4* P4 = reinterpret_cast<const float4*>(P);
+#pragma unroll
+    for (int u = 0; u < kStreamUnroll; ++u) {
+        const int64_t f = (int64_t)blockIdx.x * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
+        if (f >= MB * NB * per) continue;
+        const int64_t b = f / per, e = f - b * per;     // b = i NB + j
+        const int64_t r = e / (s / 4), c = (e - r * (s / 4)) * 4;
+        const int64_t R = (b / NB) * s + r, Cc = (b % NB) * s + c;
+        if (R >= m || Cc >= n) continue;
+        float4 acc = P4[(b * KB) * per + e];
+        for (int64_t p = 1; p < KB; ++p) acc = f4add(acc, P4[(b * KB + p) * per + e]);
+        const float* v = &acc.x;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (Cc + q < n) C[R * n + Cc + q] = v[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
 static int64_t pow7(int l) {
@@ -828,6 +879,21 @@ hipError_t launch_combine(const Src& s, int level, int variant, int64_t blocks, 
         hipLaunchKernelGGL((k_combine<Src, 1>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
     else
         hipLaunchKernelGGL((k_combine<Src, 0>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_blocks(const float* X, int64_t rows, int64_t cols, int64_t ld, float* dst, int64_t s,
+                              hipStream_t st) {
+    const int64_t nblocks = ((rows + s - 1) / s) * ((cols + s - 1) / s);
+    const int64_t grid = (nblocks * (s * s / 4) + kStreamPerBlock - 1) / kStreamPerBlock;
+    hipLaunchKernelGGL(k_pack_blocks, dim3((unsigned)grid), dim3(kStreamThreads), 0, st, X, rows, cols, ld, dst, s,
+                       nblocks);
+    return hipGetLastError();
+}
+hipError_t launch_reduce_blocks(const float* P, float* C, int64_t m, int64_t n, int64_t s, int64_t MB, int64_t NB,
+                                int64_t KB, hipStream_t st) {
+    const int64_t grid = (MB * NB * (s * s / 4) + kStreamPerBlock - 1) / kStreamPerBlock;
+    hipLaunchKernelGGL(k_reduce_blocks, dim3((unsigned)grid), dim3(kStreamThreads), 0, st, P, C, m, n, s, MB, NB, KB);
     return hipGetLastError();
 }
 

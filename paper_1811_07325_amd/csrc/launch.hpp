@@ -35,6 +35,14 @@ int64_t gemm_tiles_per_leaf(int planes, int tile, int64_t leaf);
 // Resident blocks per CU of the leaf GEMM for (planes, tile).
 int gemm_blocks_per_cu(int planes, int tile);
 
+// Rectangular products: pack rows x cols of X (leading dimension ld) into
+// zero-padded s x s blocks (row-major block order), and sum the block
+// products P[(i NB + j) KB + p] over p into C (m x n, leading dimension n).
+hipError_t launch_pack_blocks(const float* X, int64_t rows, int64_t cols, int64_t ld, float* dst, int64_t s,
+                              hipStream_t st);
+hipError_t launch_reduce_blocks(const float* P, float* C, int64_t m, int64_t n, int64_t s, int64_t MB, int64_t NB,
+                                int64_t KB, hipStream_t st);
+
 // Measurement helpers (k_check.hip).
 hipError_t launch_matvec_f64(const float* M, const double* x, double* y, int64_t n, hipStream_t st);
 hipError_t launch_row_errors(const float* C, int64_t n, const int64_t* rows, int64_t nrows,

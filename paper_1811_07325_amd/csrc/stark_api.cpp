@@ -283,6 +283,7 @@ stark_status stark_destroy(stark_ctx* ctx) {
     for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
     batched_release(ctx);
     if (ctx->ws_owned && ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->rect) (void)hipFree(ctx->rect);
     if (ctx->side_stream) (void)hipStreamDestroy(ctx->side_stream);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);

@@ -116,6 +116,8 @@ def _load() -> ctypes.CDLL:
         "stark_workspace": ([P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)], I),
         "stark_tune": ([P, P, P, P, I64, I, I, I, ctypes.c_double, ctypes.POINTER(stark_tune_point), I,
                         ctypes.POINTER(I), P], I),
+        "stark_gemm_rect": ([P, P, P, P, I64, I64, I64, I, I, P], I),
+        "stark_rect_block_edge": ([I64, I64, I64, I], I64),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -131,7 +133,7 @@ def header_symbols() -> list[str]:
     """Every function the public header declares."""
     with open(HEADER) as f:
         text = f.read()
-    return sorted(set(re.findall(r"^\s*(?:stark_status|int|const char\*)\s+(stark_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:stark_status|int|int64_t|const char\*)\s+(stark_\w+)\s*\(", text, re.M)))
 
 
 def _check(call: str, rc: int, ok=(STARK_OK,)) -> int:
@@ -197,6 +199,16 @@ def stark_gemm_batched(ctx, As, Bs, Cs, ns, depth: int, precision: int, stream=N
     c = arrP(*[_ptr(x).value for x in Cs])
     nn = (ctypes.c_int64 * count)(*ns)
     _check("stark_gemm_batched", _lib.stark_gemm_batched(ctx, count, a, b, c, nn, depth, precision, _stream(stream)))
+
+
+def stark_gemm_rect(ctx, A, B, C, m: int, k: int, n: int, depth: int, precision: int, stream=None) -> None:
+    """C (m x n) = A (m x k) B (k x n) by square-block partition."""
+    _check("stark_gemm_rect", _lib.stark_gemm_rect(ctx, _ptr(A), _ptr(B), _ptr(C), m, k, n, depth, precision,
+                                                   _stream(stream)))
+
+
+def stark_rect_block_edge(m: int, k: int, n: int, depth: int) -> int:
+    return int(_lib.stark_rect_block_edge(m, k, n, depth))
 
 
 def stark_submit(ctx, n: int, precision: int, depth: int = STARK_DEPTH_AUTO, A=None, B=None, C=None,
