@@ -334,15 +334,21 @@ __device__ __forceinline__ void seven(int side, float x11, float x12, float x21,
 // (common.hpp): A side with rows = rows of S, B side with rows = columns of T
 // (transposed), so the leaf GEMM reads both k-contiguous.
 //
-// A block covers a 64 x 64 tile of output positions; thread t owns rows
-// 4*(t/16)..+3 and columns 4*(t%16)..+3 of it, read as float4 (16 threads
-// cover a 256-byte row segment).  A side: each thread stores 8-byte pieces;
-// a tile fills 8 whole 1 KB blocks per output and plane.  B side: the tile of
-// each output and plane is transposed through LDS (rows of 64 bf16 + 8 pad)
-// and written back in 16-byte chunks of T^T rows, kSplitRound outputs at a
-// time.
-constexpr int kSplitTile = 64;
-constexpr int kSplitLdsRow = kSplitTile + 8;        // bf16 per LDS row (144 B, 16-byte aligned)
+// A block covers a kSplitRows x 64 tile of output positions; thread t owns
+// rows kSplitRPT*(t/16).. and columns 4*(t%16)..+3 of it, read as float4
+// (16 threads cover a 256-byte row segment).  A side: each thread stores
+// 8-byte pieces; a tile fills whole 1 KB blocks per output and plane.  B
+// side: the tile of each output and plane is transposed through LDS (rows of
+// kSplitRows + 8 16-bit terms) and written back in 16-byte chunks of T^T
+// rows, kSplitRound outputs at a time.
+#ifndef STK_SPLIT_ROWS
+#define STK_SPLIT_ROWS 32
+#endif
+constexpr int kSplitTile = 64;                      // tile columns
+constexpr int kSplitRows = STK_SPLIT_ROWS;          // tile rows (64 or 32)
+constexpr int kSplitRPT = kSplitRows / 16;          // rows per thread
+constexpr int kSplitLdsRow = kSplitRows + 8;        // bf16 per LDS row of T^T (16-byte aligned)
+static_assert(kSplitRows == 64 || kSplitRows == 32, "split tile rows");
 
 template <int P> struct SplitRound { static constexpr int R = 2; };
 template <> struct SplitRound<3> { static constexpr int R = 1; };
@@ -352,12 +358,12 @@ template <> struct SplitRound<3> { static constexpr int R = 1; };
 // quadrant values are formed on the fly as child c1's operand (child4).
 template <int NOUT, bool FUSED, int W, int C1>
 __device__ __forceinline__ void split_values(const float* X, int64_t ld, int64_t n, int64_t L, int64_t r0, int64_t c0,
-                                             int side, bool bounded, float (&v)[NOUT][4][4]) {
+                                             int side, bool bounded, float (&v)[NOUT][kSplitRPT][4]) {
     auto quad = [&](int64_t r, int64_t c) {
         return FUSED ? child4<W, C1>(X, ld, n, 2 * L, r, c, side, bounded) : load4(X, ld, n, r, c, bounded);
     };
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kSplitRPT; ++i) {
         const int64_t r = r0 + i;
         if (NOUT == 7) {
             const float4 x11 = quad(r, c0);
@@ -383,23 +389,29 @@ __device__ __forceinline__ void split_values(const float* X, int64_t ld, int64_t
 // Split 4 values into P planes: planes[p] holds 4 16-bit terms packed in 8
 // bytes -- bfloat16, or (fp16) binary16 of the values times `scale` (a power
 // of two, so the scaling is exact).
-template <int P>
-__device__ __forceinline__ void split4(const float (&x)[4], uint2 (&planes)[P], bool fp16, float scale) {
-    float r[4] = {x[0], x[1], x[2], x[3]};
-    if (fp16) {
+template <int P, int N>
+__device__ __forceinline__ void splitN(const float (&x)[N], uint32_t (&planes)[P][N / 2], bool fp16, float scale) {
+    float r[N];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) r[e] *= scale;
-    }
+    for (int e = 0; e < N; ++e) r[e] = fp16 ? x[e] * scale : x[e];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        uint16_t b[4];
+        uint16_t b[N];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < N; ++e) {
             b[e] = fp16 ? f16_bits(r[e]) : bf16_bits(r[e]);
             r[e] = r[e] - (fp16 ? f16_value(b[e]) : bf16_value(b[e]));
         }
-        planes[p] = make_uint2((uint32_t)b[0] | ((uint32_t)b[1] << 16), (uint32_t)b[2] | ((uint32_t)b[3] << 16));
+#pragma unroll
+        for (int e = 0; e < N / 2; ++e) planes[p][e] = (uint32_t)b[2 * e] | ((uint32_t)b[2 * e + 1] << 16);
     }
+}
+
+// 4 or 2 consecutive 16-bit terms (8 or 4 bytes) at p.
+template <int N>
+__device__ __forceinline__ void store_terms(uint16_t* p, const uint32_t (&w)[N / 2]) {
+    if (N == 4) *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[N / 2 - 1]);
+    else *reinterpret_cast<uint32_t*>(p) = w[0];
 }
 
 // `node`: the level-(depth-1) node whose seven children's operands are
@@ -410,9 +422,9 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
                                            uint16_t* lds) {
     const int64_t L = d.leaf;
     const int64_t tiles_row = L / kSplitTile;
-    const int64_t R0 = (tile / tiles_row) * kSplitTile, C0 = (tile % tiles_row) * kSplitTile;
+    const int64_t R0 = (tile / tiles_row) * kSplitRows, C0 = (tile % tiles_row) * kSplitTile;
     const int tid = threadIdx.x;
-    const int ri = 4 * (tid >> 4), ci = 4 * (tid & 15);
+    const int ri = kSplitRPT * (tid >> 4), ci = 4 * (tid & 15);
     const int plevel = FUSED ? d.depth - 2 : (NOUT == 7) ? d.depth - 1 : 0;
     const float* X;
     int64_t ld;
@@ -421,7 +433,7 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
                      node * (int64_t)NOUT * P * L * L;
     const int64_t LL = L * L;
 
-    float v[NOUT][4][4];
+    float v[NOUT][kSplitRPT][4];
     split_values<NOUT, FUSED, W, C1>(X, ld, d.n, L, R0 + ri, C0 + ci, side, bounded, v);
     const bool fp16 = d.fp16 != 0;
     const float scale =
@@ -432,18 +444,17 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
 #pragma unroll
         for (int o = 0; o < NOUT; ++o)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                uint2 pl[P];
-                split4<P>(v[o][i], pl, fp16, scale);
+            for (int i = 0; i < kSplitRPT; ++i) {
+                uint32_t pl[P][2];
+                splitN<P, 4>(v[o][i], pl, fp16, scale);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    *reinterpret_cast<uint2*>(base + ((int64_t)o * P + p) * LL + blk_offset(R0 + ri + i, C0 + ci, L)) =
-                        pl[p];
+                    store_terms<4>(base + ((int64_t)o * P + p) * LL + blk_offset(R0 + ri + i, C0 + ci, L), pl[p]);
             }
         return;
     }
     constexpr int R = NOUT == 1 ? 1 : SplitRound<P>::R;
-    constexpr int TILE_U16 = kSplitTile * kSplitLdsRow;
+    constexpr int TILE_U16 = kSplitTile * kSplitLdsRow;     // 64 rows of T^T
 #pragma unroll
     for (int o0 = 0; o0 < NOUT; o0 += R) {
         // transpose into LDS: column ci + e of T becomes row ci + e of T^T
@@ -452,25 +463,28 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
             if (o0 + oo >= NOUT) break;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float col[4] = {v[o0 + oo][0][e], v[o0 + oo][1][e], v[o0 + oo][2][e], v[o0 + oo][3][e]};
-                uint2 pl[P];
-                split4<P>(col, pl, fp16, scale);
+                float col[kSplitRPT];
+#pragma unroll
+                for (int i = 0; i < kSplitRPT; ++i) col[i] = v[o0 + oo][i][e];
+                uint32_t pl[P][kSplitRPT / 2];
+                splitN<P, kSplitRPT>(col, pl, fp16, scale);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    *reinterpret_cast<uint2*>(lds + (oo * P + p) * TILE_U16 + (ci + e) * kSplitLdsRow + ri) = pl[p];
+                    store_terms<kSplitRPT>(lds + (oo * P + p) * TILE_U16 + (ci + e) * kSplitLdsRow + ri, pl[p]);
             }
         }
         __syncthreads();
-        // write back whole rows of T^T: 8 chunks of 16 bytes per row
+        // write back whole rows of T^T: kSplitRows / 8 chunks of 16 bytes per row
+        constexpr int CPR = kSplitRows / 8;
 #pragma unroll
         for (int oo = 0; oo < R; ++oo) {
             if (o0 + oo >= NOUT) break;
 #pragma unroll
             for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int id = tid + 256 * h;
-                    const int j = id >> 3, q = id & 7;
+                for (int h = 0; h < kSplitTile * CPR / kStreamThreads; ++h) {
+                    const int id = tid + kStreamThreads * h;
+                    const int j = id / CPR, q = id % CPR;
                     const uint4 val = *reinterpret_cast<const uint4*>(lds + (oo * P + p) * TILE_U16 + j * kSplitLdsRow + 8 * q);
                     *reinterpret_cast<uint4*>(base + ((int64_t)(o0 + oo) * P + p) * LL + blk_offset(C0 + j, R0 + 8 * q, L)) =
                         val;
@@ -493,7 +507,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
     const ProbDesc& d = src.get(src.locate(xcd_slot(blockIdx.x, gridDim.x), local));
     const int side = blockIdx.y;
     const int64_t L = d.leaf;
-    const int64_t tiles = (L / kSplitTile) * (L / kSplitTile);
+    const int64_t tiles = (L / kSplitRows) * (L / kSplitTile);
     if (d.depth >= 2) {
         const int64_t c1 = local % 7, rest = local / 7;
         const int64_t tile = rest % tiles, node = 7 * (rest / tiles) + c1;
@@ -822,7 +836,7 @@ int64_t blocks_divide(const ProbDesc& d, int level) {
     return pow7(level) * ((q4 + kStreamPerBlock - 1) / kStreamPerBlock);
 }
 int64_t blocks_split(const ProbDesc& d) {
-    const int64_t tiles = (d.leaf / kSplitTile) * (d.leaf / kSplitTile);
+    const int64_t tiles = (d.leaf / kSplitRows) * (d.leaf / kSplitTile);
     const int64_t nodes = d.depth > 0 ? pow7(d.depth - 1) : 1;
     return nodes * tiles;
 }
