@@ -350,8 +350,11 @@ constexpr int kSplitRPT = kSplitRows / 16;          // rows per thread
 constexpr int kSplitLdsRow = kSplitRows + 8;        // bf16 per LDS row of T^T (16-byte aligned)
 static_assert(kSplitRows == 64 || kSplitRows == 32, "split tile rows");
 
-template <int P> struct SplitRound { static constexpr int R = 2; };
-template <> struct SplitRound<3> { static constexpr int R = 1; };
+#ifndef STK_SPLIT_ROUND2
+#define STK_SPLIT_ROUND2 2
+#endif
+template <int P> struct SplitRound { static constexpr int R = STK_SPLIT_ROUND2; };
+template <> struct SplitRound<3> { static constexpr int R = (STK_SPLIT_ROUND2 + 1) / 2; };
 
 // v[o][i][e]: output o at tile row i, column e of this thread's 4 x 4 piece.
 // FUSED: X is the operand of the grandparent (edge 4L) and the parent's

@@ -142,7 +142,7 @@ def test_serving_alone_vs_mix_bitwise(S):
         reqs = []
         for i in range(18):
             n = int(rng.choice([128, 200, 512, 777, 1024, 2048]))
-            prec = int(rng.choice([0, 1]))
+            prec = int(rng.choice([0, 1, 17]))     # 17: BF16X3, Winograd's variant
             A, B = inputs.normal(n, 50 + i), inputs.normal(n, 90 + i)
             reqs.append((n, prec, dev(A), dev(B), A, B))
         alone = []
