@@ -8,11 +8,14 @@ resident in HBM before the timed region; the timed region is K back-to-back
 multiplies on one stream, bracketed by device synchronisation.
 
 Reported beside it, on the same GPU and inputs: the plain binary32 Strassen
-path (autotuned depth), the classical product (depth 0, binary32 leaves) and
-BF16x6; the error of the headline result against the FP64 oracle on 256
+path (autotuned depth), the classical product (depth 0, binary32 leaves),
+FP16x3, BF16x6, BF16x3 at depth 1, Winograd's variant, a rectangular product
+and torch.matmul (external context), each with Freivalds' check; the
+per-phase times with algorithmic bytes and flops; the error of the headline result against the FP64 oracle on 256
 sampled rows and Freivalds' check; the leaf GEMM's roofline; the oracle's own
-speed on the host (sampled rows); and a serving run (Poisson stream of
-requests of mixed sizes and precisions) with p50/p99 latency.
+speed on the host (about 1000 sampled rows, ~10 s); and a serving run
+(Poisson stream of requests of mixed sizes and precisions) with p50/p99
+latency.
 
 Prints ONE JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -54,6 +57,8 @@ def parse():
     p.add_argument("--no-serving", action="store_true")
     p.add_argument("--serving-requests", type=int, default=2000)
     p.add_argument("--rows", type=int, default=256, help="sampled rows for the error check")
+    p.add_argument("--cpu-rows", type=int, default=768,
+                   help="extra sampled rows the oracle computes for the CPU baseline timing")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "leaf_gemm_traffic.txt"),
                    help="HBM traffic of the leaf GEMM measured by rocprofv3 counters, if present")
     p.add_argument("--phase-reps", type=int, default=5, help="repetitions of each phase for the live roofline")
@@ -344,13 +349,20 @@ def main() -> int:
         compare["torch_matmul_fp32_external"] = {"ms": m_, "tflops": 2.0 * n ** 3 / (m_ * 1e-3) * 1e-12,
                                                  "freivalds": freivalds()}
 
-    # -- CPU baseline: the oracle on the sampled rows ---------------------------
+    # -- CPU baseline: the oracle on a bounded sample of rows -----------------------
+    # (the error-check rows plus more rows, about 10 s of host work in total)
     cpu = None
     if not args.no_cpu_baseline:
-        flops = 2.0 * rows.size * n * n
-        cpu = {"value": flops / t_rows * 1e-12, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
-               "sample": f"classical FP64 triple loop, {rows.size} sampled rows of the n={n} product "
-                         f"({flops:.3g} flops, {t_rows:.1f} s)"}
+        extra = inputs.sample_rows(n, args.cpu_rows, 7)
+        t0 = time.perf_counter()
+        oracle.rows_f64(Ah, Bh, extra)
+        t_extra = time.perf_counter() - t0
+        nrows, secs = rows.size + extra.size, t_rows + t_extra
+        flops = 2.0 * nrows * n * n
+        cpu = {"value": flops / secs * 1e-12, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"classical FP64 triple loop, {nrows} sampled rows of the n={n} product "
+                         f"({flops:.3g} flops, {secs:.1f} s)"}
+        log(f"cpu baseline: {cpu['value']:.4f} TFLOP/s on {cpu['cores']} threads ({secs:.1f} s)")
 
     # -- serving -----------------------------------------------------------------
     serving = None
