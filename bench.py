@@ -17,7 +17,7 @@ speed on the host (about 1000 sampled rows, ~10 s); and a serving run
 (Poisson stream of requests of mixed sizes and precisions) with p50/p99
 latency.
 
-Prints ONE JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -166,7 +166,7 @@ def read_traffic(path: str, key: str):
 def main() -> int:
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         return 2
     import torch
 

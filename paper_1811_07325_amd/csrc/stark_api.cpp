@@ -36,11 +36,20 @@ void set_error(const char* fmt, ...) {
 const char* get_error() { return t_err.c_str(); }
 
 int gemm_grid(stark_ctx* ctx, int planes, int tile, int64_t tiles) {
-    static int occ_cache[3][3] = {{0}};
+    // resident blocks per CU of every (planes, tile) variant, queried once
+    // (thread-safe static initialisation; the serving thread calls this too)
+    struct Occ {
+        int v[3][3];
+        Occ() {
+            const int pl[3] = {0, 2, 3}, tl[3] = {128, 64, 256};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) v[a][b] = gemm_blocks_per_cu(pl[a], tl[b]);
+        }
+    };
+    static const Occ occ;
     const int pi = planes == 0 ? 0 : planes == 2 ? 1 : 2;
     const int ti = tile == 128 ? 0 : tile == 64 ? 1 : 2;
-    if (!occ_cache[pi][ti]) occ_cache[pi][ti] = gemm_blocks_per_cu(planes, tile);
-    const int64_t g = (int64_t)ctx->num_cu * occ_cache[pi][ti];
+    const int64_t g = (int64_t)ctx->num_cu * occ.v[pi][ti];
     return (int)std::min<int64_t>(g, tiles);
 }
 
