@@ -533,9 +533,11 @@ __global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
 // keeps every leaf operand (at most 2^depth max) below 2^14; Winograd's
 // variant sums up to 4 blocks per level, so there e = 14 - 2 depth - E.
 // ---------------------------------------------------------------------------
+constexpr int kAbsThreads = 1024;   // 16 waves per part: 2 x 256 parts fill the chip
+
 template <class Src>
-__global__ __launch_bounds__(kStreamThreads) void k_absmax(Src src) {
-    __shared__ float part[kStreamThreads];
+__global__ __launch_bounds__(kAbsThreads) void k_absmax(Src src) {
+    __shared__ float part[kAbsThreads];
     int64_t local;
     const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
     const int side = blockIdx.y;
@@ -549,21 +551,21 @@ __global__ __launch_bounds__(kStreamThreads) void k_absmax(Src src) {
     const float4* X4 = reinterpret_cast<const float4*>(X + lo);
     static_assert(kStreamUnroll == 4, "the final reduction below folds four partial maxima");
     float m[kStreamUnroll] = {};
-    for (int64_t i = threadIdx.x; i < nv; i += kStreamUnroll * kStreamThreads) {
+    for (int64_t i = threadIdx.x; i < nv; i += kStreamUnroll * kAbsThreads) {
         float4 v[kStreamUnroll];
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u) {
-            const int64_t j = i + u * kStreamThreads;
+            const int64_t j = i + u * kAbsThreads;
             v[u] = j < nv ? X4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u)
             m[u] = fmaxf(m[u], fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)), fmaxf(fabsf(v[u].z), fabsf(v[u].w))));
     }
-    for (int64_t i = lo + 4 * nv + threadIdx.x; i < hi; i += kStreamThreads) m[0] = fmaxf(m[0], fabsf(X[i]));
+    for (int64_t i = lo + 4 * nv + threadIdx.x; i < hi; i += kAbsThreads) m[0] = fmaxf(m[0], fabsf(X[i]));
     part[threadIdx.x] = fmaxf(fmaxf(m[0], m[1]), fmaxf(m[2], m[3]));
     __syncthreads();
-    for (int w = kStreamThreads / 2; w > 0; w >>= 1) {
+    for (int w = kAbsThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) part[threadIdx.x] = fmaxf(part[threadIdx.x], part[threadIdx.x + w]);
         __syncthreads();
     }
@@ -857,7 +859,7 @@ hipError_t launch_pad(const Src& s, int64_t blocks, hipStream_t st) {
 }
 template <class Src>
 hipError_t launch_absmax(const Src& s, int64_t blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_absmax<Src>), dim3((unsigned)blocks, 2), dim3(kStreamThreads), 0, st, s);
+    hipLaunchKernelGGL((k_absmax<Src>), dim3((unsigned)blocks, 2), dim3(kAbsThreads), 0, st, s);
     return hipGetLastError();
 }
 template <class Src>

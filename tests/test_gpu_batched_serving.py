@@ -196,6 +196,38 @@ def test_serving_generated_operands_and_checksums(S):
         S.stark_destroy(c)
 
 
+def test_serving_concurrent_submitters(S):
+    """Four host threads submit and poll at once: every request completes and
+    its checksum equals the one it gets alone."""
+    import threading
+    c = S.stark_create(0, hbm_budget_bytes=4 << 30, max_slots=4)
+    try:
+        spec = [(256 + 64 * (i % 5), i % 2, 500 + i) for i in range(24)]
+        alone = {}
+        for n, p, seed in spec:
+            t = S.stark_submit(c, n, p, S.STARK_DEPTH_AUTO, seed=seed, tag=seed)
+            alone[seed] = wait(S, c, [t])[t].checksum
+        got, errors = {}, []
+
+        def worker(part):
+            try:
+                ts = [S.stark_submit(c, n, p, S.STARK_DEPTH_AUTO, seed=seed, tag=seed) for n, p, seed in part]
+                for t, r in wait(S, c, ts).items():
+                    got[r.tag] = r.checksum
+            except Exception as e:      # surfaced below
+                errors.append(e)
+
+        threads = [threading.Thread(target=worker, args=(spec[k::4],)) for k in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        assert not errors, errors
+        assert got == alone
+    finally:
+        S.stark_destroy(c)
+
+
 def test_serving_admission_respects_budget(S):
     budget = 64 << 20
     c = S.stark_create(0, hbm_budget_bytes=budget, max_slots=8)

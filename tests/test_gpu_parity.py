@@ -395,6 +395,28 @@ def test_graph_replays_are_identical(S, ctx):
     assert np.array_equal(outs[0], run(S, ctx, A, B, 2, "fp32"))
 
 
+def test_graph_cache_eviction_keeps_results(S, ctx):
+    """More (plan, pointer) keys than the graph cache holds (64): every call
+    still gives the same result, including replays of evicted and re-captured
+    graphs."""
+    n = 256
+    A = inputs.uniform(n, 21)
+    B = inputs.uniform(n, 22)
+    dA, dB = dev(A), dev(B)
+    ref = run(S, ctx, A, B, 1, "bf16x3")
+    Cs = [torch.empty((n, n), dtype=torch.float32, device="cuda") for _ in range(80)]
+    s = torch.cuda.Stream()
+    for rep in range(3):                     # eager, capture (evicting), capture again
+        for C in Cs:
+            C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        for C in Cs:
+            S.stark_gemm(ctx, dA, dB, C, n, 1, PREC["bf16x3"], s)
+        s.synchronize()
+        for i, C in enumerate(Cs):
+            assert np.array_equal(C.cpu().numpy(), ref), (rep, i)
+
+
 def test_generator_matches_host_twin(S):
     n = 300
     X = torch.empty((n, n), dtype=torch.float32, device="cuda")
