@@ -23,6 +23,13 @@
  *     enqueued on `stream` has completed.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls enqueue work and return; they do not synchronise.
+ *   - A context's workspace holds one call's intermediates at a time, so the
+ *     calls that use it (stark_gemm, stark_gemm_phases, stark_gemm_batched,
+ *     stark_gemm_rect, stark_tune) run one after another on the device
+ *     whatever streams they are given: each waits for the previous one's
+ *     work.  Multiplies meant to overlap on the device go through the
+ *     serving calls (stark_submit) or separate contexts.  Contexts are
+ *     thread-safe; calls from several threads are serialised.
  *   - Status codes are returned; no exception crosses the ABI.  On failure
  *     stark_last_error() returns a message (thread-local, valid until the
  *     next failing call on that thread).

@@ -70,6 +70,9 @@ struct stark_ctx {
     std::map<stk::GraphKey, int> graph_seen;
     hipStream_t side_stream = nullptr;   // used when the caller passes the null stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // end of the last call that used the workspace or the rectangular blocks
+    hipEvent_t ws_done = nullptr;
+    bool ws_recorded = false;
     // autotuner
     std::map<std::pair<int64_t, int>, stk::TuneEntry> tune;
     std::string tune_path;
@@ -91,6 +94,13 @@ stark_status run_cached(stark_ctx* ctx, const Plan& p, const float* A, const flo
 
 // Make sure the context workspace holds `bytes` (caller lock held).
 stark_status ensure_workspace(stark_ctx* ctx, size_t bytes);
+
+// The workspace and the rectangular blocks hold one call's intermediates at a
+// time.  ws_wait orders the work a call is about to enqueue on `st` after the
+// previous such call's work (whatever stream that used); ws_done records the
+// end of this call's work on `st`.  Caller lock held.
+stark_status ws_wait(stark_ctx* ctx, hipStream_t st);
+stark_status ws_done(stark_ctx* ctx, hipStream_t st, stark_status rc);
 
 // User operands of one multiply: non-NULL, n > 0, 16-byte aligned, C
 // overlapping neither A nor B.  Sets the error message.

@@ -46,6 +46,33 @@ static bool overlap(const void* a, size_t an, const void* b, size_t bn) {
     return pa < pb + bn && pb < pa + an;
 }
 
+// Pack, multiply the block products as one batch, reduce (stark_gemm_rect).
+static stark_status rect_run(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t m, int64_t k, int64_t n,
+                             int64_t s, int64_t MB, int64_t KB, int64_t NB, int depth, int prec, hipStream_t st) {
+    const size_t ss = (size_t)s * (size_t)s;
+    const int64_t count = MB * NB * KB;
+    float* Ablk = static_cast<float*>(ctx->rect);
+    float* Bblk = Ablk + (size_t)(MB * KB) * ss;
+    float* Pblk = Bblk + (size_t)(KB * NB) * ss;
+    STK_HIP(launch_pack_blocks(A, m, k, k, Ablk, s, st));
+    STK_HIP(launch_pack_blocks(B, k, n, n, Bblk, s, st));
+    std::vector<const float*> pa(count), pb(count);
+    std::vector<float*> pc(count);
+    std::vector<int64_t> ns(count, s);
+    for (int64_t i = 0; i < MB; ++i)
+        for (int64_t j = 0; j < NB; ++j)
+            for (int64_t p = 0; p < KB; ++p) {
+                const int64_t t = (i * NB + j) * KB + p;
+                pa[t] = Ablk + (size_t)(i * KB + p) * ss;
+                pb[t] = Bblk + (size_t)(p * NB + j) * ss;
+                pc[t] = Pblk + (size_t)t * ss;
+            }
+    const stark_status rc = gemm_batched(ctx, (int)count, pa.data(), pb.data(), pc.data(), ns.data(), depth, prec, st);
+    if (rc != STARK_OK) return rc;
+    STK_HIP(launch_reduce_blocks(Pblk, C, m, n, s, MB, NB, KB, st));
+    return STARK_OK;
+}
+
 }  // namespace stk
 
 using namespace stk;
@@ -84,29 +111,10 @@ stark_status stark_gemm_rect(stark_ctx* ctx, const float* A, const float* B, flo
     hipStream_t st = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(ctx->mu);
     STK_HIP(hipSetDevice(ctx->device));
-    const size_t ss = (size_t)s * (size_t)s;
-    stark_status rc = ensure_rect(ctx, (size_t)(MB * KB + KB * NB + count) * ss * sizeof(float));
+    stark_status rc = ensure_rect(ctx, (size_t)(MB * KB + KB * NB + count) * (size_t)s * (size_t)s * sizeof(float));
     if (rc != STARK_OK) return rc;
-    float* Ablk = static_cast<float*>(ctx->rect);
-    float* Bblk = Ablk + (size_t)(MB * KB) * ss;
-    float* Pblk = Bblk + (size_t)(KB * NB) * ss;
-    STK_HIP(launch_pack_blocks(A, m, k, k, Ablk, s, st));
-    STK_HIP(launch_pack_blocks(B, k, n, n, Bblk, s, st));
-    std::vector<const float*> pa(count), pb(count);
-    std::vector<float*> pc(count);
-    std::vector<int64_t> ns(count, s);
-    for (int64_t i = 0; i < MB; ++i)
-        for (int64_t j = 0; j < NB; ++j)
-            for (int64_t p = 0; p < KB; ++p) {
-                const int64_t t = (i * NB + j) * KB + p;
-                pa[t] = Ablk + (size_t)(i * KB + p) * ss;
-                pb[t] = Bblk + (size_t)(p * NB + j) * ss;
-                pc[t] = Pblk + (size_t)t * ss;
-            }
-    rc = gemm_batched(ctx, (int)count, pa.data(), pb.data(), pc.data(), ns.data(), depth, (int)prec, st);
-    if (rc != STARK_OK) return rc;
-    STK_HIP(launch_reduce_blocks(Pblk, C, m, n, s, MB, NB, KB, st));
-    return STARK_OK;
+    if ((rc = ws_wait(ctx, st)) != STARK_OK) return rc;
+    return ws_done(ctx, st, rect_run(ctx, A, B, C, m, k, n, s, MB, KB, NB, depth, (int)prec, st));
 }
 
 }  // extern "C"

@@ -111,6 +111,20 @@ stark_status ensure_workspace(stark_ctx* ctx, size_t bytes) {
     return STARK_OK;
 }
 
+stark_status ws_wait(stark_ctx* ctx, hipStream_t st) {
+    if (ctx->ws_recorded) STK_HIP(hipStreamWaitEvent(st, ctx->ws_done, 0));
+    return STARK_OK;
+}
+
+stark_status ws_done(stark_ctx* ctx, hipStream_t st, stark_status rc) {
+    // recorded after a failure too: part of the call's work may be enqueued
+    const hipError_t e = hipEventRecord(ctx->ws_done, st);
+    if (e == hipSuccess) ctx->ws_recorded = true;
+    if (rc != STARK_OK) return rc;
+    STK_HIP(e);
+    return STARK_OK;
+}
+
 static constexpr size_t kMaxGraphs = 64;
 
 stark_status run_cached(stark_ctx* ctx, const Plan& p, const float* A, const float* B, float* C, void* ws,
@@ -265,6 +279,7 @@ stark_status stark_create(stark_ctx** out, const stark_config* cfg) {
     STK_HIP(hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking));
     STK_HIP(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
     STK_HIP(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+    STK_HIP(hipEventCreateWithFlags(&ctx->ws_done, hipEventDisableTiming));
     size_t free_b = 0, total_b = 0;
     STK_HIP(hipMemGetInfo(&free_b, &total_b));
     ctx->hbm_budget = c.hbm_budget_bytes ? c.hbm_budget_bytes : free_b / 4 * 3;
@@ -296,6 +311,7 @@ stark_status stark_destroy(stark_ctx* ctx) {
     if (ctx->side_stream) (void)hipStreamDestroy(ctx->side_stream);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->ws_done) (void)hipEventDestroy(ctx->ws_done);
     delete ctx;
     return rc;
 }
@@ -311,7 +327,8 @@ stark_status stark_gemm(stark_ctx* ctx, const float* A, const float* B, float* C
     std::lock_guard<std::mutex> lk(ctx->mu);
     STK_HIP(hipSetDevice(ctx->device));
     if (depth == STARK_DEPTH_AUTO) {
-        rc = tuned_depth(ctx, A, B, C, n, (int)prec, st, &depth);
+        if ((rc = ws_wait(ctx, st)) != STARK_OK) return rc;
+        rc = ws_done(ctx, st, tuned_depth(ctx, A, B, C, n, (int)prec, st, &depth));
         if (rc != STARK_OK) return rc;
     }
     Plan p;
@@ -319,7 +336,8 @@ stark_status stark_gemm(stark_ctx* ctx, const float* A, const float* B, float* C
     if (!why.empty()) { set_error("%s (n=%lld depth=%d)", why.c_str(), (long long)n, depth); return STARK_EINVAL; }
     rc = ensure_workspace(ctx, p.bytes);
     if (rc != STARK_OK) return rc;
-    return run_cached(ctx, p, A, B, C, ctx->ws, st);
+    if ((rc = ws_wait(ctx, st)) != STARK_OK) return rc;
+    return ws_done(ctx, st, run_cached(ctx, p, A, B, C, ctx->ws, st));
 }
 
 stark_status stark_gemm_phases(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int depth,
@@ -335,7 +353,9 @@ stark_status stark_gemm_phases(stark_ctx* ctx, const float* A, const float* B, f
     STK_HIP(hipSetDevice(ctx->device));
     rc = ensure_workspace(ctx, p.bytes);
     if (rc != STARK_OK) return rc;
-    return run_plan(ctx, p, make_desc(p, A, B, C, ctx->ws), mask, static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((rc = ws_wait(ctx, st)) != STARK_OK) return rc;
+    return ws_done(ctx, st, run_plan(ctx, p, make_desc(p, A, B, C, ctx->ws), mask, st));
 }
 
 stark_status stark_tune(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, stark_precision prec,
@@ -350,8 +370,9 @@ stark_status stark_tune(stark_ctx* ctx, const float* A, const float* B, float* C
     STK_HIP(hipSetDevice(ctx->device));
     std::vector<TuneEntry> res;
     int depth = 0;
-    rc = tune_range(ctx, A, B, C, n, (int)prec, min_depth, max_depth, tol, static_cast<hipStream_t>(stream), res,
-                    &depth);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((rc = ws_wait(ctx, st)) != STARK_OK) return rc;
+    rc = ws_done(ctx, st, tune_range(ctx, A, B, C, n, (int)prec, min_depth, max_depth, tol, st, res, &depth));
     if (rc != STARK_OK) return rc;
     if (points)
         for (int i = 0; i < cap && i < (int)res.size(); ++i)
@@ -380,7 +401,10 @@ stark_status stark_gemm_batched(stark_ctx* ctx, int count, const float* const* A
     if (depth < 0) { set_error("batched calls need an explicit depth >= 0"); return STARK_EINVAL; }
     std::lock_guard<std::mutex> lk(ctx->mu);
     STK_HIP(hipSetDevice(ctx->device));
-    return gemm_batched(ctx, count, A, B, C, n, depth, (int)prec, static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const stark_status rc = ws_wait(ctx, st);
+    if (rc != STARK_OK) return rc;
+    return ws_done(ctx, st, gemm_batched(ctx, count, A, B, C, n, depth, (int)prec, st));
 }
 
 stark_status stark_matvec_f64(const float* M, const double* x, double* y, int64_t n, void* stream) {

@@ -417,6 +417,46 @@ def test_graph_cache_eviction_keeps_results(S, ctx):
             assert np.array_equal(C.cpu().numpy(), ref), (rep, i)
 
 
+def test_calls_on_two_streams_run_in_order(S, ctx):
+    """One context, calls on two streams issued back to back: the calls share
+    the context's workspace, so each must wait for the previous one's work.
+    Every result equals its single-call result bit for bit (eager, captured
+    and replayed), also with a batched and a rectangular call in the mix."""
+    n, depth, p = 2048, 2, PREC["bf16x3"]
+    print(f"case n={n} depth={depth} prec=bf16x3 two streams", flush=True)
+    probs = [(inputs.uniform(n, 31 + 2 * i), inputs.uniform(n, 32 + 2 * i)) for i in range(3)]
+    refs = [run(S, ctx, A, B, depth, "bf16x3") for A, B in probs]
+    dA = [dev(A) for A, _ in probs]
+    dB = [dev(B) for _, B in probs]
+    Cs = [torch.empty((n, n), dtype=torch.float32, device="cuda") for _ in range(3)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(3):                     # eager, capture, replay
+        for C in Cs:
+            C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        S.stark_gemm(ctx, dA[0], dB[0], Cs[0], n, depth, p, s1)
+        S.stark_gemm(ctx, dA[1], dB[1], Cs[1], n, depth, p, s2)
+        S.stark_gemm_batched(ctx, [dA[2]], [dB[2]], [Cs[2]], [n], depth, p, s1)
+        s1.synchronize()
+        s2.synchronize()
+        for i, C in enumerate(Cs):
+            assert np.array_equal(C.cpu().numpy(), refs[i]), (rep, i)
+    # a rectangular call on one stream right after a square call on the other
+    m, k = 1024, 2048
+    A = np.random.default_rng(41).integers(-8, 9, (m, k)).astype(np.float32)
+    B = np.random.default_rng(42).integers(-8, 9, (k, n)).astype(np.float32)
+    dRa, dRb = dev(A), dev(B)
+    Cr = torch.full((m, n), float("nan"), dtype=torch.float32, device="cuda")
+    Cs[0].fill_(float("nan"))
+    torch.cuda.synchronize()
+    S.stark_gemm(ctx, dA[0], dB[0], Cs[0], n, depth, p, s1)
+    S.stark_gemm_rect(ctx, dRa, dRb, Cr, m, k, n, 1, p, s2)
+    s1.synchronize()
+    s2.synchronize()
+    assert np.array_equal(Cs[0].cpu().numpy(), refs[0])
+    assert np.array_equal(Cr.cpu().numpy(), oracle.gemm_rect_f64(A, B).astype(np.float32))
+
+
 def test_generator_matches_host_twin(S):
     n = 300
     X = torch.empty((n, n), dtype=torch.float32, device="cuda")
