@@ -41,6 +41,7 @@ struct BatchEntry {
     std::vector<BatchLaunch> launches;
     hipGraphExec_t exec = nullptr;
     int uses = 0;
+    uint64_t last_use = 0;
 };
 
 struct BatchKey {
@@ -57,6 +58,33 @@ struct BatchKey {
 
 std::mutex g_batch_mu;
 std::map<std::pair<stark_ctx*, BatchKey>, BatchEntry> g_batches;
+uint64_t g_batch_clock = 0;
+constexpr size_t kMaxBatches = 64;   // cached batches per context (least recently used evicted)
+
+void release_entry(BatchEntry& e) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.dev) (void)hipFree(e.dev);
+    e.exec = nullptr;
+    e.dev = nullptr;
+}
+
+// Make room for one more entry of `ctx`.  The victim's last launch belongs to
+// an earlier call, which has finished once the last call's end event has
+// (every call waits for the one before it).  Lock held.
+stark_status evict_for(stark_ctx* ctx) {
+    auto victim = g_batches.end();
+    size_t mine = 0;
+    for (auto it = g_batches.begin(); it != g_batches.end(); ++it) {
+        if (it->first.first != ctx) continue;
+        ++mine;
+        if (victim == g_batches.end() || it->second.last_use < victim->second.last_use) victim = it;
+    }
+    if (mine < kMaxBatches) return STARK_OK;
+    if (ctx->ws_recorded) STK_HIP(hipEventSynchronize(ctx->ws_done));
+    release_entry(victim->second);
+    g_batches.erase(victim);
+    return STARK_OK;
+}
 
 stark_status enqueue(stark_ctx* ctx, const BatchEntry& e, hipStream_t st) {
     const ProbDesc* table = static_cast<const ProbDesc*>(e.dev);
@@ -112,6 +140,8 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
     std::lock_guard<std::mutex> lk(g_batch_mu);
     auto it = g_batches.find({ctx, key});
     if (it == g_batches.end()) {
+        rc = evict_for(ctx);
+        if (rc != STARK_OK) return rc;
         BatchEntry e;
         e.count = count;
         e.planes = plans[0].planes;
@@ -173,6 +203,7 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
     BatchEntry& e = it->second;
     hipStream_t gs = key.stream;
     e.uses++;
+    e.last_use = ++g_batch_clock;
     if (e.uses == 1) return enqueue(ctx, e, st);
     if (!e.exec) {
         hipGraph_t g = nullptr;
@@ -206,8 +237,7 @@ void batched_release(stark_ctx* ctx) {
     std::lock_guard<std::mutex> lk(g_batch_mu);
     for (auto it = g_batches.begin(); it != g_batches.end();) {
         if (it->first.first == ctx) {
-            if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
-            if (it->second.dev) (void)hipFree(it->second.dev);
+            release_entry(it->second);
             it = g_batches.erase(it);
         } else {
             ++it;

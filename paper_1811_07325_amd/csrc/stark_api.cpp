@@ -154,9 +154,12 @@ stark_status run_cached(stark_ctx* ctx, const Plan& p, const float* A, const flo
         (void)hipGraphDestroy(g);
         STK_HIP(ei);
         if (ctx->graphs.size() >= kMaxGraphs) {
+            // the evicted graph's last launch belongs to an earlier call, which
+            // has finished once the last call's end event has (every call
+            // waits for the one before it); its stream may be gone by now
             const GraphKey old = ctx->graph_lru.back();
             ctx->graph_lru.pop_back();
-            STK_HIP(hipStreamSynchronize(old.stream));
+            if (ctx->ws_recorded) STK_HIP(hipEventSynchronize(ctx->ws_done));
             (void)hipGraphExecDestroy(ctx->graphs[old]);
             ctx->graphs.erase(old);
         }

@@ -417,6 +417,28 @@ def test_graph_cache_eviction_keeps_results(S, ctx):
             assert np.array_equal(C.cpu().numpy(), ref), (rep, i)
 
 
+def test_batched_cache_eviction_keeps_results(S, ctx):
+    """More distinct batches than the batched-call cache keeps per context
+    (64): every call still gives the single-call result, including replays of
+    evicted and re-captured batches."""
+    n = 256
+    A = inputs.uniform(n, 23)
+    B = inputs.uniform(n, 24)
+    dA, dB = dev(A), dev(B)
+    ref = run(S, ctx, A, B, 1, "bf16x3")
+    Cs = [torch.empty((n, n), dtype=torch.float32, device="cuda") for _ in range(80)]
+    s = torch.cuda.Stream()
+    for rep in range(3):                     # eager, capture (evicting), capture again
+        for C in Cs:
+            C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        for C in Cs:
+            S.stark_gemm_batched(ctx, [dA], [dB], [C], [n], 1, PREC["bf16x3"], s)
+        s.synchronize()
+        for i, C in enumerate(Cs):
+            assert np.array_equal(C.cpu().numpy(), ref), (rep, i)
+
+
 def test_calls_on_two_streams_run_in_order(S, ctx):
     """One context, calls on two streams issued back to back: the calls share
     the context's workspace, so each must wait for the previous one's work.
