@@ -210,7 +210,8 @@ typedef struct {
     uint64_t completed;
     uint64_t failed;
     double throughput_tflops; /* effective 2n^3/t over the engine's busy span     */
-    double p50_ms;            /* latency submit -> done                            */
+    double p50_ms;            /* latency submit -> done, over the most recent
+                                 2^20 completed requests                           */
     double p99_ms;
     double max_inflight_bytes;
     int max_concurrent;       /* most requests on the device at once               */

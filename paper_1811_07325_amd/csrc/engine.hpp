@@ -53,6 +53,7 @@ class Engine {
 public:
     static constexpr int kMaxBypass = 8;
     static constexpr size_t kMaxQueue = 1 << 16;
+    static constexpr size_t kLatWindow = 1 << 20;   // latencies kept for p50 / p99
 
     Engine(stark_ctx* ctx, size_t budget, int slots, hipError_t* err);
     ~Engine();
@@ -99,7 +100,8 @@ private:
     bool stop_ = false;
     std::thread thread_;
     // statistics
-    std::vector<double> lat_ms_;
+    std::vector<double> lat_ms_;       // ring of the last kLatWindow latencies
+    size_t lat_next_ = 0;
     uint64_t completed_ = 0, failed_ = 0;
     double flops_ = 0, first_admit_ = -1, last_done_ = 0;
     size_t max_bytes_ = 0;

@@ -284,7 +284,10 @@ void Engine::finish(int si) {
     q->t_done = now_us();
     q->status = STARK_OK;
     ++completed_;
-    lat_ms_.push_back((q->t_done - q->t_submit) * 1e-3);
+    const double lat = (q->t_done - q->t_submit) * 1e-3;
+    if (lat_ms_.size() < kLatWindow) lat_ms_.push_back(lat);
+    else lat_ms_[lat_next_] = lat;
+    lat_next_ = (lat_next_ + 1) % kLatWindow;
     flops_ += 2.0 * (double)q->r.n * (double)q->r.n * (double)q->r.n;
     last_done_ = q->t_done;
     arena_.free(q->off, q->bytes);
@@ -350,6 +353,15 @@ void Engine::loop() {
     }
 }
 
+// Guards the creation of a context's engine (first stark_submit) against
+// readers of the pointer (stark_poll, stark_stats on other threads).
+static std::mutex g_engine_mu;
+
+static Engine* engine_of(stark_ctx* ctx) {
+    std::lock_guard<std::mutex> lk(g_engine_mu);
+    return ctx->engine.get();
+}
+
 static stark_status ensure_engine(stark_ctx* ctx) {
     if (ctx->engine) return STARK_OK;
     hipError_t err = hipSuccess;
@@ -370,26 +382,29 @@ extern "C" {
 
 stark_status stark_submit(stark_ctx* ctx, const stark_request* r, uint64_t* ticket) {
     if (!ctx || !r || !ticket) { set_error("NULL argument"); return STARK_EINVAL; }
-    static std::mutex start_mu;
+    Engine* e = nullptr;
     {
-        std::lock_guard<std::mutex> lk(start_mu);
+        std::lock_guard<std::mutex> lk(g_engine_mu);
         const stark_status rc = ensure_engine(ctx);
         if (rc != STARK_OK) return rc;
+        e = ctx->engine.get();
     }
-    return ctx->engine->submit(*r, ticket);
+    return e->submit(*r, ticket);
 }
 
 stark_status stark_poll(stark_ctx* ctx, uint64_t ticket, stark_result* out) {
     if (!ctx) { set_error("ctx is NULL"); return STARK_EINVAL; }
-    if (!ctx->engine) { set_error("unknown ticket %llu", (unsigned long long)ticket); return STARK_ENOTFOUND; }
-    return ctx->engine->poll(ticket, out);
+    Engine* e = engine_of(ctx);
+    if (!e) { set_error("unknown ticket %llu", (unsigned long long)ticket); return STARK_ENOTFOUND; }
+    return e->poll(ticket, out);
 }
 
 stark_status stark_stats(stark_ctx* ctx, stark_stats_t* out) {
     if (!ctx || !out) { set_error("NULL argument"); return STARK_EINVAL; }
     std::memset(out, 0, sizeof *out);
-    if (!ctx->engine) return STARK_OK;
-    return ctx->engine->stats(out);
+    Engine* e = engine_of(ctx);
+    if (!e) return STARK_OK;
+    return e->stats(out);
 }
 
 }  // extern "C"
