@@ -210,21 +210,24 @@ def main() -> int:
         log(f"autotuning {args.precision} depth in [{args.min_depth}, {args.max_depth}]")
         tune_pts = S.stark_tune(ctx, A, B, C, n, prec, args.min_depth, args.max_depth, 1e-5, st)
         ok = [p for p in tune_pts if p[2] <= 1e-5]
-        depth = min(ok, key=lambda p: p[1])[0] if ok else min(tune_pts, key=lambda p: p[2])[0]
+        depth, tile = (min(ok, key=lambda p: p[1]) if ok else min(tune_pts, key=lambda p: p[2]))[::3]
         for p in tune_pts:
-            log(f"  depth {p[0]}: {p[1]:.3f} ms, freivalds {p[2]:.2e}")
+            log(f"  depth {p[0]} tile {p[3]}: {p[1]:.3f} ms, freivalds {p[2]:.2e}")
+        log(f"  chosen: depth {depth}, tile {tile}")
     else:
-        depth = args.depth
+        depth, tile = args.depth, S.stark_plan_info(n, args.depth, prec).gemm_tile
 
     # -- timed region -----------------------------------------------------------
-    log(f"timing {args.precision} depth {depth}: warmup {args.warmup}, steps {args.steps}")
-    ms = timed(depth, prec, args.steps, args.warmup)
+    # after autotuning, the library runs what the autotuner recorded (depth and tile)
+    run_depth = S.STARK_DEPTH_AUTO if args.depth is None else depth
+    log(f"timing {args.precision} depth {depth} tile {tile}: warmup {args.warmup}, steps {args.steps}")
+    ms = timed(run_depth, prec, args.steps, args.warmup)
     eff = 2.0 * n ** 3 / (ms * 1e-3) * 1e-12
     log(f"  {ms:.3f} ms/step, {eff:.1f} effective TFLOP/s")
 
     # -- error of the headline result (C holds it) ------------------------------
     import oracle
-    S.stark_gemm(ctx, A, B, C, n, depth, prec, st)
+    S.stark_gemm(ctx, A, B, C, n, run_depth, prec, st)
     st.synchronize()
     rows = inputs.sample_rows(n, args.rows, 2)
     Ah = A.cpu().numpy()
@@ -252,7 +255,10 @@ def main() -> int:
     log(f"  error: rel_frob(rows)={rel_rows:.3e} max_abs={max_abs:.3e} freivalds={freiv:.3e}")
 
     # -- roofline of the dominant kernel (leaf GEMM), timed live --------------
+    # (phase-only launches use the planner's tile class)
     plan = S.stark_plan_info(n, depth, prec)
+    if plan.gemm_tile != tile:
+        log(f"  note: phases use the planner's tile {plan.gemm_tile}, the timed multiply tile {tile}")
     S.stark_gemm_phases(ctx, A, B, C, n, depth, prec, S.STARK_PHASE_DIVIDE, st)
     reps = max(1, args.phase_reps)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
@@ -290,7 +296,8 @@ def main() -> int:
         f"({achieved * 1e-12:.1f} TF/s of {unit_peak * 1e-12:.0f}), combine {t_comb:.3f} ms")
     roofline = {"bound": "mfma", "achieved": achieved * 1e-12, "peak": unit_peak * 1e-12, "unit": "TFLOP/s",
                 "frac": achieved / unit_peak, "traffic": traffic,
-                "kernel": ("k_gemm_bf16_big" if plan.gemm_tile == 256 else "k_gemm_bf16") if planes else "k_gemm_f32",
+                "kernel": ("k_gemm_bf16" if planes else "k_gemm_f32") + ("_big" if plan.gemm_tile == 256 else ""),
+                "gemm_tile": plan.gemm_tile,
                 "work_per_launch": f"{nleaf} leaves x {prods} x 2*{L}^3 flops"}
 
     # -- comparisons on the same GPU ----------------------------------------------
@@ -305,17 +312,18 @@ def main() -> int:
                                      ("fp16x3_winograd", S.STARK_FP16X3 | S.STARK_WINOGRAD, 2, 4),
                                      ("fp32_winograd", S.STARK_FP32 | S.STARK_WINOGRAD, 1, 4)):
             if dmin == dmax:
-                d_ = dmin
+                d_, t_ = dmin, S.stark_plan_info(n, dmin, p_).gemm_tile
                 pts = []
             else:
                 pts = S.stark_tune(ctx, A, B, C, n, p_, dmin, dmax, 1e-5, st)
                 okp = [p for p in pts if p[2] <= 1e-5]
-                d_ = min(okp, key=lambda p: p[1])[0] if okp else min(pts, key=lambda p: p[2])[0]
-            m_ = timed(d_, p_, max(3, args.steps // 2), 1)
-            compare[name] = {"depth": d_, "ms": m_, "tflops": 2.0 * n ** 3 / (m_ * 1e-3) * 1e-12,
+                d_, t_ = (min(okp, key=lambda p: p[1]) if okp else min(pts, key=lambda p: p[2]))[::3]
+            # a tuned leg runs what the autotuner recorded (depth and tile)
+            m_ = timed(d_ if dmin == dmax else S.STARK_DEPTH_AUTO, p_, max(3, args.steps // 2), 1)
+            compare[name] = {"depth": d_, "tile": t_, "ms": m_, "tflops": 2.0 * n ** 3 / (m_ * 1e-3) * 1e-12,
                              "freivalds": freivalds(),
-                             "tune": [{"depth": a, "ms": b, "err": c} for a, b, c in pts]}
-            log(f"  {name}: depth {d_}, {m_:.3f} ms, {compare[name]['tflops']:.1f} TF/s, "
+                             "tune": [{"depth": a, "ms": b, "err": c, "tile": t} for a, b, c, t in pts]}
+            log(f"  {name}: depth {d_} tile {t_}, {m_:.3f} ms, {compare[name]['tflops']:.1f} TF/s, "
                 f"freivalds {compare[name]['freivalds']:.2e}")
         # rectangular: (n/2) x n times n x (n/2), square-block partition,
         # operands are views of the headline A, B and C storage
@@ -378,10 +386,11 @@ def main() -> int:
         "config": {"workload": f"strassen C=AB n={n} normal(0,1) {args.precision} depth={depth}"
                                f" (autotuned in [{args.min_depth},{args.max_depth}])" if args.depth is None else
                                f"strassen C=AB n={n} normal(0,1) {args.precision} depth={depth}",
-                   "n": n, "depth": depth, "precision": args.precision, "leaf": L, "n_pad": plan.n_pad},
+                   "n": n, "depth": depth, "gemm_tile": tile, "precision": args.precision, "leaf": L,
+                   "n_pad": plan.n_pad},
         "error": {"rel_frob_sampled_rows": rel_rows, "max_abs_sampled_rows": max_abs, "freivalds": freiv,
                   "rows": int(rows.size), "target": 1e-5, "meets_target": rel_rows <= 1e-5},
-        "tune": [{"depth": a, "ms": b, "err": c} for a, b, c in tune_pts],
+        "tune": [{"depth": a, "ms": b, "err": c, "tile": t} for a, b, c, t in tune_pts],
         "phases": phases, "roofline": roofline, "cpu_baseline": cpu, "compare": compare, "serving": serving,
     }
     print(json.dumps(out), flush=True)

@@ -142,21 +142,26 @@ stark_status stark_gemm_rect(stark_ctx* ctx, const float* A, const float* B, flo
 int64_t stark_rect_block_edge(int64_t m, int64_t k, int64_t n, int depth);
 
 /* One measured point of the autotuner: depth, median time of three runs
- * (ms) and the relative error estimated by Freivalds' check in binary64. */
+ * (ms), the relative error estimated by Freivalds' check in binary64, and the
+ * leaf-GEMM tile class (64, 128 or 256: the edge of the square output tile one
+ * workgroup computes). */
 typedef struct {
     int depth;
     double ms;
     double err;
+    int tile;
 } stark_tune_point;
 
-/* Autotune the depth for (n, p): run every depth in [min_depth, max_depth]
- * (clamped to stark_max_depth(n)) on the caller's A and B (C is overwritten),
- * time each after a warm-up, estimate its error as
- * ||C x - A (B x)|| / ||A (B x)|| for a Gaussian x, and record the fastest
- * depth whose error is <= tol (tol <= 0: 1e-5 or STARK_TUNE_TOL), else the
- * most accurate.  Later calls with depth = STARK_DEPTH_AUTO use the record.
- * Up to `cap` points are written to `points` (may be NULL) and their number
- * to *count (may be NULL).  Synchronises `stream`. */
+/* Autotune the depth and the leaf-GEMM tile class for (n, p): for every depth
+ * in [min_depth, max_depth] (clamped to stark_max_depth(n)), run the planner's
+ * tile class and its valid neighbours (64 / 128 / 256 dividing the leaf) on
+ * the caller's A and B (C is overwritten), time each after a warm-up,
+ * estimate its error as ||C x - A (B x)|| / ||A (B x)|| for a Gaussian x, and
+ * record the fastest (depth, tile) whose error is <= tol (tol <= 0: 1e-5 or
+ * STARK_TUNE_TOL), else the most accurate.  Later calls with depth =
+ * STARK_DEPTH_AUTO (stark_gemm, stark_submit) use the record.  Up to `cap`
+ * points are written to `points` (may be NULL) and their number to *count
+ * (may be NULL).  Synchronises `stream`. */
 stark_status stark_tune(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n,
                         stark_precision p, int min_depth, int max_depth, double tol,
                         stark_tune_point* points, int cap, int* count, void* stream);

@@ -35,18 +35,19 @@ const char* get_error();
 
 struct GraphKey {
     int64_t n;
-    int depth, precision;
+    int depth, precision, tile;
     const void *A, *B, *C, *ws;
     hipStream_t stream;
     bool operator<(const GraphKey& o) const {
-        return std::tie(n, depth, precision, A, B, C, ws, stream) <
-               std::tie(o.n, o.depth, o.precision, o.A, o.B, o.C, o.ws, o.stream);
+        return std::tie(n, depth, precision, tile, A, B, C, ws, stream) <
+               std::tie(o.n, o.depth, o.precision, o.tile, o.A, o.B, o.C, o.ws, o.stream);
     }
     bool operator==(const GraphKey& o) const { return !(*this < o) && !(o < *this); }
 };
 
 struct TuneEntry {
     int depth;
+    int tile;   // leaf-GEMM tile class (0: the planner's rule)
     double ms;
     double err;
 };
@@ -106,14 +107,14 @@ stark_status ws_done(stark_ctx* ctx, hipStream_t st, stark_status rc);
 // overlapping neither A nor B.  Sets the error message.
 stark_status check_operands(const float* A, const float* B, const float* C, int64_t n);
 
-// Autotuner (tuner.cpp): depth for (n, precision), measuring on the caller's
-// operands if the size is new.  Caller lock held.
+// Autotuner (tuner.cpp): depth and leaf-GEMM tile class for (n, precision),
+// measuring on the caller's operands if the size is new.  Caller lock held.
 stark_status tuned_depth(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int precision,
-                         hipStream_t st, int* depth);
+                         hipStream_t st, int* depth, int* tile);
 void tuner_load(stark_ctx* ctx);
 stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int precision,
                         int dmin, int dmax, double tol, hipStream_t st, std::vector<TuneEntry>& results,
-                        int* depth);
+                        int* depth, int* tile);
 
 // Leaf-GEMM grid for `tiles` tiles: resident blocks per CU x CUs, capped.
 int gemm_grid(stark_ctx* ctx, int planes, int tile, int64_t tiles);

@@ -51,6 +51,17 @@ int max_depth_for(int64_t n) {
     return k;
 }
 
+int tile_candidates(const Plan& p, int out[3]) {
+    const int classes[3] = {64, 128, 256};
+    int me = 0;
+    while (classes[me] != p.tile) ++me;
+    int k = 0;
+    out[k++] = p.tile;
+    for (int j : {me - 1, me + 1})
+        if (j >= 0 && j < 3 && p.leaf % classes[j] == 0) out[k++] = classes[j];
+    return k;
+}
+
 int planes_for(int precision) {
     if (precision & ~(STARK_PRECISION_MASK | STARK_WINOGRAD)) return -1;
     switch (precision & STARK_PRECISION_MASK) {
@@ -64,7 +75,7 @@ int planes_for(int precision) {
 
 static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
-std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
+std::string make_plan(int64_t n, int depth, int precision, Plan& p, int tile) {
     p = Plan();
     if (n <= 0) return "n must be positive";
     if (n > (int64_t)1 << 20) return "n too large";
@@ -88,6 +99,11 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p) {
         if (p.leaf % 256 == 0 && t256 >= 256) p.tile = 256;
         else if (p.leaf % 128 == 0 && (t128 >= 128 || p.leaf % 64 != 0)) p.tile = 128;
         else p.tile = 64;
+    }
+    if (tile != 0) {
+        if (tile != 64 && tile != 128 && tile != 256) return "tile must be 64, 128 or 256";
+        if (p.leaf % tile != 0) return "tile does not divide the leaf";
+        p.tile = tile;
     }
     for (int l = 0; l < STK_MAXD; ++l) {
         p.div_a[l] = p.div_b[l] = p.comb[l] = -1;

@@ -36,8 +36,14 @@ int64_t padded_size(int64_t n, int depth);
 int max_depth_for(int64_t n);
 int planes_for(int precision);  // -1 if unknown (STARK_WINOGRAD may be set)
 
-// Returns "" on success, else the reason the plan is invalid.
-std::string make_plan(int64_t n, int depth, int precision, Plan& out);
+// Returns "" on success, else the reason the plan is invalid.  tile = 0
+// takes the rule's leaf-GEMM tile class; 64, 128 or 256 (dividing the leaf)
+// forces one (the autotuner's choice).
+std::string make_plan(int64_t n, int depth, int precision, Plan& out, int tile = 0);
+
+// Tile classes the autotuner measures for a plan: its own and the valid
+// neighbouring classes (64, 128, 256 that divide the leaf).
+int tile_candidates(const Plan& p, int out[3]);
 
 // Descriptor of the plan with user/workspace pointers filled in.
 ProbDesc make_desc(const Plan& p, const float* A, const float* B, float* C, void* ws);

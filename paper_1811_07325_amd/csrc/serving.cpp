@@ -148,14 +148,21 @@ stark_status Engine::submit(const stark_request& r, uint64_t* ticket) {
     q->r = r;
     q->gen = gen;
     q->own_c = (r.C == nullptr);
-    int depth = r.depth;
+    int depth = r.depth, tile = 0;
     if (depth == STARK_DEPTH_AUTO) {
         std::lock_guard<std::mutex> lk(ctx_->mu);
         auto it = ctx_->tune.find({r.n, (int)r.precision});
-        depth = it != ctx_->tune.end() ? it->second.depth : default_serving_depth(r.n, (int)r.precision);
+        if (it != ctx_->tune.end()) {
+            depth = it->second.depth;
+            tile = it->second.tile;
+        } else {
+            depth = default_serving_depth(r.n, (int)r.precision);
+        }
     }
-    depth = std::min(std::max(depth, 0), max_depth_for(r.n));
-    const std::string why = make_plan(r.n, depth, (int)r.precision, q->plan);
+    const int clamped = std::min(std::max(depth, 0), max_depth_for(r.n));
+    if (clamped != depth) tile = 0;
+    depth = clamped;
+    const std::string why = make_plan(r.n, depth, (int)r.precision, q->plan, tile);
     if (!why.empty()) { set_error("%s", why.c_str()); return STARK_EINVAL; }
     q->bytes = request_footprint(q->plan, q->gen, q->own_c);
     if (q->bytes > arena_.size()) {

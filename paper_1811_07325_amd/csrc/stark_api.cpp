@@ -131,7 +131,7 @@ stark_status run_cached(stark_ctx* ctx, const Plan& p, const float* A, const flo
                         hipStream_t st) {
     const ProbDesc d = make_desc(p, A, B, C, ws);
     hipStream_t gs = st ? st : ctx->side_stream;   // capture needs a non-null stream
-    const GraphKey key{p.n, p.depth, p.precision, A, B, C, ws, gs};
+    const GraphKey key{p.n, p.depth, p.precision, p.tile, A, B, C, ws, gs};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         int& seen = ctx->graph_seen[key];
@@ -329,13 +329,14 @@ stark_status stark_gemm(stark_ctx* ctx, const float* A, const float* B, float* C
     hipStream_t st = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(ctx->mu);
     STK_HIP(hipSetDevice(ctx->device));
+    int tile = 0;   // the planner's rule unless the autotuner chose one
     if (depth == STARK_DEPTH_AUTO) {
         if ((rc = ws_wait(ctx, st)) != STARK_OK) return rc;
-        rc = ws_done(ctx, st, tuned_depth(ctx, A, B, C, n, (int)prec, st, &depth));
+        rc = ws_done(ctx, st, tuned_depth(ctx, A, B, C, n, (int)prec, st, &depth, &tile));
         if (rc != STARK_OK) return rc;
     }
     Plan p;
-    const std::string why = make_plan(n, depth, (int)prec, p);
+    const std::string why = make_plan(n, depth, (int)prec, p, tile);
     if (!why.empty()) { set_error("%s (n=%lld depth=%d)", why.c_str(), (long long)n, depth); return STARK_EINVAL; }
     rc = ensure_workspace(ctx, p.bytes);
     if (rc != STARK_OK) return rc;
@@ -372,14 +373,15 @@ stark_status stark_tune(stark_ctx* ctx, const float* A, const float* B, float* C
     std::lock_guard<std::mutex> lk(ctx->mu);
     STK_HIP(hipSetDevice(ctx->device));
     std::vector<TuneEntry> res;
-    int depth = 0;
+    int depth = 0, tile = 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((rc = ws_wait(ctx, st)) != STARK_OK) return rc;
-    rc = ws_done(ctx, st, tune_range(ctx, A, B, C, n, (int)prec, min_depth, max_depth, tol, st, res, &depth));
+    rc = ws_done(ctx, st,
+                 tune_range(ctx, A, B, C, n, (int)prec, min_depth, max_depth, tol, st, res, &depth, &tile));
     if (rc != STARK_OK) return rc;
     if (points)
         for (int i = 0; i < cap && i < (int)res.size(); ++i)
-            points[i] = stark_tune_point{res[i].depth, res[i].ms, res[i].err};
+            points[i] = stark_tune_point{res[i].depth, res[i].ms, res[i].err, res[i].tile};
     if (count) *count = (int)res.size();
     return STARK_OK;
 }

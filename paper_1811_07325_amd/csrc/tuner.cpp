@@ -1,12 +1,14 @@
 // Autotuner for the recursion depth (the paper's block-size choice: wall clock
 // against partition size is U-shaped, with an optimum per matrix size,
-// Section V-C).  For a new (n, precision) it runs every usable depth on the
-// caller's operands, times three runs after a warm-up with HIP events, and
-// measures each result's error with Freivalds' check in binary64 on the GPU:
-// e = ||C x - A (B x)|| / ||A (B x)|| for a Gaussian x, whose square has the
-// squared relative Frobenius error as its expectation.  The fastest depth
-// whose error is within the tolerance (default 1e-5, STARK_TUNE_TOL) wins;
-// if none is, the most accurate.  Results persist in a small text file.
+// Section V-C) and the leaf-GEMM tile class.  For a new (n, precision) it
+// runs every usable depth, each with the planner's tile class and its valid
+// neighbours, on the caller's operands, times three runs after a warm-up with
+// HIP events, and measures each result's error with Freivalds' check in
+// binary64 on the GPU: e = ||C x - A (B x)|| / ||A (B x)|| for a Gaussian x,
+// whose square has the squared relative Frobenius error as its expectation.
+// The fastest (depth, tile) whose error is within the tolerance (default
+// 1e-5, STARK_TUNE_TOL) wins; if none is, the most accurate.  Results persist
+// in a small text file.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,10 +26,10 @@ static void tuner_save(stark_ctx* ctx) {
     if (ctx->tune_path.empty()) return;
     FILE* f = std::fopen(ctx->tune_path.c_str(), "w");
     if (!f) return;
-    std::fprintf(f, "# n precision depth ms freivalds_error\n");
+    std::fprintf(f, "# n precision depth ms freivalds_error tile\n");
     for (const auto& kv : ctx->tune)
-        std::fprintf(f, "%lld %d %d %.6f %.6e\n", (long long)kv.first.first, kv.first.second, kv.second.depth,
-                     kv.second.ms, kv.second.err);
+        std::fprintf(f, "%lld %d %d %.6f %.6e %d\n", (long long)kv.first.first, kv.first.second, kv.second.depth,
+                     kv.second.ms, kv.second.err, kv.second.tile);
     std::fclose(f);
 }
 
@@ -39,18 +41,20 @@ void tuner_load(stark_ctx* ctx) {
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
         long long n;
-        int prec, depth;
+        int prec, depth, tile = 0;
         double ms, err;
-        if (std::sscanf(line, "%lld %d %d %lf %lf", &n, &prec, &depth, &ms, &err) == 5 && n > 0 && depth >= 0 &&
-            depth <= max_depth_for(n))
-            ctx->tune[{(int64_t)n, prec}] = TuneEntry{depth, ms, err};
+        const int got = std::sscanf(line, "%lld %d %d %lf %lf %d", &n, &prec, &depth, &ms, &err, &tile);
+        Plan p;
+        if (got >= 5 && n > 0 && depth >= 0 && depth <= max_depth_for(n) &&
+            make_plan(n, depth, prec, p, got == 6 ? tile : 0).empty())
+            ctx->tune[{(int64_t)n, prec}] = TuneEntry{depth, got == 6 ? tile : 0, ms, err};
     }
     std::fclose(f);
 }
 
 stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int precision,
                         int dmin, int dmax, double tol, hipStream_t st, std::vector<TuneEntry>& results,
-                        int* depth) {
+                        int* depth, int* tile) {
     const int maxd = std::min(dmax, max_depth_for(n));
     if (tol <= 0) tol = ctx->tune_tol;
     // Gaussian probe (fixed seed) and A (B x), binary64.
@@ -84,35 +88,47 @@ stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C
     double nref = 0.0;
     for (double v : habx) nref += v * v;
     nref = std::sqrt(nref);
-    for (int d = std::max(dmin, 0); d <= maxd && rc == STARK_OK; ++d) {
-        Plan p;
-        if (!make_plan(n, d, precision, p).empty()) continue;
-        if (ensure_workspace(ctx, p.bytes) != STARK_OK) break;   // deeper plans only grow
+    // One (depth, tile) point: warm-up, three timed runs, Freivalds error.
+    // False stops the search (an error, or a workspace that cannot grow:
+    // deeper plans only need more).
+    auto measure = [&](const Plan& p) -> bool {
+        if (ensure_workspace(ctx, p.bytes) != STARK_OK) return false;
         const ProbDesc desc = make_desc(p, A, B, C, ctx->ws);
-        if ((rc = run_plan(ctx, p, desc, STARK_PHASE_ALL, st)) != STARK_OK) break;
+        if ((rc = run_plan(ctx, p, desc, STARK_PHASE_ALL, st)) != STARK_OK) return false;
         std::vector<float> times;
-        for (int r = 0; r < 3 && rc == STARK_OK; ++r) {
+        for (int r = 0; r < 3; ++r) {
             float ms = 0.f;
-            if ((e = hipEventRecord(e0, st)) != hipSuccess) { fail("event", e); break; }
-            if ((rc = run_plan(ctx, p, desc, STARK_PHASE_ALL, st)) != STARK_OK) break;
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) { fail("event", e); return false; }
+            if ((rc = run_plan(ctx, p, desc, STARK_PHASE_ALL, st)) != STARK_OK) return false;
             if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
                 (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
                 fail("timing", e);
-                break;
+                return false;
             }
             times.push_back(ms);
         }
-        if (rc != STARK_OK) break;
         if ((e = launch_matvec_f64(C, dx, dcx, n, st)) != hipSuccess ||
             (e = hipMemcpyAsync(hcx.data(), dcx, n * 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
             (e = hipStreamSynchronize(st)) != hipSuccess) {
             fail("error check", e);
-            break;
+            return false;
         }
         double num = 0.0;
         for (int64_t i = 0; i < n; ++i) num += (hcx[i] - habx[i]) * (hcx[i] - habx[i]);
         std::sort(times.begin(), times.end());
-        results.push_back(TuneEntry{d, times[times.size() / 2], nref > 0 ? std::sqrt(num) / nref : 0.0});
+        results.push_back(TuneEntry{p.depth, p.tile, times[times.size() / 2], nref > 0 ? std::sqrt(num) / nref : 0.0});
+        return true;
+    };
+    bool more = rc == STARK_OK;
+    for (int d = std::max(dmin, 0); d <= maxd && more; ++d) {
+        Plan rule;
+        if (!make_plan(n, d, precision, rule).empty()) continue;
+        int tiles[3];
+        const int ntiles = tile_candidates(rule, tiles);
+        for (int ti = 0; ti < ntiles && more; ++ti) {
+            Plan p;
+            if (make_plan(n, d, precision, p, tiles[ti]).empty()) more = measure(p);
+        }
     }
     if (dx) (void)hipFree(dx);
     if (dbx) (void)hipFree(dbx);
@@ -134,18 +150,20 @@ stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C
     ctx->tune[{n, precision}] = *best;
     tuner_save(ctx);
     *depth = best->depth;
+    *tile = best->tile;
     return STARK_OK;
 }
 
 stark_status tuned_depth(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int precision,
-                         hipStream_t st, int* depth) {
+                         hipStream_t st, int* depth, int* tile) {
     auto it = ctx->tune.find({n, precision});
     if (it != ctx->tune.end()) {
         *depth = it->second.depth;
+        *tile = it->second.tile;
         return STARK_OK;
     }
     std::vector<TuneEntry> results;
-    return tune_range(ctx, A, B, C, n, precision, 0, 5, 0.0, st, results, depth);
+    return tune_range(ctx, A, B, C, n, precision, 0, 5, 0.0, st, results, depth, tile);
 }
 
 }  // namespace stk

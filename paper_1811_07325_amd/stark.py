@@ -75,7 +75,7 @@ class stark_stats_t(ctypes.Structure):
 
 
 class stark_tune_point(ctypes.Structure):
-    _fields_ = [("depth", ctypes.c_int), ("ms", ctypes.c_double), ("err", ctypes.c_double)]
+    _fields_ = [("depth", ctypes.c_int), ("ms", ctypes.c_double), ("err", ctypes.c_double), ("tile", ctypes.c_int)]
 
 
 class stark_plan_desc(ctypes.Structure):
@@ -275,13 +275,13 @@ def stark_workspace(ctx):
 
 def stark_tune(ctx, A, B, C, n: int, precision: int, min_depth: int, max_depth: int, tol: float = 0.0,
                stream=None):
-    """Autotune; returns the list of (depth, ms, err) points measured."""
-    cap = 16
+    """Autotune; returns the list of (depth, ms, err, tile) points measured."""
+    cap = 64
     pts = (stark_tune_point * cap)()
     cnt = ctypes.c_int()
     _check("stark_tune", _lib.stark_tune(ctx, _ptr(A), _ptr(B), _ptr(C), n, precision, min_depth, max_depth, tol,
                                          pts, cap, ctypes.byref(cnt), _stream(stream)))
-    return [(pts[i].depth, pts[i].ms, pts[i].err) for i in range(min(cnt.value, cap))]
+    return [(pts[i].depth, pts[i].ms, pts[i].err, pts[i].tile) for i in range(min(cnt.value, cap))]
 
 
 def raw_call(name: str, *args) -> int:

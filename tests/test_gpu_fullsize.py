@@ -116,14 +116,18 @@ def test_n16384_split_precision_autotuned(S, ctx, precision):
     C = torch.empty((n, n), dtype=torch.float32, device="cuda")
     st = torch.cuda.Stream()
     pts = S.stark_tune(ctx, dA, dB, C, n, prec, 2, 4, 1e-5, st)
-    assert sorted(p[0] for p in pts) == [2, 3, 4]
+    assert sorted(set(p[0] for p in pts)) == [2, 3, 4]
+    for d in (2, 3, 4):      # the planner's tile class is always measured; every class divides the leaf
+        assert S.stark_plan_info(n, d, prec).gemm_tile in [p[3] for p in pts if p[0] == d]
+    assert all((n >> p[0]) % p[3] == 0 for p in pts)
     ok = [p for p in pts if p[2] <= 1e-5]
-    depth = min(ok, key=lambda p: p[1])[0] if ok else min(pts, key=lambda p: p[2])[0]
+    tuned = min(ok, key=lambda p: p[1]) if ok else min(pts, key=lambda p: p[2])
+    depth = tuned[0]
     outs = []
-    for _ in range(3):                 # eager, capture, replay
+    for _ in range(3):                 # eager, capture, replay of what the autotuner recorded
         C.fill_(float("nan"))
         torch.cuda.synchronize()
-        S.stark_gemm(ctx, dA, dB, C, n, depth, prec, st)
+        S.stark_gemm(ctx, dA, dB, C, n, S.STARK_DEPTH_AUTO, prec, st)
         st.synchronize()
         outs.append(C.clone())
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
@@ -137,8 +141,8 @@ def test_n16384_split_precision_autotuned(S, ctx, precision):
     S.stark_matvec_f64(C, x, y[2], n, st)
     st.synchronize()
     freiv = float(torch.linalg.norm(y[2] - y[1]) / torch.linalg.norm(y[1]))
-    tuned = next(p for p in pts if p[0] == depth)
-    print(f"n=16384 {precision}: tune {[(d, round(m, 3), f'{e:.2e}') for d, m, e in pts]}; depth {depth}: "
+    print(f"n=16384 {precision}: tune {[(d, t, round(m, 3), f'{e:.2e}') for d, m, e, t in pts]}; "
+          f"depth {depth} tile {tuned[3]}: "
           f"rel_frob(256 rows)={err:.3e} max_abs={mabs:.3e} freivalds={freiv:.3e}")
     assert err <= SPLIT_BOUND[precision](depth)
     # Freivalds' estimate and the sampled rows measure the same error: same order

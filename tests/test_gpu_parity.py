@@ -479,6 +479,30 @@ def test_calls_on_two_streams_run_in_order(S, ctx):
     assert np.array_equal(Cr.cpu().numpy(), oracle.gemm_rect_f64(A, B).astype(np.float32))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3", "bf16x6"])
+def test_tuner_record_selects_tile(S, tmp_path, prec):
+    """A record (n, precision, depth, tile) in the autotuner's cache file makes
+    STARK_DEPTH_AUTO run that depth with that leaf-GEMM tile class: every
+    class dividing the leaf gives the exact integer product."""
+    n, depth = 1024, 1       # leaf 512: tile classes 64, 128 and 256 all divide it
+    print(f"case n={n} depth={depth} prec={prec} tiles 64/128/256", flush=True)
+    A = inputs.integers(n, 51)
+    B = inputs.integers(n, 52)
+    exact = oracle.gemm_i64(A.astype(np.int64), B.astype(np.int64))
+    dA, dB = dev(A), dev(B)
+    for tile in (64, 128, 256):
+        path = tmp_path / f"tune_{prec}_{tile}.txt"
+        path.write_text(f"# n precision depth ms freivalds_error tile\n{n} {PREC[prec]} {depth} 1.0 0.0 {tile}\n")
+        c = S.stark_create(0, tuner_cache=str(path))
+        try:
+            C = torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda")
+            S.stark_gemm(c, dA, dB, C, n, S.STARK_DEPTH_AUTO, PREC[prec], None)
+            torch.cuda.synchronize()
+            assert np.array_equal(C.cpu().numpy().astype(np.int64), exact), tile
+        finally:
+            S.stark_destroy(c)
+
+
 def test_generator_matches_host_twin(S):
     n = 300
     X = torch.empty((n, n), dtype=torch.float32, device="cuda")
