@@ -2,17 +2,20 @@
 // one persistent, grouped launch multiplies every leaf pair M_id = S_id T_id
 // (7^depth of them per problem, all problems of a batch) on the matrix cores.
 //
-//  k_gemm_f32   binary32 operands read in place (views included), MFMA
-//               v_mfma_f32_16x16x4_f32, binary32 accumulation.
-//  k_gemm_bf16  operands pre-split into P bf16 planes (blocked layout of
-//               blk_offset; B transposed so both are k-contiguous), MFMA
-//               v_mfma_f32_16x16x32_bf16 over the cross products of the
-//               planes whose magnitude matters, binary32 accumulation.
-//
-// Both: 256 threads = 4 waves in a 2 x 2 arrangement, each wave a
-// (BM/2) x (BN/2) sub-tile of 16 x 16 MFMA blocks; K advances in steps of 32
-// through a double-buffered LDS tile fed from registers, so the global loads
-// of step k+1 are in flight while step k runs on the matrix cores.
+//  k_gemm_f32_big / _mid / _small
+//                    binary32 operands read in place (views included), MFMA
+//                    v_mfma_f32_16x16x4_f32, binary32 accumulation; one
+//                    kernel body (gemm32_lds) with 256-, 128- and 64-wide
+//                    tiles, operand tiles copied from global memory straight
+//                    into LDS.
+//  k_gemm_bf16_big / _mid / _small
+//                    operands pre-split into P 16-bit planes (blocked layout
+//                    of blk_offset; B transposed so both are k-contiguous),
+//                    MFMA v_mfma_f32_16x16x32_bf16 (or _f16) over the cross
+//                    products of the planes whose magnitude matters, binary32
+//                    accumulation; one kernel body (gemm16_lds) with 256-,
+//                    128- and 64-wide tiles, operand tiles copied from global
+//                    memory straight into LDS.
 // Tile order is static (no atomics, no split-K): tile t of the grid-stride
 // loop is remapped so that the blocks of one XCD (blockIdx mod 8) work on
 // consecutive tiles, and tiles inside a leaf are visited in groups of 8 tile
@@ -49,7 +52,6 @@ __device__ __forceinline__ float unscale_of(const ProbDesc& d) {
     return ldexpf(1.0f, -(ex[0] + ex[1]));
 }
 
-constexpr int kGemmThreads = 256;
 constexpr int kGroupRows = 8;
 
 // Tile coordinates of logical tile `r` of a leaf with tm_cnt x tn_cnt tiles,
@@ -68,127 +70,6 @@ __device__ __forceinline__ void tile_coords(int64_t r, int64_t tm_cnt, int64_t t
 // ---------------------------------------------------------------------------
 // binary32 leaf GEMM.
 // ---------------------------------------------------------------------------
-template <class Src, int BM, int BN>
-__global__ __launch_bounds__(kGemmThreads) void k_gemm_f32(Src src, int64_t total_tiles) {
-    constexpr int BK = 32;
-    constexpr int LDA = BK + 4;          // As[m][k], k contiguous (row 144 B)
-    constexpr int LDB = BN + 4;          // Bs[k][n], n contiguous
-    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
-    constexpr int A_LD = BM * BK / 4 / kGemmThreads;   // float4 loads per thread
-    constexpr int B_LD = BK * BN / 4 / kGemmThreads;
-    __shared__ __attribute__((aligned(16))) float As[2][BM * LDA];
-    __shared__ __attribute__((aligned(16))) float Bs[2][BK * LDB];
-
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
-    const int li = lane & 15, lg = lane >> 4;
-    const int64_t G = gridDim.x;
-    const int64_t slot = xcd_slot(blockIdx.x, G);
-
-    for (int64_t t = slot; t < total_tiles; t += G) {
-        int64_t local;
-        const ProbDesc& d = src.get(src.locate(t, local));
-        const int64_t L = d.leaf;
-        const int64_t tm_cnt = L / BM, tn_cnt = L / BN, tpl = tm_cnt * tn_cnt;
-        const int64_t leaf = local / tpl;
-        int64_t tm, tn;
-        tile_coords(local - leaf * tpl, tm_cnt, tn_cnt, tm, tn);
-        const float *Ap, *Bp;
-        int64_t lda, ldb;
-        resolve(d, 0, d.depth, leaf, Ap, lda);
-        resolve(d, 1, d.depth, leaf, Bp, ldb);
-        float* Cp;
-        int64_t ldc;
-        if (d.depth == 0) { Cp = d.C; ldc = d.n; }
-        else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * L * L; ldc = L; }
-        const bool crop = d.depth == 0 && d.bounded0;   // depth 0 writes C directly
-        const int64_t m0 = tm * BM, n0 = tn * BN;
-
-        f32x4 acc[TM][TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-        float4 ra[A_LD], rb[B_LD];
-        auto gload = [&](int64_t k0) {
-#pragma unroll
-            for (int i = 0; i < A_LD; ++i) {
-                const int idx = tid + kGemmThreads * i;
-                const int row = idx / (BK / 4), kq = idx % (BK / 4);
-                ra[i] = *reinterpret_cast<const float4*>(Ap + (m0 + row) * lda + k0 + 4 * kq);
-            }
-#pragma unroll
-            for (int i = 0; i < B_LD; ++i) {
-                const int idx = tid + kGemmThreads * i;
-                const int kr = idx / (BN / 4), nq = idx % (BN / 4);
-                rb[i] = *reinterpret_cast<const float4*>(Bp + (k0 + kr) * ldb + n0 + 4 * nq);
-            }
-        };
-        auto sstore = [&](int buf) {
-#pragma unroll
-            for (int i = 0; i < A_LD; ++i) {
-                const int idx = tid + kGemmThreads * i;
-                const int row = idx / (BK / 4), kq = idx % (BK / 4);
-                *reinterpret_cast<float4*>(&As[buf][row * LDA + 4 * kq]) = ra[i];
-            }
-#pragma unroll
-            for (int i = 0; i < B_LD; ++i) {
-                const int idx = tid + kGemmThreads * i;
-                const int kr = idx / (BN / 4), nq = idx % (BN / 4);
-                *reinterpret_cast<float4*>(&Bs[buf][kr * LDB + 4 * nq]) = rb[i];
-            }
-        };
-
-        const int64_t KT = L / BK;
-        gload(0);
-        sstore(0);
-        __syncthreads();
-        for (int64_t kt = 0; kt < KT; ++kt) {
-            const int buf = (int)(kt & 1);
-            if (kt + 1 < KT) gload((kt + 1) * BK);
-            const float* as = As[buf];
-            const float* bs = Bs[buf];
-#pragma unroll
-            for (int ks = 0; ks < BK / 16; ++ks) {
-                // MFMA s of this step takes k = 16ks + 4g + s from lane group g.
-                float4 a[TM];
-                float b[TN][4];
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-                    a[i] = *reinterpret_cast<const float4*>(&as[(wm * WM + 16 * i + li) * LDA + 16 * ks + 4 * lg]);
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        b[j][s] = bs[(16 * ks + 4 * lg + s) * LDB + wn * WN + 16 * j + li];
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int i = 0; i < TM; ++i) {
-                        const float av = s == 0 ? a[i].x : s == 1 ? a[i].y : s == 2 ? a[i].z : a[i].w;
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[j][s], acc[i][j], 0, 0, 0);
-                    }
-            }
-            if (kt + 1 < KT) sstore(buf ^ 1);
-            __syncthreads();
-        }
-
-        // D layout of a 16x16 MFMA block: lane (li, lg), element r -> row 4lg + r, column li.
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
-                    const int64_t col = n0 + wn * WN + 16 * j + li;
-                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r];
-                }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // bf16-split leaf GEMM.  Planes p = 0 (hi), 1 (mid), 2 (lo).  The products
@@ -215,127 +96,7 @@ struct SplitProducts<3> {
     }
 };
 
-template <class Src, int BM, int BN, int P, bool F16>
-__global__ __launch_bounds__(kGemmThreads) void k_gemm_bf16(Src src, int64_t total_tiles) {
-    using VT = typename Op16<F16>::T;
-    constexpr int BK = 32;
-    constexpr int LDK = BK + 8;                   // uint16 per LDS row (80 B)
-    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
-    constexpr int A_LD = BM * (BK / 8) / kGemmThreads;  // 16-byte loads per plane
-    constexpr int B_LD = BN * (BK / 8) / kGemmThreads;
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][P][BM * LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][P][BN * LDK];
-
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
-    const int li = lane & 15, lg = lane >> 4;
-    const int64_t G = gridDim.x;
-    const int64_t slot = xcd_slot(blockIdx.x, G);
-
-    for (int64_t t = slot; t < total_tiles; t += G) {
-        int64_t local;
-        const ProbDesc& d = src.get(src.locate(t, local));
-        const int64_t L = d.leaf, LL = L * L;
-        const int64_t tm_cnt = L / BM, tn_cnt = L / BN, tpl = tm_cnt * tn_cnt;
-        const int64_t leaf = local / tpl;
-        int64_t tm, tn;
-        tile_coords(local - leaf * tpl, tm_cnt, tn_cnt, tm, tn);
-        const uint16_t* Ah = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_a + leaf * P * LL;
-        const uint16_t* Bh = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_b + leaf * P * LL;
-        float* Cp;
-        int64_t ldc;
-        if (d.depth == 0) { Cp = d.C; ldc = d.n; }
-        else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
-        const bool crop = d.depth == 0 && d.bounded0;
-        const float unscale = unscale_of(d);
-        const int64_t m0 = tm * BM, n0 = tn * BN;
-
-        f32x4 acc[TM][TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-        uint4 ra[P][A_LD], rb[P][B_LD];
-        auto gload = [&](int64_t k0) {
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-#pragma unroll
-                for (int i = 0; i < A_LD; ++i) {
-                    const int idx = tid + kGemmThreads * i;
-                    const int row = idx >> 2, q = idx & 3;
-                    ra[p][i] = *reinterpret_cast<const uint4*>(Ah + p * LL + blk_offset(m0 + row, k0 + 8 * q, L));
-                }
-#pragma unroll
-                for (int i = 0; i < B_LD; ++i) {
-                    const int idx = tid + kGemmThreads * i;
-                    const int row = idx >> 2, q = idx & 3;
-                    rb[p][i] = *reinterpret_cast<const uint4*>(Bh + p * LL + blk_offset(n0 + row, k0 + 8 * q, L));
-                }
-            }
-        };
-        auto sstore = [&](int buf) {
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-#pragma unroll
-                for (int i = 0; i < A_LD; ++i) {
-                    const int idx = tid + kGemmThreads * i;
-                    const int row = idx >> 2, q = idx & 3;
-                    *reinterpret_cast<uint4*>(&As[buf][p][row * LDK + 8 * q]) = ra[p][i];
-                }
-#pragma unroll
-                for (int i = 0; i < B_LD; ++i) {
-                    const int idx = tid + kGemmThreads * i;
-                    const int row = idx >> 2, q = idx & 3;
-                    *reinterpret_cast<uint4*>(&Bs[buf][p][row * LDK + 8 * q]) = rb[p][i];
-                }
-            }
-        };
-
-        const int64_t KT = L / BK;
-        gload(0);
-        sstore(0);
-        __syncthreads();
-        for (int64_t kt = 0; kt < KT; ++kt) {
-            const int buf = (int)(kt & 1);
-            if (kt + 1 < KT) gload((kt + 1) * BK);
-            VT a[P][TM], b[P][TN];
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-                    a[p][i] = __builtin_bit_cast(VT, *reinterpret_cast<const uint4*>(
-                                                         &As[buf][p][(wm * WM + 16 * i + li) * LDK + 8 * lg]));
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    b[p][j] = __builtin_bit_cast(VT, *reinterpret_cast<const uint4*>(
-                                                         &Bs[buf][p][(wn * WN + 16 * j + li) * LDK + 8 * lg]));
-            }
-#pragma unroll
-            for (int q = 0; q < SplitProducts<P>::count; ++q)
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        acc[i][j] = Op16<F16>::mfma(a[SplitProducts<P>::a(q)][i], b[SplitProducts<P>::b(q)][j],
-                                                    acc[i][j]);
-            if (kt + 1 < KT) sstore(buf ^ 1);
-            __syncthreads();
-        }
-
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
-                    const int64_t col = n0 + wn * WN + 16 * j + li;
-                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r] * unscale;
-                }
-    }
-}
-
+// LDS address space pointer of the direct global->LDS loads.
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 // Configuration of the large-leaf kernel: block tile, wave grid and LDS
@@ -350,6 +111,11 @@ struct BigCfgT {
 template <int P> struct BigCfg;
 template <> struct BigCfg<2> : BigCfgT<256, 256, 2, 4, 2> {};   // 8 waves of 128 x 64, 128 KB LDS
 template <> struct BigCfg<3> : BigCfgT<256, 128, 4, 2, 2> {};   // 8 waves of 64 x 64, 144 KB LDS
+// 128 x 128 and 64 x 64 tiles (leaves too small to fill the chip with
+// 256-wide tiles): 4 waves of 64 x 64 / 32 x 32, two stages (64 / 32 KB for
+// P = 2), two or more blocks per CU.  Three stages were slower for 128 x 128.
+template <int P> struct MidCfg : BigCfgT<128, 128, 2, 2, 2> {};
+template <int P> struct SmallCfg : BigCfgT<64, 64, 2, 2, 2> {};
 
 // Wait until at most N of this wave's vector-memory operations are pending.
 template <int N>
@@ -368,9 +134,8 @@ __device__ __forceinline__ void wait_vmcnt() {
 // as the operands' blocked layout in HBM (blk_offset), so each load copies a
 // contiguous 1 KB block.
 // ---------------------------------------------------------------------------
-template <class Src, int P, bool F16>
-__global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_t total_tiles) {
-    using Cfg = BigCfg<P>;
+template <class Cfg, class Src, int P, bool F16>
+__device__ __forceinline__ void gemm16_lds(Src src, int64_t total_tiles) {
     using VT = typename Op16<F16>::T;
     constexpr int BM = Cfg::BM, BN = Cfg::BN, NW = Cfg::NW, STAGES = Cfg::STAGES;
     constexpr int WAVES_N = Cfg::WAVES_N;
@@ -491,34 +256,64 @@ __global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_
 }
 
 
+template <class Src, int P, bool F16>
+__global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_t total_tiles) {
+    gemm16_lds<BigCfg<P>, Src, P, F16>(src, total_tiles);
+}
+template <class Src, int P, bool F16>
+__global__ __launch_bounds__(MidCfg<P>::NT) void k_gemm_bf16_mid(Src src, int64_t total_tiles) {
+    gemm16_lds<MidCfg<P>, Src, P, F16>(src, total_tiles);
+}
+template <class Src, int P, bool F16>
+__global__ __launch_bounds__(SmallCfg<P>::NT) void k_gemm_bf16_small(Src src, int64_t total_tiles) {
+    gemm16_lds<SmallCfg<P>, Src, P, F16>(src, total_tiles);
+}
+
 // ---------------------------------------------------------------------------
-// binary32 leaf GEMM for large leaves: 256 x 256 block tile, 8 waves of
-// 128 x 64, K steps of 16, three LDS stages filled by direct global->LDS
-// loads straight from the binary32 operands (views included: leading
-// dimension from the recursion), no register staging.
-//   A stage image: [256 rows][4 chunks of 4 k], chunk position c ^ blk_swz(row
+// binary32 leaf GEMM: BM x BN block tile (256 x 256 with 8 waves of 128 x 64
+// for large leaves; 128 x 128 or 64 x 64 with 4 waves otherwise), K steps of
+// 16, three LDS stages filled by direct global->LDS loads straight from the
+// binary32 operands (views included: leading dimension from the recursion),
+// no register staging.
+//   A stage image: [BM rows][4 chunks of 4 k], chunk position c ^ blk_swz(row
 //     mod 16) (as the 16-bit blocked layout), one load = one 16-row block.
-//   B stage image: [16 k][64 chunks of 4 n], chunk position c ^ f32_bswz(k),
-//     one load = one 256-wide k-row.
+//   B stage image: [16 k][BN/4 chunks of 4 n], chunk position c ^ f32_bswz(k),
+//     one load = 256 / BN consecutive k-rows.
 // The permutation is applied on the global side (lane l fetches the chunk
 // that belongs at LDS unit l), so both MFMA operand reads are bank-conflict
-// free.  MFMA s of a step gives lane group g the k = 4g + s, as in
-// k_gemm_f32, so the accumulation sequence (and the result) is the same as
-// that kernel's.
+// free.  MFMA s of a step gives lane group g the k = 4g + s, so every tile
+// size accumulates each output in the same order (ascending k) and gives the
+// same result.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int f32_bswz(int k) { return ((k >> 2) & 1) << 2; }
 
 constexpr int kF32BigThreads = 512;
 
-template <class Src>
-__global__ __launch_bounds__(kF32BigThreads) void k_gemm_f32_big(Src src, int64_t total_tiles) {
-    constexpr int BM = 256, BN = 256, BK = 16, NW = 8, WAVES_N = 4, STAGES = 3;
-    constexpr int WM = 128, WN = 64, TM = WM / 16, TN = WN / 16;
+template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int STAGES_>
+struct F32CfgT {
+    static constexpr int BM = BM_, BN = BN_, WAVES_M = WAVES_M_, WAVES_N = WAVES_N_, STAGES = STAGES_;
+    static constexpr int NW = WAVES_M * WAVES_N, NT = 64 * NW;
+};
+using F32BigCfg = F32CfgT<256, 256, 2, 4, 3>;    // 8 waves of 128 x 64, 96 KB LDS
+using F32MidCfg = F32CfgT<128, 128, 2, 2, 3>;    // 4 waves of 64 x 64, 48 KB LDS
+using F32SmallCfg = F32CfgT<64, 64, 2, 2, 3>;    // 4 waves of 32 x 32, 24 KB LDS
+static_assert(F32BigCfg::NT == kF32BigThreads, "thread count of the 256-wide kernel");
+
+// One B load of a wave moves 256 consecutive floats of the stage image: 256 /
+// BN k-rows (lane l: k-row l / (BN / 4), chunk l % (BN / 4)).
+template <class Cfg, class Src>
+__device__ __forceinline__ void gemm32_lds(Src src, int64_t total_tiles) {
+    constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = 16, NW = Cfg::NW, WAVES_N = Cfg::WAVES_N;
+    constexpr int STAGES = Cfg::STAGES;
+    constexpr int WM = BM / Cfg::WAVES_M, WN = BN / WAVES_N, TM = WM / 16, TN = WN / 16;
     constexpr int AU = BM * BK / 4;                    // 16-byte units of A per stage
     constexpr int UNITS = AU + BK * BN / 4;            // plus B
     constexpr int GA = BM / 16;                        // A blocks of 16 rows per stage
-    static_assert(GA % NW == 0 && BK % NW == 0, "loads must split evenly over the waves");
-    constexpr int LPS = GA / NW + BK / NW;             // direct loads per lane per stage
+    constexpr int CPR = BN / 4;                        // 16-byte chunks per B k-row
+    constexpr int RPL = 64 / CPR;                      // B k-rows per wave load
+    constexpr int GB = BK / RPL;                       // B loads per stage
+    static_assert(BN >= 64 && GA % NW == 0 && GB % NW == 0, "loads must split evenly over the waves");
+    constexpr int LPS = GA / NW + GB / NW;             // direct loads per lane per stage
     __shared__ __attribute__((aligned(16))) uint4 lds[STAGES][UNITS];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -548,10 +343,12 @@ __global__ __launch_bounds__(kF32BigThreads) void k_gemm_f32_big(Src src, int64_
 
         // Per-lane sources.  A block g (rows 16g..16g+15) goes to wave g % NW;
         // lane l fills unit 4*(l/4) + l%4 of the block: row l/4, position
-        // l%4, holding chunk (l%4) ^ blk_swz(l/4).  B k-row r goes to wave
-        // r % NW; lane l fills position l, holding chunk l ^ f32_bswz(r).
+        // l%4, holding chunk (l%4) ^ blk_swz(l/4).  B load q (k-rows RPL q ..)
+        // goes to wave q % NW; lane l fills position l % CPR of k-row
+        // RPL q + l / CPR, holding chunk (l % CPR) ^ f32_bswz(k-row).
         const int arow = lane >> 2;
         const float* a_src = Ap + (m0 + arow) * lda + 4 * ((lane & 3) ^ blk_swz(arow));
+        const int bsub = lane / CPR, bpos = lane % CPR;
         auto issue = [&](int stage, int64_t k0) {
 #pragma unroll
             for (int r = 0; r < GA / NW; ++r) {
@@ -560,10 +357,10 @@ __global__ __launch_bounds__(kF32BigThreads) void k_gemm_f32_big(Src src, int64_
                                                  (lds_void_t*)&lds[stage][64 * g], 16, 0, 0);
             }
 #pragma unroll
-            for (int r = 0; r < BK / NW; ++r) {
-                const int kr = w + NW * r;
-                __builtin_amdgcn_global_load_lds(Bp + (k0 + kr) * ldb + n0 + 4 * (lane ^ f32_bswz(kr)),
-                                                 (lds_void_t*)&lds[stage][AU + 64 * kr], 16, 0, 0);
+            for (int r = 0; r < GB / NW; ++r) {
+                const int q = w + NW * r, kr = RPL * q + bsub;
+                __builtin_amdgcn_global_load_lds(Bp + (k0 + kr) * ldb + n0 + 4 * (bpos ^ f32_bswz(kr)),
+                                                 (lds_void_t*)&lds[stage][AU + 64 * q], 16, 0, 0);
             }
         };
 
@@ -622,12 +419,29 @@ __global__ __launch_bounds__(kF32BigThreads) void k_gemm_f32_big(Src src, int64_
     }
 }
 
+template <class Src>
+__global__ __launch_bounds__(F32BigCfg::NT) void k_gemm_f32_big(Src src, int64_t total_tiles) {
+    gemm32_lds<F32BigCfg, Src>(src, total_tiles);
+}
+template <class Src>
+__global__ __launch_bounds__(F32MidCfg::NT) void k_gemm_f32_mid(Src src, int64_t total_tiles) {
+    gemm32_lds<F32MidCfg, Src>(src, total_tiles);
+}
+template <class Src>
+__global__ __launch_bounds__(F32SmallCfg::NT) void k_gemm_f32_small(Src src, int64_t total_tiles) {
+    gemm32_lds<F32SmallCfg, Src>(src, total_tiles);
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-template <class Src, int BM, int BN>
-static hipError_t launch_f32_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemm_f32<Src, BM, BN>), dim3(grid), dim3(kGemmThreads), 0, st, s, tiles);
+template <class Src>
+static hipError_t launch_f32_tile_t(const Src& s, int tile, int64_t tiles, int grid, hipStream_t st) {
+    if (tile == 128) {
+        hipLaunchKernelGGL((k_gemm_f32_mid<Src>), dim3(grid), dim3(F32MidCfg::NT), 0, st, s, tiles);
+    } else {
+        hipLaunchKernelGGL((k_gemm_f32_small<Src>), dim3(grid), dim3(F32SmallCfg::NT), 0, st, s, tiles);
+    }
     return hipGetLastError();
 }
 template <class Src>
@@ -635,14 +449,18 @@ static hipError_t launch_f32_big_t(const Src& s, int64_t tiles, int grid, hipStr
     hipLaunchKernelGGL((k_gemm_f32_big<Src>), dim3(grid), dim3(kF32BigThreads), 0, st, s, tiles);
     return hipGetLastError();
 }
-template <class Src, int BM, int BN, int P, bool F16>
-static hipError_t launch_bf16_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemm_bf16<Src, BM, BN, P, F16>), dim3(grid), dim3(kGemmThreads), 0, st, s, tiles);
-    return hipGetLastError();
-}
 template <class Src, int P, bool F16>
 static hipError_t launch_bf16_big_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
     hipLaunchKernelGGL((k_gemm_bf16_big<Src, P, F16>), dim3(grid), dim3(BigCfg<P>::NT), 0, st, s, tiles);
+    return hipGetLastError();
+}
+// 16-bit leaf GEMM with a 128- or 64-wide tile
+template <class Src, int P, bool F16>
+static hipError_t launch_bf16_tile_t(const Src& s, int tile, int64_t tiles, int grid, hipStream_t st) {
+    if (tile == 128)
+        hipLaunchKernelGGL((k_gemm_bf16_mid<Src, P, F16>), dim3(grid), dim3(MidCfg<P>::NT), 0, st, s, tiles);
+    else
+        hipLaunchKernelGGL((k_gemm_bf16_small<Src, P, F16>), dim3(grid), dim3(SmallCfg<P>::NT), 0, st, s, tiles);
     return hipGetLastError();
 }
 
@@ -664,34 +482,30 @@ int gemm_blocks_per_cu(int planes, int tile) {
     // Occupancy does not depend on the descriptor source or the 16-bit flavour.
     if (planes == 0)
         return tile == 256   ? occupancy(k_gemm_f32_big<OneProb>, kF32BigThreads)
-               : tile == 128 ? occupancy(k_gemm_f32<OneProb, 128, 128>, kGemmThreads)
-                             : occupancy(k_gemm_f32<OneProb, 64, 64>, kGemmThreads);
+               : tile == 128 ? occupancy(k_gemm_f32_mid<OneProb>, F32MidCfg::NT)
+                             : occupancy(k_gemm_f32_small<OneProb>, F32SmallCfg::NT);
     if (tile == 256)
         return planes == 2 ? occupancy(k_gemm_bf16_big<OneProb, 2, false>, BigCfg<2>::NT)
                            : occupancy(k_gemm_bf16_big<OneProb, 3, false>, BigCfg<3>::NT);
     if (planes == 2)
-        return tile == 128 ? occupancy(k_gemm_bf16<OneProb, 128, 128, 2, false>, kGemmThreads)
-                           : occupancy(k_gemm_bf16<OneProb, 64, 64, 2, false>, kGemmThreads);
-    return tile == 128 ? occupancy(k_gemm_bf16<OneProb, 128, 128, 3, false>, kGemmThreads)
-                       : occupancy(k_gemm_bf16<OneProb, 64, 64, 3, false>, kGemmThreads);
+        return tile == 128 ? occupancy(k_gemm_bf16_mid<OneProb, 2, false>, MidCfg<2>::NT)
+                           : occupancy(k_gemm_bf16_small<OneProb, 2, false>, SmallCfg<2>::NT);
+    return tile == 128 ? occupancy(k_gemm_bf16_mid<OneProb, 3, false>, MidCfg<3>::NT)
+                       : occupancy(k_gemm_bf16_small<OneProb, 3, false>, SmallCfg<3>::NT);
 }
 
 template <class Src>
 hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t tiles, int grid, hipStream_t st) {
-    if (planes == 0) return tile == 256   ? launch_f32_big_t<Src>(s, tiles, grid, st)
-                            : tile == 128 ? launch_f32_t<Src, 128, 128>(s, tiles, grid, st)
-                                          : launch_f32_t<Src, 64, 64>(s, tiles, grid, st);
+    if (planes == 0) return tile == 256 ? launch_f32_big_t<Src>(s, tiles, grid, st)
+                                        : launch_f32_tile_t<Src>(s, tile, tiles, grid, st);
     if (f16) {   // FP16X3: two binary16 planes
         if (tile == 256) return launch_bf16_big_t<Src, 2, true>(s, tiles, grid, st);
-        return tile == 128 ? launch_bf16_t<Src, 128, 128, 2, true>(s, tiles, grid, st)
-                           : launch_bf16_t<Src, 64, 64, 2, true>(s, tiles, grid, st);
+        return launch_bf16_tile_t<Src, 2, true>(s, tile, tiles, grid, st);
     }
     if (tile == 256) return planes == 2 ? launch_bf16_big_t<Src, 2, false>(s, tiles, grid, st)
                                         : launch_bf16_big_t<Src, 3, false>(s, tiles, grid, st);
-    if (planes == 2) return tile == 128 ? launch_bf16_t<Src, 128, 128, 2, false>(s, tiles, grid, st)
-                                        : launch_bf16_t<Src, 64, 64, 2, false>(s, tiles, grid, st);
-    return tile == 128 ? launch_bf16_t<Src, 128, 128, 3, false>(s, tiles, grid, st)
-                       : launch_bf16_t<Src, 64, 64, 3, false>(s, tiles, grid, st);
+    return planes == 2 ? launch_bf16_tile_t<Src, 2, false>(s, tile, tiles, grid, st)
+                       : launch_bf16_tile_t<Src, 3, false>(s, tile, tiles, grid, st);
 }
 
 template hipError_t launch_gemm<OneProb>(const OneProb&, int, int, bool, int64_t, int, hipStream_t);

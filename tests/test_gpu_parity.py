@@ -483,13 +483,18 @@ def test_calls_on_two_streams_run_in_order(S, ctx):
 def test_tuner_record_selects_tile(S, tmp_path, prec):
     """A record (n, precision, depth, tile) in the autotuner's cache file makes
     STARK_DEPTH_AUTO run that depth with that leaf-GEMM tile class: every
-    class dividing the leaf gives the exact integer product."""
+    class dividing the leaf gives the exact integer product, and the same
+    float result bit for bit (same accumulation order), on the oracle's
+    model."""
     n, depth = 1024, 1       # leaf 512: tile classes 64, 128 and 256 all divide it
     print(f"case n={n} depth={depth} prec={prec} tiles 64/128/256", flush=True)
     A = inputs.integers(n, 51)
     B = inputs.integers(n, 52)
     exact = oracle.gemm_i64(A.astype(np.int64), B.astype(np.int64))
     dA, dB = dev(A), dev(B)
+    Af, Bf = inputs.uniform(n, 53), inputs.uniform(n, 54)
+    dAf, dBf = dev(Af), dev(Bf)
+    floats = []
     for tile in (64, 128, 256):
         path = tmp_path / f"tune_{prec}_{tile}.txt"
         path.write_text(f"# n precision depth ms freivalds_error tile\n{n} {PREC[prec]} {depth} 1.0 0.0 {tile}\n")
@@ -499,8 +504,16 @@ def test_tuner_record_selects_tile(S, tmp_path, prec):
             S.stark_gemm(c, dA, dB, C, n, S.STARK_DEPTH_AUTO, PREC[prec], None)
             torch.cuda.synchronize()
             assert np.array_equal(C.cpu().numpy().astype(np.int64), exact), tile
+            C.fill_(float("nan"))
+            S.stark_gemm(c, dAf, dBf, C, n, S.STARK_DEPTH_AUTO, PREC[prec], None)
+            torch.cuda.synchronize()
+            floats.append(C.cpu().numpy())
         finally:
             S.stark_destroy(c)
+    # every tile class accumulates each output in the same order
+    assert np.array_equal(floats[0], floats[1]) and np.array_equal(floats[0], floats[2])
+    model = oracle.strassen_model_f32(Af, Bf, depth, base(prec)[0], n, "strassen")
+    assert rel_f(floats[0], model) < 4 * 2.0 ** -24 * (n >> depth) ** 0.5 * 2 ** depth
 
 
 def test_generator_matches_host_twin(S):
