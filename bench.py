@@ -13,9 +13,11 @@ FP16x3, BF16x6, BF16x3 at depth 1, Winograd's variant, a rectangular product
 and torch.matmul (external context), each with Freivalds' check; the
 per-phase times with algorithmic bytes and flops; the error of the headline result against the FP64 oracle on 256
 sampled rows and Freivalds' check; the leaf GEMM's roofline; the oracle's own
-speed on the host (about 1000 sampled rows, ~10 s); and a serving run
-(Poisson stream of requests of mixed sizes and precisions) with p50/p99
-latency.
+speed on the host (about 1000 sampled rows, ~10 s); a batched run (64
+independent binary32 products of sizes drawn from {256, 384, 1000, 1024,
+2048, 3000, 4096}, one grouped graph-captured launch sequence per depth);
+and a serving run (Poisson stream of requests of mixed sizes and precisions)
+with p50/p99 latency.
 
 Prints ONE JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
@@ -55,6 +57,9 @@ def parse():
     p.add_argument("--no-compare", action="store_true", help="skip the FP32 / classical / BF16x6 legs")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-serving", action="store_true")
+    p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--batched-only", action="store_true",
+                   help="only run the batched workload, print its JSON object and exit")
     p.add_argument("--serving-requests", type=int, default=2000)
     p.add_argument("--rows", type=int, default=256, help="sampled rows for the error check")
     p.add_argument("--cpu-rows", type=int, default=768,
@@ -121,6 +126,51 @@ def run_serving(S, count: int, seed: int = 5, budget: int = 96 << 30, slots: int
     return out
 
 
+def run_batched(S, torch, st, count: int = 64, seed: int = 7) -> dict:
+    """`count` independent products, sizes drawn from {256, 384, 1000, 1024,
+    2048, 3000, 4096} (odd sizes padded), binary32 uniform[-1, 1] operands, in
+    one stark_gemm_batched call (every leaf of every problem in one grouped
+    launch, graph-captured), at depths 0..2 (clamped per problem); Freivalds'
+    check on every product of the fastest depth."""
+    from paper_1811_07325_amd import inputs
+    rng = np.random.default_rng(seed)
+    sizes = [int(x) for x in rng.choice([256, 384, 1000, 1024, 2048, 3000, 4096], count)]
+    As = [torch.from_numpy(inputs.uniform(m, 2 * i)).cuda() for i, m in enumerate(sizes)]
+    Bs = [torch.from_numpy(inputs.uniform(m, 2 * i + 1)).cuda() for i, m in enumerate(sizes)]
+    Cs = [torch.empty((m, m), dtype=torch.float32, device="cuda") for m in sizes]
+    flops = sum(2.0 * m ** 3 for m in sizes)
+    ctx = S.stark_create(0)
+    per_depth = []
+    for depth in (0, 1, 2):
+        for _ in range(2):                     # eager, then captured
+            S.stark_gemm_batched(ctx, As, Bs, Cs, sizes, depth, S.STARK_FP32, st)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(5):
+            S.stark_gemm_batched(ctx, As, Bs, Cs, sizes, depth, S.STARK_FP32, st)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        per_depth.append({"depth": depth, "ms": ms, "tflops": flops / (ms * 1e-3) * 1e-12})
+        log(f"batched {count} fp32 depth {depth}: {ms:.3f} ms, {flops / (ms * 1e-3) * 1e-12:.1f} TF/s")
+    best = min(per_depth, key=lambda r: r["ms"])
+    S.stark_gemm_batched(ctx, As, Bs, Cs, sizes, best["depth"], S.STARK_FP32, st)
+    st.synchronize()
+    worst = 0.0
+    for i, m in enumerate(sizes):
+        x = torch.from_numpy(inputs.gaussian_vector(m, 100 + i)).cuda()
+        y = [torch.empty(m, dtype=torch.float64, device="cuda") for _ in range(3)]
+        S.stark_matvec_f64(Bs[i], x, y[0], m, st)
+        S.stark_matvec_f64(As[i], y[0], y[1], m, st)
+        S.stark_matvec_f64(Cs[i], x, y[2], m, st)
+        st.synchronize()
+        worst = max(worst, float(torch.linalg.norm(y[2] - y[1]) / torch.linalg.norm(y[1])))
+    S.stark_destroy(ctx)
+    return {"problems": count, "sizes": sorted(set(sizes)), "precision": "fp32", "flops": flops,
+            "depth": best["depth"], "ms": best["ms"], "tflops": best["tflops"], "per_depth": per_depth,
+            "freivalds_max": worst}
+
+
 COPY_BYTES = 1 << 30
 
 
@@ -180,6 +230,9 @@ def main() -> int:
     dev = torch.device("cuda", 0)
     st = torch.cuda.Stream(device=dev)
     prec = S.PRECISIONS[args.precision]
+    if args.batched_only:
+        print(json.dumps(run_batched(S, torch, st)), flush=True)
+        return 0
 
     log(f"generating inputs n={n}")
     A = torch.from_numpy(inputs.normal(n, 0)).to(dev)
@@ -373,6 +426,9 @@ def main() -> int:
         log(f"cpu baseline: {cpu['value']:.4f} TFLOP/s on {cpu['cores']} threads ({secs:.1f} s)")
 
     # -- serving -----------------------------------------------------------------
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(S, torch, st)
     serving = None
     if not args.no_serving:
         serving = run_serving(S, count=args.serving_requests)
@@ -391,7 +447,8 @@ def main() -> int:
         "error": {"rel_frob_sampled_rows": rel_rows, "max_abs_sampled_rows": max_abs, "freivalds": freiv,
                   "rows": int(rows.size), "target": 1e-5, "meets_target": rel_rows <= 1e-5},
         "tune": [{"depth": a, "ms": b, "err": c, "tile": t} for a, b, c, t in tune_pts],
-        "phases": phases, "roofline": roofline, "cpu_baseline": cpu, "compare": compare, "serving": serving,
+        "phases": phases, "roofline": roofline, "cpu_baseline": cpu, "compare": compare, "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     return 0
