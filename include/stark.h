@@ -114,6 +114,14 @@ stark_status stark_workspace_size(int64_t n, int depth, stark_precision p, size_
 /* Largest depth usable for n (leaf size >= 64 after padding). */
 int stark_max_depth(int64_t n);
 
+/* Depth (0..3) the library uses for a STARK_DEPTH_AUTO request that no
+ * autotuner record covers (served requests): the one of least modelled time,
+ * from the plan's matrix-core work at the measured rate of its leaf-GEMM tile
+ * class, its streaming bytes and its launch count; at most 1 for BF16X3,
+ * whose error roughly doubles per level.  -1 for n <= 0 or an unknown
+ * precision. */
+int stark_model_depth(int64_t n, stark_precision p);
+
 /* C = A * B with `depth` Strassen levels (Algorithm 1; depth 0 is the
  * classical product on the same leaf kernels).  depth = STARK_DEPTH_AUTO asks
  * the autotuner (which may also run measurements on `stream` the first time a

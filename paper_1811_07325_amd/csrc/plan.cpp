@@ -22,6 +22,7 @@
 //   pad_a, pad_b        depth-0 binary32 only: zero-padded copies.
 #include "plan.hpp"
 
+#include <algorithm>
 #include <stdexcept>
 
 #include "../../include/stark.h"
@@ -90,14 +91,17 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p, int tile) {
     p.np = padded_size(n, depth);
     p.leaf = p.np >> depth;
     p.padded = (p.np != n);
-    // Leaf GEMM tile class: the largest whose tile count still fills the
-    // chip (256 CUs).
+    // Leaf GEMM tile class: the largest whose tiles still fill most of the
+    // chip -- 256-wide tiles run one block per CU (256 CUs), 128-wide two;
+    // measured, 256-wide tiles beat 128-wide ones down to about 3/4 of a
+    // wave of tiles and 128-wide tiles beat 64-wide ones above about 3/4 of
+    // their two waves.
     {
         const int64_t leaves = pow7(depth);
         const int64_t t256 = leaves * (p.leaf / 256) * (p.leaf / 256);
         const int64_t t128 = leaves * (p.leaf / 128) * (p.leaf / 128);
-        if (p.leaf % 256 == 0 && t256 >= 256) p.tile = 256;
-        else if (p.leaf % 128 == 0 && (t128 >= 128 || p.leaf % 64 != 0)) p.tile = 128;
+        if (p.leaf % 256 == 0 && t256 >= 192) p.tile = 256;
+        else if (p.leaf % 128 == 0 && t128 >= 384) p.tile = 128;
         else p.tile = 64;
     }
     if (tile != 0) {
@@ -234,6 +238,38 @@ Work plan_work(const Plan& p) {
     }
     if (p.pad_a >= 0) w.pad_bytes = 2.0 * ((double)p.n * p.n * E + (double)p.np * p.np * E);
     return w;
+}
+
+double model_seconds(const Plan& p) {
+    const Work w = plan_work(p);
+    const bool split = p.planes > 0;
+    const double rate = split ? (p.tile == 256 ? 1.40e15 : p.tile == 128 ? 0.80e15 : 0.70e15)
+                              : (p.tile == 256 ? 117e12 : p.tile == 128 ? 103e12 : 80e12);
+    const double rows = (split && p.planes == 3 && p.tile == 256) ? 2.0 : 1.0;  // 256 x 128 tiles
+    const double tiles = (double)pow7(p.depth) * rows * (double)(p.leaf / p.tile) * (double)(p.leaf / p.tile);
+    const double fill = std::min(1.0, tiles / 256.0);   // share of the 256 CUs with a tile
+    const double klen = (double)p.leaf / ((double)p.leaf + 128.0);   // per-tile start and store cost
+    int launches = 1 + (p.pad_a >= 0 ? 1 : 0) + (split ? 1 : 0) + (p.scale >= 0 ? 2 : 0);
+    for (int l = 0; l < p.fp32_levels; ++l) launches += p.div_slots[l] > 0 ? 1 : 0;
+    launches += p.depth >= 2 ? p.depth - 1 : p.depth;
+    const double bytes = w.divide_bytes + w.split_bytes + w.combine_bytes + w.pad_bytes;
+    return w.mfma_flops / (rate * fill * klen) + bytes / 4e12 + launches * 6e-6;
+}
+
+int model_depth(int64_t n, int precision) {
+    // BF16X3 loses about a factor 2 of accuracy per level (16-bit split):
+    // at most one level keeps it near 1e-5
+    int dmax = std::min(max_depth_for(n), 3);
+    if ((precision & STARK_PRECISION_MASK) == STARK_BF16X3) dmax = std::min(dmax, 1);
+    int best = 0;
+    double best_s = 0.0;
+    for (int d = 0; d <= dmax; ++d) {
+        Plan p;
+        if (!make_plan(n, d, precision, p).empty()) continue;
+        const double s = model_seconds(p);
+        if (d == 0 || s < best_s) { best = d; best_s = s; }
+    }
+    return best;
 }
 
 }  // namespace stk

@@ -57,4 +57,14 @@ struct Work {
 };
 Work plan_work(const Plan& p);
 
+// Rough time of a plan on one MI355X (seconds): matrix-core work at the
+// measured rate of its tile class, scaled down when its tiles leave CUs
+// idle and for short K (leaf / (leaf + 128)), streaming bytes at 4 TB/s,
+// and 6 us per launch.  Only used to
+// choose a depth where nothing has been measured.
+double model_seconds(const Plan& p);
+
+// Depth (0..3) of least model_seconds for (n, precision); BF16X3 at most 1.
+int model_depth(int64_t n, int precision);
+
 }  // namespace stk

@@ -72,14 +72,7 @@ size_t Arena::largest_free() const {
     return m;
 }
 
-int default_serving_depth(int64_t n, int precision) {
-    // binary32 leaves: one level per doubling above 2048; bf16 split leaves
-    // keep their error budget at one level at most
-    int d;
-    if ((precision & STARK_PRECISION_MASK) == STARK_FP32) d = n >= 8192 ? 2 : n >= 4096 ? 1 : 0;
-    else d = n >= 4096 ? 1 : 0;
-    return std::min(d, max_depth_for(n));
-}
+int default_serving_depth(int64_t n, int precision) { return model_depth(n, precision); }
 
 size_t request_footprint(const Plan& p, bool gen, bool own_c) {
     const size_t nn = (size_t)p.n * (size_t)p.n * 4;

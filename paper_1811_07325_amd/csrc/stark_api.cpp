@@ -212,6 +212,11 @@ const char* stark_last_error(void) { return get_error(); }
 
 int stark_max_depth(int64_t n) { return n > 0 ? max_depth_for(n) : 0; }
 
+int stark_model_depth(int64_t n, stark_precision prec) {
+    if (n <= 0 || n > ((int64_t)1 << 20) || planes_for((int)prec) < 0) return -1;
+    return model_depth(n, (int)prec);
+}
+
 stark_status stark_workspace_size(int64_t n, int depth, stark_precision prec, size_t* bytes) {
     if (!bytes) { set_error("bytes is NULL"); return STARK_EINVAL; }
     Plan p;

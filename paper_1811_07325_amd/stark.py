@@ -102,6 +102,7 @@ def _load() -> ctypes.CDLL:
         "stark_destroy": ([P], I),
         "stark_workspace_size": ([I64, I, I, ctypes.POINTER(ctypes.c_size_t)], I),
         "stark_max_depth": ([I64], I),
+        "stark_model_depth": ([I64, I], I),
         "stark_gemm": ([P, P, P, P, I64, I, I, P], I),
         "stark_gemm_batched": ([P, I, P, P, P, P, I, I, P], I),
         "stark_submit": ([P, ctypes.POINTER(stark_request), ctypes.POINTER(ctypes.c_uint64)], I),
@@ -185,6 +186,11 @@ def stark_workspace_size(n: int, depth: int, precision: int) -> int:
 
 def stark_max_depth(n: int) -> int:
     return _lib.stark_max_depth(n)
+
+
+def stark_model_depth(n: int, precision: int) -> int:
+    """Depth used for STARK_DEPTH_AUTO requests without an autotuner record."""
+    return _lib.stark_model_depth(n, precision)
 
 
 def stark_gemm(ctx, A, B, C, n: int, depth: int, precision: int, stream=None) -> None:

@@ -175,6 +175,34 @@ def test_tile_class_choice(S):
     assert S.stark_plan_info(512, 2, 1).gemm_tile == 64    # 49 leaves of 128: more, smaller tiles
     assert S.stark_plan_info(2048, 1, 0).gemm_tile == 128
     assert S.stark_plan_info(384, 1, 1).gemm_tile == 64
+    # 256-wide tiles down to about 3/4 of a wave (196 and 252 tiles), 64-wide
+    # below about 3/4 of two waves of 128-wide tiles (256 tiles)
+    assert S.stark_plan_info(2048, 2, 0).gemm_tile == 256   # 49 leaves of 512: 196 tiles
+    assert S.stark_plan_info(3000, 1, 1).gemm_tile == 256   # 7 leaves of 1536: 252 tiles
+    assert S.stark_plan_info(2048, 0, 1).gemm_tile == 64    # 256 tiles of 128
+    for n in (256, 1000, 2048, 3000, 4096, 8192, 16384):
+        for d in range(S.stark_max_depth(n) + 1):
+            pl = S.stark_plan_info(n, d, 1)
+            assert pl.leaf % pl.gemm_tile == 0
+
+
+def test_model_depth(S):
+    """The depth used for served requests without an autotuner record."""
+    for n in (64, 128, 700, 1000, 2048, 2500, 3000, 4096, 6000, 8192, 16384, 20000):
+        for p in (0, 1, 2, 3, 16, 17):
+            d = S.stark_model_depth(n, p)
+            assert 0 <= d <= min(3, S.stark_max_depth(n))
+            if p & 15 == 1:
+                assert d <= 1           # BF16X3's error roughly doubles per level
+    for n in (128, 512, 1000, 1024):
+        assert S.stark_model_depth(n, 0) == 0 and S.stark_model_depth(n, 1) == 0   # launches dominate
+    # measured best depths (one MI355X): binary32 0 at 4096, 2 at 8192, 3 at 16384;
+    # BF16X3 1 at 3000 (7 leaves of 1536 on 256-wide tiles beat one 3008 leaf on 64-wide ones)
+    assert S.stark_model_depth(4096, 0) == 0
+    assert S.stark_model_depth(8192, 0) == 2
+    assert S.stark_model_depth(16384, 0) == 3
+    assert S.stark_model_depth(3000, 1) == 1
+    assert S.stark_model_depth(0, 0) == -1 and S.stark_model_depth(100, 99) == -1
 
 
 def test_plan_work_figures(S):
