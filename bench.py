@@ -130,8 +130,9 @@ def run_batched(S, torch, st, count: int = 64, seed: int = 7) -> dict:
     """`count` independent products, sizes drawn from {256, 384, 1000, 1024,
     2048, 3000, 4096} (odd sizes padded), binary32 uniform[-1, 1] operands, in
     one stark_gemm_batched call (every leaf of every problem in one grouped
-    launch, graph-captured), at depths 0..2 (clamped per problem); Freivalds'
-    check on every product of the fastest depth."""
+    launch, graph-captured), at depths 0..2 (clamped per problem) and with
+    STARK_DEPTH_AUTO (each problem at the model's depth for its size);
+    Freivalds' check on every product of the fastest setting."""
     from paper_1811_07325_amd import inputs
     rng = np.random.default_rng(seed)
     sizes = [int(x) for x in rng.choice([256, 384, 1000, 1024, 2048, 3000, 4096], count)]
@@ -141,7 +142,7 @@ def run_batched(S, torch, st, count: int = 64, seed: int = 7) -> dict:
     flops = sum(2.0 * m ** 3 for m in sizes)
     ctx = S.stark_create(0)
     per_depth = []
-    for depth in (0, 1, 2):
+    for depth in (0, 1, 2, S.STARK_DEPTH_AUTO):
         for _ in range(2):                     # eager, then captured
             S.stark_gemm_batched(ctx, As, Bs, Cs, sizes, depth, S.STARK_FP32, st)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -151,10 +152,12 @@ def run_batched(S, torch, st, count: int = 64, seed: int = 7) -> dict:
         e1.record(st)
         e1.synchronize()
         ms = e0.elapsed_time(e1) / 5
-        per_depth.append({"depth": depth, "ms": ms, "tflops": flops / (ms * 1e-3) * 1e-12})
-        log(f"batched {count} fp32 depth {depth}: {ms:.3f} ms, {flops / (ms * 1e-3) * 1e-12:.1f} TF/s")
+        label = "auto" if depth == S.STARK_DEPTH_AUTO else depth
+        per_depth.append({"depth": label, "ms": ms, "tflops": flops / (ms * 1e-3) * 1e-12})
+        log(f"batched {count} fp32 depth {label}: {ms:.3f} ms, {flops / (ms * 1e-3) * 1e-12:.1f} TF/s")
     best = min(per_depth, key=lambda r: r["ms"])
-    S.stark_gemm_batched(ctx, As, Bs, Cs, sizes, best["depth"], S.STARK_FP32, st)
+    S.stark_gemm_batched(ctx, As, Bs, Cs, sizes, S.STARK_DEPTH_AUTO if best["depth"] == "auto" else best["depth"],
+                         S.STARK_FP32, st)
     st.synchronize()
     worst = 0.0
     for i, m in enumerate(sizes):

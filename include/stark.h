@@ -175,10 +175,13 @@ stark_status stark_tune(stark_ctx* ctx, const float* A, const float* B, float* C
                         stark_tune_point* points, int cap, int* count, void* stream);
 
 /* `count` independent products C[i] = A[i] * B[i] of sizes n[i] (host arrays
- * of device pointers / sizes), all at the same depth (clamped per problem to
- * stark_max_depth) and precision.  Every recursion level of every problem is
- * one launch, and all leaf products of all problems form one grouped launch;
- * the sequence is captured once into a hipGraph and replayed.
+ * of device pointers / sizes), all in one precision, at `depth` (clamped per
+ * problem to stark_max_depth) or, with depth = STARK_DEPTH_AUTO, each problem
+ * at its autotuner record (depth and tile class) if the context has one for
+ * (n[i], p), else at stark_model_depth(n[i], p) -- the autotuner itself is
+ * not run.  Every recursion level of every problem is one launch, and all
+ * leaf products of all problems form one grouped launch per tile class; the
+ * sequence is captured once into a hipGraph and replayed.
  * Errors as stark_gemm. */
 stark_status stark_gemm_batched(stark_ctx* ctx, int count, const float* const* A,
                                 const float* const* B, float* const* C, const int64_t* n,

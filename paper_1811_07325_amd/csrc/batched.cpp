@@ -47,12 +47,13 @@ struct BatchEntry {
 struct BatchKey {
     std::vector<const void*> ptrs;
     std::vector<int64_t> sizes;
-    int depth, precision;
+    std::vector<int> plans;   // depth and tile class of every problem
+    int precision;
     const void* ws;
     hipStream_t stream;
     bool operator<(const BatchKey& o) const {
-        return std::tie(ptrs, sizes, depth, precision, ws, stream) <
-               std::tie(o.ptrs, o.sizes, o.depth, o.precision, o.ws, o.stream);
+        return std::tie(ptrs, sizes, plans, precision, ws, stream) <
+               std::tie(o.ptrs, o.sizes, o.plans, o.precision, o.ws, o.stream);
     }
 };
 
@@ -117,8 +118,15 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
     std::vector<size_t> off(count);
     size_t total = 0;
     for (int i = 0; i < count; ++i) {
-        const int d = std::min(depth, max_depth_for(n[i]));
-        const std::string why = make_plan(n[i], d, precision, plans[i]);
+        int d, tile = 0;
+        if (depth == STARK_DEPTH_AUTO) {   // the problem's autotuner record, else the model's depth
+            auto it = ctx->tune.find({n[i], precision});
+            if (it != ctx->tune.end()) { d = it->second.depth; tile = it->second.tile; }
+            else d = model_depth(n[i], precision);
+        } else {
+            d = std::min(depth, max_depth_for(n[i]));
+        }
+        const std::string why = make_plan(n[i], d, precision, plans[i], tile);
         if (!why.empty()) { set_error("problem %d: %s", i, why.c_str()); return STARK_EINVAL; }
         off[i] = total;
         total += (plans[i].bytes + 255) / 256 * 256;
@@ -127,7 +135,10 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
     if (rc != STARK_OK) return rc;
 
     BatchKey key;
-    key.depth = depth;
+    for (const Plan& p : plans) {
+        key.plans.push_back(p.depth);
+        key.plans.push_back(p.tile);
+    }
     key.precision = precision;
     key.ws = ctx->ws;
     key.stream = st ? st : ctx->side_stream;

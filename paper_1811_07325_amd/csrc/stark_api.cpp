@@ -408,7 +408,7 @@ stark_status stark_gemm_batched(stark_ctx* ctx, int count, const float* const* A
         if (rc != STARK_OK) return rc;
     }
     if (planes_for((int)prec) < 0) { set_error("unknown precision %d", (int)prec); return STARK_EUNSUPPORTED; }
-    if (depth < 0) { set_error("batched calls need an explicit depth >= 0"); return STARK_EINVAL; }
+    if (depth < 0 && depth != STARK_DEPTH_AUTO) { set_error("depth must be >= 0 or STARK_DEPTH_AUTO"); return STARK_EINVAL; }
     std::lock_guard<std::mutex> lk(ctx->mu);
     STK_HIP(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
