@@ -448,7 +448,12 @@ def main() -> int:
                    "n": n, "depth": depth, "gemm_tile": tile, "precision": args.precision, "leaf": L,
                    "n_pad": plan.n_pad},
         "error": {"rel_frob_sampled_rows": rel_rows, "max_abs_sampled_rows": max_abs, "freivalds": freiv,
-                  "rows": int(rows.size), "target": 1e-5, "meets_target": rel_rows <= 1e-5},
+                  "rows": int(rows.size), "target": 1e-5, "meets_target": rel_rows <= 1e-5,
+                  # measured paths of this run within the target (Freivalds estimate), fastest first
+                  "target_met_by": sorted(({"path": k, "tflops": v["tflops"], "freivalds": v["freivalds"]}
+                                           for k, v in compare.items()
+                                           if v.get("freivalds") is not None and v["freivalds"] <= 1e-5),
+                                          key=lambda r: -r["tflops"])},
         "tune": [{"depth": a, "ms": b, "err": c, "tile": t} for a, b, c, t in tune_pts],
         "phases": phases, "roofline": roofline, "cpu_baseline": cpu, "compare": compare, "batched": batched,
         "serving": serving,
