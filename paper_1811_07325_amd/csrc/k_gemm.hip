@@ -217,6 +217,9 @@ __device__ __forceinline__ void gemm16_lds(Src src, int64_t total_tiles) {
             else wait_vmcnt<0>();
             __syncthreads();     // every wave's part of step kt landed; step kt-1's reads are done
             if (kt + STAGES - 1 < KT) issue((int)((kt + STAGES - 1) % STAGES), (kt + STAGES - 1) * BK);
+            // three planes: the compiler's DS / MFMA interleaving strategy 1
+            // (measured 4 % faster there, 3 % slower with two planes)
+            if constexpr (P == 3) __builtin_amdgcn_iglp_opt(1);
             const uint4* sl = lds[kt % STAGES];
             VT b[P][TN];
 #pragma unroll
