@@ -456,6 +456,12 @@ def main() -> int:
                                           key=lambda r: -r["tflops"])},
         "tune": [{"depth": a, "ms": b, "err": c, "tile": t} for a, b, c, t in tune_pts],
         "phases": phases, "roofline": roofline, "cpu_baseline": cpu, "compare": compare, "batched": batched,
+        # the paper's own figure for this size (distributed Spark, FP64; another machine): context only
+        "paper_context": {"n": 16384, "stark_wall_clock_s": 161.0, "effective_tflops": 2.0 * 16384 ** 3 / 161.0 * 1e-12,
+                          "source": "Fig. 6 and Table V (fastest partition, b = 16)",
+                          "hardware": "3 nodes, each 2 x 6-core Xeon 2.60 GHz, 132 GB, 14 Gb/s InfiniBand; "
+                                      "Spark 1.6.0 with 5 executors x 5 cores; FP64 leaf products through BLAS",
+                          "serial_strassen_one_node_s": 2453.0},
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
