@@ -262,7 +262,7 @@ bool Engine::admit(Req* q, int si) {
     if (e != hipSuccess || rc != STARK_OK) {
         q->status = rc != STARK_OK ? rc : STARK_EDEVICE;
         // make sure nothing of this request is still running before its memory is reused
-        hipStreamSynchronize(s.stream);
+        (void)hipStreamSynchronize(s.stream);
         (void)hipGetLastError();
         q->t_done = now_us();
         ++failed_;
