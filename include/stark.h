@@ -235,6 +235,12 @@ typedef struct {
 
 stark_status stark_stats(stark_ctx* ctx, stark_stats_t* out);
 
+/* Start a new statistics window: counts, latencies, throughput span and
+ * maxima restart from the requests completed after this call (requests in
+ * flight are counted when they finish).  Thread-safe; no effect before the
+ * first stark_submit. */
+stark_status stark_stats_reset(stark_ctx* ctx);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* stark_last_error(void);
 

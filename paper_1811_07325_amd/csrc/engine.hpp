@@ -42,6 +42,36 @@ private:
     size_t size_ = 0, used_ = 0;
 };
 
+// Device memory of the served requests: segments allocated when admissions
+// need them (at least kSegmentBytes each, at most the budget in total), each
+// carved first-fit by an Arena.  A budget is not allocated up front: on a
+// device whose memory was freed before, allocating tens of GiB takes seconds.
+class SegmentedArena {
+public:
+    static constexpr size_t kSegmentBytes = size_t(4) << 30;
+    enum Result { kOk, kWait, kFail };
+    explicit SegmentedArena(size_t budget = 0) : budget_(budget) {}
+    // `idle`: nothing is in flight, so every segment is empty and may be
+    // replaced by one large enough.  kWait: no room until requests finish;
+    // kFail: the device refused the memory while idle.
+    Result alloc(size_t bytes, bool idle, int* seg, size_t* off);
+    void free(int seg, size_t off, size_t bytes) { segs_[seg].arena.free(off, bytes); used_ -= round(bytes); }
+    char* base(int seg) const { return static_cast<char*>(segs_[seg].base); }
+    size_t used() const { return used_; }
+    size_t budget() const { return budget_; }
+    size_t allocated() const { return allocated_; }
+    void release();
+
+private:
+    static size_t round(size_t b) { return (b + 255) / 256 * 256; }
+    struct Seg {
+        void* base;
+        Arena arena;
+    };
+    std::vector<Seg> segs_;
+    size_t budget_, allocated_ = 0, used_ = 0;
+};
+
 // Depth used for a request when it asks for STARK_DEPTH_AUTO and the
 // autotuner has no record for its size.
 int default_serving_depth(int64_t n, int precision);
@@ -61,6 +91,7 @@ public:
     stark_status submit(const stark_request& r, uint64_t* ticket);
     stark_status poll(uint64_t ticket, stark_result* out);
     stark_status stats(stark_stats_t* out);
+    void reset_stats();
 
 private:
     struct Req {
@@ -68,6 +99,7 @@ private:
         stark_request r{};
         Plan plan;
         size_t bytes = 0, off = 0;
+        int seg = -1;                 // arena segment
         bool gen = false, own_c = false;
         int slot = -1;
         double t_submit = 0, t_admit = 0, t_done = 0;
@@ -88,9 +120,8 @@ private:
     void finish(int slot);
 
     stark_ctx* ctx_;
-    void* base_ = nullptr;        // device arena
     double* host_sums_ = nullptr; // pinned, one per slot
-    Arena arena_;
+    SegmentedArena mem_;          // device memory of the requests in flight
     std::vector<Slot> slots_;
     std::mutex mu_;
     std::condition_variable cv_;

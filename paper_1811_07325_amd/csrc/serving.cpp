@@ -72,6 +72,39 @@ size_t Arena::largest_free() const {
     return m;
 }
 
+SegmentedArena::Result SegmentedArena::alloc(size_t bytes, bool idle, int* seg, size_t* off) {
+    for (size_t i = 0; i < segs_.size(); ++i)
+        if (segs_[i].arena.alloc(bytes, off)) {
+            *seg = (int)i;
+            used_ += round(bytes);
+            return kOk;
+        }
+    const size_t need = round(bytes);
+    if (need > budget_ - allocated_) {
+        if (!idle || segs_.empty()) return idle ? kFail : kWait;
+        release();   // all empty: make room for one segment that holds the request
+    }
+    const size_t size = std::min(std::max(need, kSegmentBytes), budget_ - allocated_);
+    void* p = nullptr;
+    if (hipMalloc(&p, size) != hipSuccess) {
+        (void)hipGetLastError();
+        return idle ? kFail : kWait;
+    }
+    segs_.push_back(Seg{p, Arena(size)});
+    allocated_ += size;
+    if (!segs_.back().arena.alloc(bytes, off)) return kFail;   // cannot happen: size >= need
+    *seg = (int)segs_.size() - 1;
+    used_ += need;
+    return kOk;
+}
+
+void SegmentedArena::release() {
+    for (auto& s : segs_) (void)hipFree(s.base);
+    segs_.clear();
+    allocated_ = 0;
+    used_ = 0;
+}
+
 int default_serving_depth(int64_t n, int precision) { return model_depth(n, precision); }
 
 size_t request_footprint(const Plan& p, bool gen, bool own_c) {
@@ -85,12 +118,10 @@ size_t request_footprint(const Plan& p, bool gen, bool own_c) {
 // ----------------------------------------------------------------------------
 // Engine
 // ----------------------------------------------------------------------------
-Engine::Engine(stark_ctx* ctx, size_t budget, int slots, hipError_t* err) : ctx_(ctx) {
+Engine::Engine(stark_ctx* ctx, size_t budget, int slots, hipError_t* err) : ctx_(ctx), mem_(budget) {
     *err = hipSetDevice(ctx->device);
-    if (*err == hipSuccess) *err = hipMalloc(&base_, budget);
     if (*err == hipSuccess) *err = hipHostMalloc(reinterpret_cast<void**>(&host_sums_), sizeof(double) * slots);
     if (*err != hipSuccess) return;
-    arena_.reset(budget);
     slots_.resize(slots);
     for (auto& s : slots_) {
         if ((*err = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess) return;
@@ -118,7 +149,7 @@ Engine::~Engine() {
         if (s.partials) (void)hipFree(s.partials);
     }
     for (auto& kv : live_) delete kv.second;   // every request is in live_ until polled
-    if (base_) (void)hipFree(base_);
+    mem_.release();
     if (host_sums_) (void)hipHostFree(host_sums_);
 }
 
@@ -158,8 +189,8 @@ stark_status Engine::submit(const stark_request& r, uint64_t* ticket) {
     const std::string why = make_plan(r.n, depth, (int)r.precision, q->plan, tile);
     if (!why.empty()) { set_error("%s", why.c_str()); return STARK_EINVAL; }
     q->bytes = request_footprint(q->plan, q->gen, q->own_c);
-    if (q->bytes > arena_.size()) {
-        set_error("request needs %zu bytes, budget is %zu", q->bytes, arena_.size());
+    if (q->bytes > mem_.budget()) {
+        set_error("request needs %zu bytes, budget is %zu", q->bytes, mem_.budget());
         return STARK_ENOMEM;
     }
     std::lock_guard<std::mutex> lk(mu_);
@@ -215,10 +246,31 @@ stark_status Engine::stats(stark_stats_t* out) {
     return STARK_OK;
 }
 
+void Engine::reset_stats() {
+    std::lock_guard<std::mutex> lk(mu_);
+    lat_ms_.clear();
+    lat_next_ = 0;
+    completed_ = failed_ = 0;
+    flops_ = 0;
+    first_admit_ = -1;
+    last_done_ = 0;
+    max_bytes_ = mem_.used();
+    max_inflight_ = inflight_;
+}
+
 bool Engine::admit(Req* q, int si) {
     size_t off;
-    if (!arena_.alloc(q->bytes, &off)) return false;
+    int seg;
+    const SegmentedArena::Result got = mem_.alloc(q->bytes, inflight_ == 0, &seg, &off);
+    if (got == SegmentedArena::kWait) return false;
+    if (got == SegmentedArena::kFail) {   // nothing in flight and the device refused the memory
+        q->status = STARK_ENOMEM;
+        q->t_done = now_us();
+        ++failed_;
+        return true;
+    }
     Slot& s = slots_[si];
+    q->seg = seg;
     q->off = off;
     q->slot = si;
     q->t_admit = now_us();
@@ -227,11 +279,11 @@ bool Engine::admit(Req* q, int si) {
     s.req = q;
     ++inflight_;
     max_inflight_ = std::max(max_inflight_, inflight_);
-    max_bytes_ = std::max(max_bytes_, arena_.used());
+    max_bytes_ = std::max(max_bytes_, mem_.used());
 
     const size_t nn = (size_t)q->r.n * (size_t)q->r.n * 4;
     const size_t nn_al = (nn + 255) / 256 * 256;
-    char* base = static_cast<char*>(base_) + off;
+    char* base = mem_.base(seg) + off;
     char* ws = base;
     char* cur = base + (q->plan.bytes + 255) / 256 * 256;
     const float* A = q->r.A;
@@ -266,7 +318,7 @@ bool Engine::admit(Req* q, int si) {
         (void)hipGetLastError();
         q->t_done = now_us();
         ++failed_;
-        arena_.free(q->off, q->bytes);
+        mem_.free(q->seg, q->off, q->bytes);
         s.busy = false;
         s.req = nullptr;
         --inflight_;
@@ -290,7 +342,7 @@ void Engine::finish(int si) {
     lat_next_ = (lat_next_ + 1) % kLatWindow;
     flops_ += 2.0 * (double)q->r.n * (double)q->r.n * (double)q->r.n;
     last_done_ = q->t_done;
-    arena_.free(q->off, q->bytes);
+    mem_.free(q->seg, q->off, q->bytes);
     s.busy = false;
     s.req = nullptr;
     --inflight_;
@@ -317,7 +369,7 @@ void Engine::loop() {
                 q->status = STARK_EDEVICE;
                 q->t_done = now_us();
                 ++failed_;
-                arena_.free(q->off, q->bytes);
+                mem_.free(q->seg, q->off, q->bytes);
                 slots_[si].busy = false;
                 slots_[si].req = nullptr;
                 --inflight_;
@@ -397,6 +449,13 @@ stark_status stark_poll(stark_ctx* ctx, uint64_t ticket, stark_result* out) {
     Engine* e = engine_of(ctx);
     if (!e) { set_error("unknown ticket %llu", (unsigned long long)ticket); return STARK_ENOTFOUND; }
     return e->poll(ticket, out);
+}
+
+stark_status stark_stats_reset(stark_ctx* ctx) {
+    if (!ctx) { set_error("ctx is NULL"); return STARK_EINVAL; }
+    Engine* e = engine_of(ctx);
+    if (e) e->reset_stats();
+    return STARK_OK;
 }
 
 stark_status stark_stats(stark_ctx* ctx, stark_stats_t* out) {

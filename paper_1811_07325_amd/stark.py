@@ -108,6 +108,7 @@ def _load() -> ctypes.CDLL:
         "stark_submit": ([P, ctypes.POINTER(stark_request), ctypes.POINTER(ctypes.c_uint64)], I),
         "stark_poll": ([P, ctypes.c_uint64, ctypes.POINTER(stark_result)], I),
         "stark_stats": ([P, ctypes.POINTER(stark_stats_t)], I),
+        "stark_stats_reset": ([P], I),
         "stark_last_error": ([], ctypes.c_char_p),
         "stark_matvec_f64": ([P, P, P, I64, P], I),
         "stark_row_errors": ([P, I64, P, I64, P, P, P], I),
@@ -240,6 +241,10 @@ def stark_poll_status(ctx, ticket: int):
     out = stark_result()
     rc = _lib.stark_poll(ctx, ticket, ctypes.byref(out))
     return rc, out
+
+
+def stark_stats_reset(ctx) -> None:
+    _check("stark_stats_reset", _lib.stark_stats_reset(ctx))
 
 
 def stark_stats(ctx) -> stark_stats_t:

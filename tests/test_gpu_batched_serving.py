@@ -233,6 +233,25 @@ def test_serving_generated_operands_and_checksums(S):
         S.stark_destroy(c)
 
 
+def test_serving_stats_reset(S):
+    """stark_stats_reset starts a new window: only requests finished after it
+    count, and the latency percentiles come from them alone."""
+    c = S.stark_create(0, hbm_budget_bytes=4 << 30, max_slots=2)
+    try:
+        S.stark_stats_reset(c)                    # no engine yet: accepted, no effect
+        wait(S, c, [S.stark_submit(c, 1024, 0, 0, seed=s, tag=s) for s in range(6)])
+        st = S.stark_stats(c)
+        assert st.completed == 6 and st.p50_ms > 0
+        S.stark_stats_reset(c)
+        st = S.stark_stats(c)
+        assert st.completed == 0 and st.failed == 0 and st.p50_ms == 0 and st.throughput_tflops == 0
+        wait(S, c, [S.stark_submit(c, 256, 1, 0, seed=s, tag=s) for s in range(3)])
+        st = S.stark_stats(c)
+        assert st.completed == 3 and st.p99_ms > 0 and st.throughput_tflops > 0
+    finally:
+        S.stark_destroy(c)
+
+
 def test_serving_concurrent_submitters(S):
     """Four host threads submit and poll at once: every request completes and
     its checksum equals the one it gets alone."""
@@ -279,6 +298,34 @@ def test_serving_admission_respects_budget(S):
         assert e.value.status == S.STARK_ENOMEM
         rc, _ = S.stark_poll_status(c, 123456789)
         assert rc == S.STARK_ENOTFOUND
+    finally:
+        S.stark_destroy(c)
+
+
+def test_serving_arena_grows_and_is_replaced_when_idle(S):
+    """The engine takes device memory in segments as admissions need it (4 GiB
+    each, within the budget).  A request larger than a segment gets one of its
+    own; when the budget is taken by segments too small for it, it waits until
+    nothing is in flight and the empty segments are replaced."""
+    budget = 6 << 30
+    c = S.stark_create(0, hbm_budget_bytes=budget, max_slots=4)
+    try:
+        small = [S.stark_submit(c, 1024, 0, 0, seed=i, tag=i) for i in range(4)]
+        big = S.stark_submit(c, 19200, 0, 0, seed=99, tag=99)      # 3 x 1.47 GB > 4 GiB
+        more = [S.stark_submit(c, 512, 1, 0, seed=10 + i, tag=10 + i) for i in range(4)]
+        res = wait(S, c, small + [big] + more)
+        assert all(r.status == S.STARK_OK for r in res.values())
+        st = S.stark_stats(c)
+        assert st.completed == 9 and st.failed == 0
+        assert st.max_inflight_bytes <= budget
+        big_sum = res[big].checksum
+    finally:
+        S.stark_destroy(c)
+    # the same request alone in an engine with room to spare: the same result
+    c = S.stark_create(0, hbm_budget_bytes=16 << 30, max_slots=1)
+    try:
+        t = S.stark_submit(c, 19200, 0, 0, seed=99, tag=99)
+        assert wait(S, c, [t])[t].checksum == big_sum
     finally:
         S.stark_destroy(c)
 
