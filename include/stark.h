@@ -94,7 +94,9 @@ typedef struct {
                                  allocates (and grows) its own                    */
     size_t workspace_bytes;   /* size of `workspace`                              */
     size_t hbm_budget_bytes;  /* serving: device bytes the engine may hold
-                                 (0 = 3/4 of free memory at create time)          */
+                                 (0 = 3/4 of free memory at create time), taken
+                                 in segments of at least 4 GiB as admissions
+                                 need them                                        */
     int max_slots;            /* serving: concurrent requests (0 = 4)             */
     const char* tuner_cache;  /* autotuner cache file (NULL = none)               */
 } stark_config;
