@@ -80,22 +80,26 @@ SegmentedArena::Result SegmentedArena::alloc(size_t bytes, bool idle, int* seg, 
             return kOk;
         }
     const size_t need = round(bytes);
-    if (need > budget_ - allocated_) {
-        if (!idle || segs_.empty()) return idle ? kFail : kWait;
-        release();   // all empty: make room for one segment that holds the request
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (need <= budget_ - allocated_) {
+            const size_t size = std::min(std::max(need, kSegmentBytes), budget_ - allocated_);
+            void* p = nullptr;
+            if (hipMalloc(&p, size) == hipSuccess) {
+                segs_.push_back(Seg{p, Arena(size)});
+                allocated_ += size;
+                if (!segs_.back().arena.alloc(bytes, off)) return kFail;   // cannot happen: size >= need
+                *seg = (int)segs_.size() - 1;
+                used_ += need;
+                return kOk;
+            }
+            (void)hipGetLastError();
+        }
+        // no room in the budget, or the device refused: when idle every
+        // segment is empty, so give them back and try once more
+        if (!idle || segs_.empty()) break;
+        release();
     }
-    const size_t size = std::min(std::max(need, kSegmentBytes), budget_ - allocated_);
-    void* p = nullptr;
-    if (hipMalloc(&p, size) != hipSuccess) {
-        (void)hipGetLastError();
-        return idle ? kFail : kWait;
-    }
-    segs_.push_back(Seg{p, Arena(size)});
-    allocated_ += size;
-    if (!segs_.back().arena.alloc(bytes, off)) return kFail;   // cannot happen: size >= need
-    *seg = (int)segs_.size() - 1;
-    used_ += need;
-    return kOk;
+    return idle ? kFail : kWait;
 }
 
 void SegmentedArena::release() {
