@@ -8,7 +8,9 @@
 * n = 16384, normal(0, 1), split-precision leaves, depth chosen by the
   autotuner among 2..4, run as the benchmark runs it (one stream, eager call
   then graph replay): 256 sampled rows against the FP64 oracle and Freivalds'
-  check.
+  check;
+* n = 49152 and 49120 (n^2 > 2^31), integer inputs: exact on rows whose
+  element offsets cross 2^31.
 """
 import numpy as np
 import pytest
@@ -149,3 +151,30 @@ def test_n16384_split_precision_autotuned(S, ctx, precision):
     assert 0.25 * err <= freiv <= 4 * err
     # the tuner's own Freivalds figure agrees with this one
     assert 0.25 * freiv <= tuned[2] <= 4 * freiv
+
+
+# n^2 > 2^31: every element offset of A, B, C and the workspace needs 64 bits.
+# Integers in [-2, 2] keep every intermediate exact (|C| <= 4n < 2^24, leaf
+# operands at most 8, exact in bf16), so sampled rows must equal the exact
+# product bit for bit -- rows whose offsets cross 2^31 and the last row
+# included.  49120 is not a multiple of 64: padding and crop at those offsets.
+@pytest.mark.parametrize("n,prec,depth", [(49152, "fp32", 0), (49152, "fp32", 1), (49120, "bf16x3", 2)])
+def test_beyond_32bit_offsets_integer_exact(S, ctx, n, prec, depth):
+    print(f"case n={n} depth={depth} prec={prec} (n^2 = {n * n} > 2^31)", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(n + depth)
+    A = torch.randint(-2, 3, (n, n), generator=g, device="cuda", dtype=torch.float32)
+    B = torch.randint(-2, 3, (n, n), generator=g, device="cuda", dtype=torch.float32)
+    C = torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda")
+    S.stark_gemm(ctx, A, B, C, n, depth, S.PRECISIONS[prec], None)
+    torch.cuda.synchronize()
+    cross = (1 << 31) // n
+    rows = torch.tensor([0, 1, cross - 1, cross, cross + 1, n // 2, n - 2, n - 1], device="cuda")
+    Ar = A[rows].double()
+    ref = torch.empty((rows.numel(), n), dtype=torch.float64, device="cuda")
+    for c0 in range(0, n, 8192):                 # exact in binary64, column chunks of B
+        ref[:, c0:c0 + 8192] = Ar @ B[:, c0:c0 + 8192].double()
+    got = C[rows].double()
+    assert torch.equal(got, ref), (got - ref).abs().max().item()
+    del A, B, C, Ar, ref, got
+    torch.cuda.empty_cache()
