@@ -135,7 +135,8 @@ stark_status stark_gemm(stark_ctx* ctx, const float* A, const float* B, float* C
 
 /* Rectangular product C (m x n) = A (m x k) B (k x n): row-major binary32
  * with leading dimensions k, n and n, 16-byte aligned base pointers (rows
- * need not be aligned).  The paper treats n = 2^p and defers other shapes to
+ * need not be aligned).  depth = STARK_DEPTH_AUTO takes
+ * stark_model_depth(min(m, k, n), p).  The paper treats n = 2^p and defers other shapes to
  * partitioning (Section III-A): A and B are packed into zero-padded square
  * s x s blocks, s = stark_rect_block_edge(m, k, n, depth); every block
  * product A_ip B_pj runs at `depth` as one problem of a grouped launch (as

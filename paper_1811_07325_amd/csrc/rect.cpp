@@ -93,8 +93,9 @@ stark_status stark_gemm_rect(stark_ctx* ctx, const float* A, const float* B, flo
         set_error("A, B and C must be 16-byte aligned");
         return STARK_EINVAL;
     }
-    if (depth < 0 || depth > STARK_MAX_DEPTH) { set_error("depth %d out of range", depth); return STARK_EINVAL; }
     if (planes_for((int)prec) < 0) { set_error("unknown precision %d", (int)prec); return STARK_EUNSUPPORTED; }
+    if (depth == STARK_DEPTH_AUTO) depth = model_depth(std::min(m, std::min(k, n)), (int)prec);
+    if (depth < 0 || depth > STARK_MAX_DEPTH) { set_error("depth %d out of range", depth); return STARK_EINVAL; }
     const size_t cb = (size_t)m * (size_t)n * 4;
     if (overlap(C, cb, A, (size_t)m * (size_t)k * 4) || overlap(C, cb, B, (size_t)k * (size_t)n * 4)) {
         set_error("C overlaps A or B");

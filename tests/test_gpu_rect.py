@@ -38,6 +38,13 @@ def mat(r, c, seed, kind):
     return rng.uniform(-1, 1, size=(r, c)).astype(np.float32)
 
 
+def exact(A, B):
+    """The integer product of integer-valued A, B: binary64 BLAS is exact here
+    (entries at most 8 in magnitude, k <= 6000: every partial sum is an
+    integer below 2^53), and far faster than numpy's int64 product."""
+    return (A.astype(np.float64) @ B.astype(np.float64)).astype(np.int64)
+
+
 def run(S, ctx, A, B, depth, prec):
     m, k = A.shape
     n = B.shape[1]
@@ -60,8 +67,7 @@ def test_rect_integer_exact(S, ctx, m, k, n, depth, prec):
           flush=True)
     A, B = mat(m, k, 1, "int"), mat(k, n, 2, "int")
     C = run(S, ctx, A, B, depth, prec)
-    exact = A.astype(np.int64) @ B.astype(np.int64)
-    assert np.array_equal(C.astype(np.int64), exact)
+    assert np.array_equal(C.astype(np.int64), exact(A, B))
 
 
 @pytest.mark.parametrize("m,k,n,depth,prec", [(300, 1000, 500, 1, "fp32"), (300, 1000, 500, 1, "bf16x3"),
@@ -131,3 +137,17 @@ def test_rect_argument_errors(S, ctx):
     with pytest.raises(S.StarkError) as e:
         S.stark_gemm_rect(ctx, dA, dB, dC, 64, 96, 32, 0, 99, None)
     assert e.value.status == S.STARK_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("m,k,n,prec", [(3000, 4096, 3000, "fp32"), (2048, 6000, 4096, "bf16x3")])
+def test_rect_auto_depth(S, ctx, m, k, n, prec):
+    """STARK_DEPTH_AUTO takes the model's depth for min(m, k, n): the same
+    result as that depth given explicitly, bit for bit, and exact on
+    integers."""
+    d = S.stark_model_depth(min(m, k, n), PREC[prec])
+    print(f"case m={m} k={k} n={n} prec={prec} auto depth {d}", flush=True)
+    A, B = mat(m, k, 5, "int"), mat(k, n, 6, "int")
+    C = run(S, ctx, A, B, S.STARK_DEPTH_AUTO, prec)
+    assert np.array_equal(C.astype(np.int64), exact(A, B))
+    A, B = mat(m, k, 7, "float"), mat(k, n, 8, "float")
+    assert np.array_equal(run(S, ctx, A, B, S.STARK_DEPTH_AUTO, prec), run(S, ctx, A, B, d, prec))
