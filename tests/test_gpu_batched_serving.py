@@ -57,7 +57,7 @@ def test_batched_integer_exact_and_equal_to_single(S, ctx, prec):
     torch.cuda.synchronize()
     for i, n in enumerate(sizes):
         C = dC[i].cpu().numpy()
-        exact = As[i].astype(np.int64) @ Bs[i].astype(np.int64)
+        exact = (As[i].astype(np.float64) @ Bs[i].astype(np.float64)).astype(np.int64)   # exact: sums < 2^53
         assert np.array_equal(C.astype(np.int64), exact), (i, n)
         assert np.array_equal(C, single(S, ctx, dA[i], dB[i], n, depth, prec)), (i, n)
 

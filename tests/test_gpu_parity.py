@@ -99,7 +99,9 @@ def test_integer_inputs_bit_exact(S, ctx, n, depth, prec):
     r = 2 if (prec.endswith("_winograd") and depth >= 3) else 8
     A = inputs.integers(n, 0, -r, r)
     B = inputs.integers(n, 1, -r, r)
-    exact = A.astype(np.int64) @ B.astype(np.int64)
+    # binary64 BLAS is exact on these integers (every partial sum is an
+    # integer below 2^53) and far faster than numpy's int64 product
+    exact = (A.astype(np.float64) @ B.astype(np.float64)).astype(np.int64)
     C = run(S, ctx, A, B, depth, prec)
     assert np.all(np.isfinite(C))
     assert np.array_equal(C.astype(np.int64), exact)
