@@ -393,19 +393,21 @@ def main() -> int:
         Ar = A[:mr]
         Br = B.view(-1)[:kr * nr].view(kr, nr)
         Cr = C.view(-1)[:mr * nr].view(mr, nr)
+        rd = S.stark_model_depth(min(mr, kr, nr), prec)      # what STARK_DEPTH_AUTO takes
         for _ in range(2):
-            S.stark_gemm_rect(ctx, Ar, Br, Cr, mr, kr, nr, 2, prec, st)
+            S.stark_gemm_rect(ctx, Ar, Br, Cr, mr, kr, nr, S.STARK_DEPTH_AUTO, prec, st)
         tr = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         tr[0].record(st)
         for _ in range(3):
-            S.stark_gemm_rect(ctx, Ar, Br, Cr, mr, kr, nr, 2, prec, st)
+            S.stark_gemm_rect(ctx, Ar, Br, Cr, mr, kr, nr, S.STARK_DEPTH_AUTO, prec, st)
         tr[1].record(st)
         tr[1].synchronize()
         m_ = tr[0].elapsed_time(tr[1]) / 3
         compare["rect_" + args.precision] = {
-            "shape": [mr, kr, nr], "depth": 2, "block_edge": S.stark_rect_block_edge(mr, kr, nr, 2), "ms": m_,
+            "shape": [mr, kr, nr], "depth": rd, "block_edge": S.stark_rect_block_edge(mr, kr, nr, rd), "ms": m_,
             "tflops": 2.0 * mr * kr * nr / (m_ * 1e-3) * 1e-12}
-        log(f"  rect {mr}x{kr}x{nr} {args.precision} depth 2: {m_:.3f} ms, {compare['rect_' + args.precision]['tflops']:.1f} TF/s")
+        log(f"  rect {mr}x{kr}x{nr} {args.precision} depth {rd} (automatic): {m_:.3f} ms, "
+            f"{compare['rect_' + args.precision]['tflops']:.1f} TF/s")
         tt = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(st):
             for _ in range(2):

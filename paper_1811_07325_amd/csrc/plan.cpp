@@ -253,7 +253,10 @@ double model_seconds(const Plan& p) {
     for (int l = 0; l < p.fp32_levels; ++l) launches += p.div_slots[l] > 0 ? 1 : 0;
     launches += p.depth >= 2 ? p.depth - 1 : p.depth;
     const double bytes = w.divide_bytes + w.split_bytes + w.combine_bytes + w.pad_bytes;
-    return w.mfma_flops / (rate * fill * klen) + bytes / 4e12 + launches * 6e-6;
+    // streaming rates fitted to measured depth choices: the 16-bit paths' split and
+    // combine move their bytes faster than the binary32 divide
+    const double bw = split ? 5e12 : 4e12;
+    return w.mfma_flops / (rate * fill * klen) + bytes / bw + launches * 6e-6;
 }
 
 int model_depth(int64_t n, int precision) {

@@ -59,8 +59,8 @@ Work plan_work(const Plan& p);
 
 // Rough time of a plan on one MI355X (seconds): matrix-core work at the
 // measured rate of its tile class, scaled down when its tiles leave CUs
-// idle and for short K (leaf / (leaf + 128)), streaming bytes at 4 TB/s,
-// and 6 us per launch.  Only used to
+// idle and for short K (leaf / (leaf + 128)), streaming bytes at 5 TB/s
+// (16-bit paths) or 4 TB/s (binary32), and 6 us per launch.  Only used to
 // choose a depth where nothing has been measured.
 double model_seconds(const Plan& p);
 
