@@ -62,7 +62,7 @@ def parse():
                    help="only run the batched workload, print its JSON object and exit")
     p.add_argument("--serving-requests", type=int, default=2000)
     p.add_argument("--rows", type=int, default=256, help="sampled rows for the error check")
-    p.add_argument("--cpu-rows", type=int, default=768,
+    p.add_argument("--cpu-rows", type=int, default=1024,
                    help="extra sampled rows the oracle computes for the CPU baseline timing")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "leaf_gemm_traffic.txt"),
                    help="HBM traffic of the leaf GEMM measured by rocprofv3 counters, if present")
