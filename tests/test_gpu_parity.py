@@ -518,6 +518,39 @@ def test_tuner_record_selects_tile(S, tmp_path, prec):
     assert rel_f(floats[0], model) < 4 * 2.0 ** -24 * (n >> depth) ** 0.5 * 2 ** depth
 
 
+def test_concurrent_threads_one_context(S, ctx):
+    """Four host threads call stark_gemm on one context, each on its own
+    stream, at the same time (the binding releases the interpreter lock):
+    the context serialises the calls and orders their device work, so every
+    result equals its single-call result bit for bit."""
+    import threading
+    n, depth, p = 1024, 2, PREC["bf16x3"]
+    probs = [(inputs.uniform(n, 61 + 2 * i), inputs.uniform(n, 62 + 2 * i)) for i in range(4)]
+    refs = [run(S, ctx, A, B, depth, "bf16x3") for A, B in probs]
+    dA = [dev(A) for A, _ in probs]
+    dB = [dev(B) for _, B in probs]
+    Cs = [torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda") for _ in range(4)]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    errors = []
+
+    def work(i):
+        try:
+            for _ in range(6):
+                S.stark_gemm(ctx, dA[i], dB[i], Cs[i], n, depth, p, streams[i])
+            streams[i].synchronize()
+        except Exception as e:          # noqa: BLE001 -- reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for i in range(4):
+        assert np.array_equal(Cs[i].cpu().numpy(), refs[i]), i
+
+
 def test_generator_matches_host_twin(S):
     n = 300
     X = torch.empty((n, n), dtype=torch.float32, device="cuda")
