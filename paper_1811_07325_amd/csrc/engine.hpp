@@ -21,26 +21,11 @@
 
 #include "../../include/stark.h"
 #include "plan.hpp"
+#include "sched.hpp"
 
 struct stark_ctx;
 
 namespace stk {
-
-// First-fit allocator over [0, size) with coalescing of freed ranges.
-class Arena {
-public:
-    explicit Arena(size_t size = 0) { reset(size); }
-    void reset(size_t size);
-    bool alloc(size_t bytes, size_t* off);
-    void free(size_t off, size_t bytes);
-    size_t used() const { return used_; }
-    size_t size() const { return size_; }
-    size_t largest_free() const;
-
-private:
-    std::map<size_t, size_t> free_;  // offset -> length
-    size_t size_ = 0, used_ = 0;
-};
 
 // Device memory of the served requests: segments allocated when admissions
 // need them (at least kSegmentBytes each, at most the budget in total), each
@@ -81,7 +66,8 @@ size_t request_footprint(const Plan& p, bool gen_operands, bool own_c);
 
 class Engine {
 public:
-    static constexpr int kMaxBypass = 8;
+    static constexpr int kMaxBypass = 8;             // passed-over requests per admission pass
+    static constexpr int kMaxHeadPasses = 1000;      // then the oldest request goes next
     static constexpr size_t kMaxQueue = 1 << 16;
     static constexpr size_t kLatWindow = 1 << 20;   // latencies kept for p50 / p99
 
@@ -100,6 +86,7 @@ private:
         Plan plan;
         size_t bytes = 0, off = 0;
         int seg = -1;                 // arena segment
+        int passed = 0;               // admission passes that went over it
         bool gen = false, own_c = false;
         int slot = -1;
         double t_submit = 0, t_admit = 0, t_done = 0;

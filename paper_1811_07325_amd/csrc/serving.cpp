@@ -20,58 +20,6 @@ double now_us() {
     return duration<double, std::micro>(steady_clock::now().time_since_epoch()).count();
 }
 
-// ----------------------------------------------------------------------------
-// Arena
-// ----------------------------------------------------------------------------
-void Arena::reset(size_t size) {
-    free_.clear();
-    size_ = size;
-    used_ = 0;
-    if (size) free_[0] = size;
-}
-
-bool Arena::alloc(size_t bytes, size_t* off) {
-    bytes = (bytes + 255) / 256 * 256;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-        if (it->second >= bytes) {
-            *off = it->first;
-            const size_t rest = it->second - bytes;
-            const size_t start = it->first + bytes;
-            free_.erase(it);
-            if (rest) free_[start] = rest;
-            used_ += bytes;
-            return true;
-        }
-    }
-    return false;
-}
-
-void Arena::free(size_t off, size_t bytes) {
-    bytes = (bytes + 255) / 256 * 256;
-    used_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    // merge with the next range
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-        it->second += nx->second;
-        free_.erase(nx);
-    }
-    // merge with the previous range
-    if (it != free_.begin()) {
-        auto pv = std::prev(it);
-        if (pv->first + pv->second == it->first) {
-            pv->second += it->second;
-            free_.erase(it);
-        }
-    }
-}
-
-size_t Arena::largest_free() const {
-    size_t m = 0;
-    for (const auto& kv : free_) m = std::max(m, kv.second);
-    return m;
-}
-
 SegmentedArena::Result SegmentedArena::alloc(size_t bytes, bool idle, int* seg, size_t* off) {
     for (size_t i = 0; i < segs_.size(); ++i)
         if (segs_[i].arena.alloc(bytes, off)) {
@@ -238,13 +186,8 @@ stark_status Engine::stats(stark_stats_t* out) {
     out->throughput_tflops = (first_admit_ >= 0 && span_s > 0) ? flops_ / span_s * 1e-12 : 0.0;
     std::vector<double> l = lat_ms_;
     std::sort(l.begin(), l.end());
-    auto pct = [&](double q) {
-        if (l.empty()) return 0.0;
-        const size_t i = std::min(l.size() - 1, (size_t)std::ceil(q * l.size()) - (q * l.size() >= 1 ? 1 : 0));
-        return l[i];
-    };
-    out->p50_ms = pct(0.50);
-    out->p99_ms = pct(0.99);
+    out->p50_ms = nearest_rank(l, 0.50);
+    out->p99_ms = nearest_rank(l, 0.99);
     out->max_inflight_bytes = (double)max_bytes_;
     out->max_concurrent = max_inflight_;
     return STARK_OK;
@@ -381,21 +324,18 @@ void Engine::loop() {
                 progress = true;
             }
         }
-        // admissions: FIFO with a bounded bypass of requests that do not fit
-        int bypass = 0;
-        for (auto it = waiting_.begin(); it != waiting_.end();) {
-            int free_slot = -1;
+        // admissions: arrival order, requests that do not fit passed over a
+        // bounded number of times (sched.hpp)
+        int free_slot = -1;
+        auto slot_free = [&] {
+            free_slot = -1;
             for (int si = 0; si < (int)slots_.size(); ++si)
                 if (!slots_[si].busy) { free_slot = si; break; }
-            if (free_slot < 0) break;
-            if (admit(*it, free_slot)) {
-                it = waiting_.erase(it);
-                progress = true;
-            } else {
-                if (++bypass > kMaxBypass) break;
-                ++it;
-            }
-        }
+            return free_slot >= 0;
+        };
+        if (admission_pass(waiting_, slot_free, [&](Req* q) { return admit(q, free_slot); }, kMaxBypass,
+                           kMaxHeadPasses) > 0)
+            progress = true;
         if (stop_ && waiting_.empty() && inflight_ == 0) break;
         if (!progress) {
             if (inflight_ > 0) {
