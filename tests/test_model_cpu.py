@@ -99,3 +99,24 @@ def test_fp16x3_keeps_binary32_accuracy():
     e16 = oracle.rel_frobenius(oracle.strassen_model_f32(A, B, 0, "fp16x3"), exact)
     e3 = oracle.rel_frobenius(oracle.strassen_model_f32(A, B, 0, "bf16x3"), exact)
     assert e16 < 1e-6 < e3
+
+
+def test_model_error_growth_with_depth():
+    """Error of the split precisions against recursion depth (n = 512,
+    normal(0, 1)): a two-term bf16 split keeps 16 significant bits (about
+    4.4e-6 at depth 0) and each Strassen level doubles the error (operand
+    sums before and quadrant sums after each leaf), so BF16X3 stays within
+    1e-5 at depth 1 and not at depth 2; FP16X3 (22 bits) and BF16X6 (24 bits)
+    stay at the binary32 level at every depth."""
+    n = 512
+    A = inputs.normal(n, 31)
+    B = inputs.normal(n, 32)
+    exact = oracle.gemm_f64(A, B)
+    err = {m: [oracle.rel_frobenius(oracle.strassen_model_f32(A, B, d, m), exact) for d in range(4)]
+           for m in ("bf16x3", "bf16x6", "fp16x3")}
+    e3 = err["bf16x3"]
+    assert 3e-6 < e3[0] < 6e-6
+    for k in range(3):
+        assert 1.6 < e3[k + 1] / e3[k] < 2.4
+    assert e3[1] < 1e-5 < e3[2]
+    assert max(err["bf16x6"]) < 1e-6 and max(err["fp16x3"]) < 1e-6
