@@ -64,8 +64,14 @@ typedef int stark_status;
  * magnitude, so every leaf operand stays below 2^14), each leaf operand split
  * into two binary16 terms hi + lo (22 significant bits), hi*hi + hi*lo +
  * lo*hi on fp16 matrix cores with binary32 accumulation, and the product
- * scaled back exactly.  Entries smaller than about 2^-25 times the largest
- * entry of their matrix lose relative precision (binary16 subnormals). */
+ * scaled back exactly (the exponent is capped at 127 for matrices whose
+ * largest magnitude is below about 2^-113).  An entry 2^-k times the largest
+ * magnitude of its matrix keeps about min(22, 38 - depth - k) significant
+ * bits (binary16 subnormals below that): at depth 0 every row and column
+ * down to 2^-20 of the largest keeps binary32-level accuracy.  At depth >= 1
+ * Strassen's operand sums add rows (and columns) of different scales, so in
+ * every leaf precision, FP32 included, a row much smaller than the rows it
+ * is added to loses accuracy; the error bound of the recursion is normwise. */
 typedef enum {
     STARK_FP32 = 0,
     STARK_BF16X3 = 1,
@@ -169,8 +175,12 @@ typedef struct {
  * the caller's A and B (C is overwritten), time each after a warm-up,
  * estimate its error as ||C x - A (B x)|| / ||A (B x)|| for a Gaussian x, and
  * record the fastest (depth, tile) whose error is <= tol (tol <= 0: 1e-5 or
- * STARK_TUNE_TOL), else the most accurate.  Later calls with depth =
- * STARK_DEPTH_AUTO (stark_gemm, stark_submit) use the record.  Up to `cap`
+ * STARK_TUNE_TOL).  If no point is within tol nothing is recorded (a record
+ * made earlier stays) and the call still returns STARK_OK: the points carry
+ * their errors.  Later calls with depth = STARK_DEPTH_AUTO (stark_gemm,
+ * stark_submit, stark_gemm_batched) use the record; one with no record tunes
+ * depths 0..5 first and, should none meet the tolerance, records the most
+ * accurate point, marked as outside it in the cache file.  Up to `cap`
  * points are written to `points` (may be NULL) and their number to *count
  * (may be NULL).  Synchronises `stream`. */
 stark_status stark_tune(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n,
@@ -215,7 +225,11 @@ typedef struct {
     double checksum;          /* sum of the result in binary64 (library-owned C)   */
 } stark_result;
 
-/* Enqueue a request; returns at once with a ticket.  Thread-safe.
+/* Enqueue a request; returns at once with a ticket.  Thread-safe.  The
+ * engine runs requests on streams of its own that do not wait for any stream
+ * of the caller: caller-owned A, B and C must hold their final contents on the
+ * device (e.g. the host synchronised after writing them) before the call, and
+ * must stay valid, and C unread, until stark_poll returns STARK_OK.
  * Errors: EINVAL, EBUSY (queue full), ENOMEM (request alone exceeds the HBM
  * budget). */
 stark_status stark_submit(stark_ctx* ctx, const stark_request* r, uint64_t* ticket);

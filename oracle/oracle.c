@@ -529,7 +529,8 @@ static float f16_round(float x)
  * levels are at most 2^depth max|X|, so scaling by 2^(14 - depth - E)
  * keeps them below 2^14 (binary16's largest finite value is 65504).  In
  * Winograd's variant an operand sums up to four blocks per level (S4, T4),
- * so its callers pass 2 * depth. */
+ * so its callers pass 2 * depth.  The exponent is capped at 127, the largest
+ * for which 2^e is a finite binary32. */
 int oracle_f16_scale_exp(const float* X, int64_t count, int depth)
 {
     float m = 0.0f;
@@ -540,7 +541,8 @@ int oracle_f16_scale_exp(const float* X, int64_t count, int depth)
     if (m == 0.0f) return 0;
     int E;
     frexp((double)m, &E);
-    return 14 - depth - E;
+    const int e = 14 - depth - E;
+    return e < 127 ? e : 127;
 }
 
 /* x ~= hi + mid + lo with each term bfloat16: hi = rne(x), mid = rne(x - hi),
@@ -572,7 +574,8 @@ void oracle_split_bf16(const float* x, int64_t count, int terms, uint16_t* out)
 /*                    plane indices sum to at most 2                          */
 /*   mode 4 (FP16X3): x scaled by 2^ex, y by 2^ey (oracle_f16_scale_exp of  */
 /*                    the whole A and B), split into two binary16 terms,     */
-/*                    xh*yh + xh*yl + xl*yh, result scaled by 2^-(ex+ey)     */
+/*                    xh*yh + xh*yl + xl*yh, result scaled by 2^-ex, then  */
+/*                    by 2^-ey (two exact steps, as the GPU epilogue)       */
 /* The GPU accumulates the leaf sums in binary32 instead; the difference is  */
 /* that accumulation's rounding only, so GPU results sit within a few units  */
 /* of accumulation error of this model at any depth.                         */
@@ -619,7 +622,7 @@ static void leaf_model(const float* X, int64_t ldx, const float* Y, int64_t ldy,
     for (int64_t i = 0; i < m; ++i)
         for (int64_t j = 0; j < m; ++j) {
             float z = (float)acc[(size_t)i * m + j];
-            if (mode == 4) z = ldexpf(z, -(g_model_ex + g_model_ey));
+            if (mode == 4) z = ldexpf(ldexpf(z, -g_model_ex), -g_model_ey);   /* one factor at a time */
             Z[i * ldz + j] = z;
         }
     free(xp); free(yp); free(acc);
@@ -700,5 +703,15 @@ int oracle_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Thread count of the OpenMP loops from here on (CPU timings on 1 thread). */
+void oracle_set_threads(int count)
+{
+#ifdef _OPENMP
+    if (count > 0) omp_set_num_threads(count);
+#else
+    (void)count;
 #endif
 }

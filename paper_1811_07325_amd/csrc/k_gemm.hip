@@ -45,11 +45,17 @@ template <> struct Op16<true> {
     }
 };
 
-// Factor that undoes the FP16X3 operand scaling 2^(e_A + e_B) (exact).
-__device__ __forceinline__ float unscale_of(const ProbDesc& d) {
-    if (!d.fp16) return 1.0f;
+// Factors 2^-e_A and 2^-e_B that undo the FP16X3 operand scaling (exact
+// powers of two; applied one after the other, so each stays a finite binary32
+// whatever the sum e_A + e_B).
+struct Unscale {
+    float a, b;
+    __device__ __forceinline__ float operator()(float x) const { return x * a * b; }
+};
+__device__ __forceinline__ Unscale unscale_of(const ProbDesc& d) {
+    if (!d.fp16) return Unscale{1.0f, 1.0f};
     const int* ex = reinterpret_cast<const int*>(reinterpret_cast<const float*>(d.ws) + d.scale) + 2 * kScaleParts;
-    return ldexpf(1.0f, -(ex[0] + ex[1]));
+    return Unscale{ldexpf(1.0f, -ex[0]), ldexpf(1.0f, -ex[1])};
 }
 
 constexpr int kGroupRows = 8;
@@ -170,7 +176,7 @@ __device__ __forceinline__ void gemm16_lds(Src src, int64_t total_tiles) {
         if (d.depth == 0) { Cp = d.C; ldc = d.n; }
         else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
         const bool crop = d.depth == 0 && d.bounded0;
-        const float unscale = unscale_of(d);
+        const Unscale unscale = unscale_of(d);
         const int64_t m0 = tm * BM, n0 = tn * BN;
 
         // One direct load of a wave moves one 1 KB block of the blocked
@@ -253,7 +259,7 @@ __device__ __forceinline__ void gemm16_lds(Src src, int64_t total_tiles) {
                 for (int r = 0; r < 4; ++r) {
                     const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
                     const int64_t col = n0 + wn * WN + 16 * j + li;
-                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r] * unscale;
+                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = unscale(acc[i][j][r]);
                 }
     }
 }

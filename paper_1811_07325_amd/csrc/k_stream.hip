@@ -532,6 +532,8 @@ __global__ __launch_bounds__(kStreamThreads) void k_split(Src src) {
 // e = 14 - depth - E, with max = m 2^E (m in [0.5, 1)): multiplying by 2^e
 // keeps every leaf operand (at most 2^depth max) below 2^14; Winograd's
 // variant sums up to 4 blocks per level, so there e = 14 - 2 depth - E.
+// e is capped at 127 so that 2^e is a finite binary32 (matrices whose largest
+// magnitude is below about 2^-113 are scaled by 2^127 only).
 // ---------------------------------------------------------------------------
 constexpr int kAbsThreads = 1024;   // 16 waves per part: 2 x 256 parts fill the chip
 
@@ -594,8 +596,9 @@ __global__ __launch_bounds__(kScaleParts) void k_scale_exp(Src src) {
         if (m > 0.0f) frexpf(m, &E);
         // a leaf operand sums at most 2 blocks per level (4 in Winograd's variant)
         const int growth = d.variant ? 2 * d.depth : d.depth;
+        const int e = m > 0.0f ? 14 - growth - E : 0;
         reinterpret_cast<int*>(reinterpret_cast<float*>(d.ws) + d.scale)[2 * kScaleParts + threadIdx.x] =
-            m > 0.0f ? 14 - growth - E : 0;
+            e < 127 ? e : 127;
     }
 }
 

@@ -92,6 +92,21 @@ def test_f16_scale_exponent():
     assert oracle.f16_scale_exp(np.zeros((4, 4), np.float32), 2) == 0
 
 
+def test_f16_scale_exponent_capped_for_tiny_matrices():
+    """The exponent is capped at 127 so that 2^e is a finite binary32; a
+    matrix near 2^-120 is then scaled by 2^127 only, its operands stay well
+    inside binary16's range and the model's product keeps its accuracy."""
+    A = (inputs.uniform(64, 23) * 2.0 ** -120).astype(np.float32)
+    B = inputs.uniform(64, 24)
+    E = int(np.frexp(float(np.max(np.abs(A))))[1])
+    assert 14 - 2 - E > 127
+    assert oracle.f16_scale_exp(A, 2) == 127
+    assert np.isfinite(np.float32(2.0) ** 127)
+    M = oracle.strassen_model_f32(A, B, 2, "fp16x3")
+    assert np.all(np.isfinite(M))
+    assert oracle.rel_frobenius(M, oracle.gemm_f64(A, B)) < 1e-6
+
+
 def test_fp16x3_keeps_binary32_accuracy():
     A = inputs.normal(64, 21)
     B = inputs.normal(64, 22)
