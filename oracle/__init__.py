@@ -81,6 +81,7 @@ def _load():
     lib.oracle_divide_f32_w.argtypes = [P, I64, P, I64, I64, P, P]
     lib.oracle_combine_f32_w.argtypes = [P, I64, P, I64]
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_f16_scale_exp.argtypes = [P, I64, ctypes.c_int]
     lib.oracle_f16_scale_exp.restype = ctypes.c_int
     lib.oracle_split_f16.argtypes = [P, I64, ctypes.c_int, P]
@@ -304,6 +305,11 @@ def rect_model_f32(A, B, s: int, depth: int, mode: str, variant: str = "strassen
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().oracle_threads())
+
+
+def set_threads(count: int) -> None:
+    """Threads of the oracle's parallel loops from here on (count >= 1)."""
+    _load().oracle_set_threads(int(count))
 
 
 def set_mutation(m: int) -> None:

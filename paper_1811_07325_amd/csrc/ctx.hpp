@@ -50,6 +50,7 @@ struct TuneEntry {
     int tile;   // leaf-GEMM tile class (0: the planner's rule)
     double ms;
     double err;
+    bool in_tol;  // err within the tolerance the point was measured against
 };
 
 }  // namespace stk
@@ -112,9 +113,11 @@ stark_status check_operands(const float* A, const float* B, const float* C, int6
 stark_status tuned_depth(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int precision,
                          hipStream_t st, int* depth, int* tile);
 void tuner_load(stark_ctx* ctx);
+// record_fallback: when no point is within tol, record the most accurate
+// one (flagged) instead of nothing.
 stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int precision,
-                        int dmin, int dmax, double tol, hipStream_t st, std::vector<TuneEntry>& results,
-                        int* depth, int* tile);
+                        int dmin, int dmax, double tol, bool record_fallback, hipStream_t st,
+                        std::vector<TuneEntry>& results, int* depth, int* tile);
 
 // Leaf-GEMM grid for `tiles` tiles: resident blocks per CU x CUs, capped.
 int gemm_grid(stark_ctx* ctx, int planes, int tile, int64_t tiles);

@@ -382,7 +382,7 @@ stark_status stark_tune(stark_ctx* ctx, const float* A, const float* B, float* C
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((rc = ws_wait(ctx, st)) != STARK_OK) return rc;
     rc = ws_done(ctx, st,
-                 tune_range(ctx, A, B, C, n, (int)prec, min_depth, max_depth, tol, st, res, &depth, &tile));
+                 tune_range(ctx, A, B, C, n, (int)prec, min_depth, max_depth, tol, false, st, res, &depth, &tile));
     if (rc != STARK_OK) return rc;
     if (points)
         for (int i = 0; i < cap && i < (int)res.size(); ++i)

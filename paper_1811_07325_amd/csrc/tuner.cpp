@@ -7,8 +7,11 @@
 // binary64 on the GPU: e = ||C x - A (B x)|| / ||A (B x)|| for a Gaussian x,
 // whose square has the squared relative Frobenius error as its expectation.
 // The fastest (depth, tile) whose error is within the tolerance (default
-// 1e-5, STARK_TUNE_TOL) wins; if none is, the most accurate.  Results persist
-// in a small text file.
+// 1e-5, STARK_TUNE_TOL) is recorded.  An explicit tuning request (stark_tune)
+// whose points all miss the tolerance records nothing; the automatic depth
+// (STARK_DEPTH_AUTO with no record) must run something, so there the most
+// accurate point is recorded, flagged as outside the tolerance.  Records
+// persist in a small text file.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,10 +29,10 @@ static void tuner_save(stark_ctx* ctx) {
     if (ctx->tune_path.empty()) return;
     FILE* f = std::fopen(ctx->tune_path.c_str(), "w");
     if (!f) return;
-    std::fprintf(f, "# n precision depth ms freivalds_error tile\n");
+    std::fprintf(f, "# n precision depth ms freivalds_error tile within_tolerance\n");
     for (const auto& kv : ctx->tune)
-        std::fprintf(f, "%lld %d %d %.6f %.6e %d\n", (long long)kv.first.first, kv.first.second, kv.second.depth,
-                     kv.second.ms, kv.second.err, kv.second.tile);
+        std::fprintf(f, "%lld %d %d %.6f %.6e %d %d\n", (long long)kv.first.first, kv.first.second, kv.second.depth,
+                     kv.second.ms, kv.second.err, kv.second.tile, kv.second.in_tol ? 1 : 0);
     std::fclose(f);
 }
 
@@ -41,20 +44,20 @@ void tuner_load(stark_ctx* ctx) {
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
         long long n;
-        int prec, depth, tile = 0;
+        int prec, depth, tile = 0, in_tol = 1;
         double ms, err;
-        const int got = std::sscanf(line, "%lld %d %d %lf %lf %d", &n, &prec, &depth, &ms, &err, &tile);
+        const int got = std::sscanf(line, "%lld %d %d %lf %lf %d %d", &n, &prec, &depth, &ms, &err, &tile, &in_tol);
         Plan p;
         if (got >= 5 && n > 0 && depth >= 0 && depth <= max_depth_for(n) &&
-            make_plan(n, depth, prec, p, got == 6 ? tile : 0).empty())
-            ctx->tune[{(int64_t)n, prec}] = TuneEntry{depth, got == 6 ? tile : 0, ms, err};
+            make_plan(n, depth, prec, p, got >= 6 ? tile : 0).empty())
+            ctx->tune[{(int64_t)n, prec}] = TuneEntry{depth, got >= 6 ? tile : 0, ms, err, in_tol != 0};
     }
     std::fclose(f);
 }
 
 stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n, int precision,
-                        int dmin, int dmax, double tol, hipStream_t st, std::vector<TuneEntry>& results,
-                        int* depth, int* tile) {
+                        int dmin, int dmax, double tol, bool record_fallback, hipStream_t st,
+                        std::vector<TuneEntry>& results, int* depth, int* tile) {
     const int maxd = std::min(dmax, max_depth_for(n));
     if (tol <= 0) tol = ctx->tune_tol;
     // Gaussian probe (fixed seed) and A (B x), binary64.
@@ -116,7 +119,8 @@ stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C
         double num = 0.0;
         for (int64_t i = 0; i < n; ++i) num += (hcx[i] - habx[i]) * (hcx[i] - habx[i]);
         std::sort(times.begin(), times.end());
-        results.push_back(TuneEntry{p.depth, p.tile, times[times.size() / 2], nref > 0 ? std::sqrt(num) / nref : 0.0});
+        const double err = nref > 0 ? std::sqrt(num) / nref : 0.0;
+        results.push_back(TuneEntry{p.depth, p.tile, times[times.size() / 2], err, err <= tol});
         return true;
     };
     bool more = rc == STARK_OK;
@@ -143,10 +147,14 @@ stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C
     }
     const TuneEntry* best = nullptr;
     for (const auto& r : results)
-        if (r.err <= tol && (!best || r.ms < best->ms)) best = &r;
-    if (!best)
+        if (r.in_tol && (!best || r.ms < best->ms)) best = &r;
+    if (!best) {
         for (const auto& r : results)
             if (!best || r.err < best->err) best = &r;
+        *depth = best->depth;
+        *tile = best->tile;
+        if (!record_fallback) return STARK_OK;   // nothing within the tolerance: no record
+    }
     ctx->tune[{n, precision}] = *best;
     tuner_save(ctx);
     *depth = best->depth;
@@ -163,7 +171,7 @@ stark_status tuned_depth(stark_ctx* ctx, const float* A, const float* B, float* 
         return STARK_OK;
     }
     std::vector<TuneEntry> results;
-    return tune_range(ctx, A, B, C, n, precision, 0, 5, 0.0, st, results, depth, tile);
+    return tune_range(ctx, A, B, C, n, precision, 0, 5, 0.0, true, st, results, depth, tile);
 }
 
 }  // namespace stk

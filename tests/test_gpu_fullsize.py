@@ -8,7 +8,8 @@
 * n = 16384, normal(0, 1), split-precision leaves, depth chosen by the
   autotuner among 2..4, run as the benchmark runs it (one stream, eager call
   then graph replay): 256 sampled rows against the FP64 oracle and Freivalds'
-  check;
+  check, within 1e-5 for the benchmark's headline path; BF16X3's error growth
+  with depth;
 * n = 49152 and 49120 (n^2 > 2^31), integer inputs: exact on rows whose
   element offsets cross 2^31.
 """
@@ -52,13 +53,9 @@ def rel_rows(C, ref, rows):
     return float(np.sqrt(np.sum(d * d) / np.sum(ref * ref))), float(np.max(np.abs(d)))
 
 
-def fp32_bound(n, depth):
-    """Componentwise-style estimate for binary32 Strassen: unit roundoff times
-    sqrt(leaf inner length) for the leaf sums, times a growth of 4 per level
-    (each level adds operand sums before and quadrant sums after the leaf),
-    times a safety factor of 8."""
-    u = 2.0 ** -24
-    return 8 * u * np.sqrt(n / 2 ** depth) * 4 ** depth
+# Relative Frobenius error allowed against the FP64 oracle for the binary32
+# and 22-bit split paths (measured errors are about 1e-6 at these sizes).
+TOL = 1e-5
 
 
 def test_n512_two_levels_fp32_and_integer_copy(S, ctx):
@@ -68,7 +65,7 @@ def test_n512_two_levels_fp32_and_integer_copy(S, ctx):
     ref = oracle.gemm_f64(A, B)
     err = oracle.rel_frobenius(C, ref)
     print(f"n=512 depth 2 fp32: rel_frob={err:.3e} max_abs={oracle.max_abs(C, ref):.3e}")
-    assert err <= fp32_bound(n, depth)
+    assert err <= TOL
     Ai, Bi = inputs.integers(n, 0), inputs.integers(n, 1)
     Ci = multiply(S, ctx, dev(Ai), dev(Bi), n, depth, S.STARK_FP32).cpu().numpy()
     assert np.array_equal(Ci.astype(np.int64), oracle.gemm_i64(Ai, Bi))
@@ -78,20 +75,32 @@ def test_n4096_three_levels_fp32_next_to_classical(S, ctx):
     n, depth = 4096, 3
     A, B = inputs.uniform(n, 0), inputs.uniform(n, 1)
     dA, dB = dev(A), dev(B)
-    rows = inputs.sample_rows(n, 64, 2)
+    rows = inputs.sample_rows(n, 256, 2)
     ref = oracle.rows_f64(A, B, rows)
     Cs = multiply(S, ctx, dA, dB, n, depth, S.STARK_FP32)
     Cc = multiply(S, ctx, dA, dB, n, 0, S.STARK_FP32)
     es, ms = rel_rows(Cs, ref, rows)
     ec, mc = rel_rows(Cc, ref, rows)
     print(f"n=4096 fp32: depth 3 rel_frob={es:.3e} max_abs={ms:.3e}; classical rel_frob={ec:.3e} max_abs={mc:.3e}")
-    assert es <= fp32_bound(n, depth)
-    assert ec <= fp32_bound(n, 0)
-    assert es <= 4 ** depth * ec       # at most a factor 4 per level over classical
+    assert es <= TOL
+    assert ec <= TOL
     # both results estimate the same product: their difference is bounded by
     # the sum of their errors
     d = (Cs - Cc).double()
-    assert float(torch.linalg.norm(d) / torch.linalg.norm(Cc.double())) <= fp32_bound(n, depth) + fp32_bound(n, 0)
+    assert float(torch.linalg.norm(d) / torch.linalg.norm(Cc.double())) <= 2 * TOL
+    # element by element against the oracle's arithmetic model of depth 3
+    # (binary32 divide / combine, exact leaf sums): what remains is the
+    # binary32 accumulation inside the 512-long leaf sums, amplified by at
+    # most 2 per level
+    model = oracle.strassen_model_f32(A, B, depth, "fp32", n)
+    got = Cs.cpu().numpy()
+    dm = oracle.rel_frobenius(got, model)
+    ulp_bound = 4 * 2.0 ** -24 * np.sqrt(n >> depth) * 2 ** depth
+    print(f"  depth 3 vs model: rel_frob={dm:.3e} (bound {ulp_bound:.3e})")
+    assert dm <= ulp_bound
+    # elementwise: every entry within that many units of the entry's scale
+    scale = np.sqrt(np.mean(model.astype(np.float64) ** 2))
+    assert np.max(np.abs(got.astype(np.float64) - model)) <= 8 * ulp_bound * scale
     # integer copy: exact on sampled rows (every intermediate is an integer
     # below 2^24 at this size)
     Ai, Bi = inputs.integers(n, 0), inputs.integers(n, 1)
@@ -101,38 +110,12 @@ def test_n4096_three_levels_fp32_next_to_classical(S, ctx):
     assert np.array_equal(got, exact.astype(np.int64))
 
 
-# Split-precision error at n = 16384, normal(0, 1) inputs.  FP16X3 keeps 22
-# significant bits per operand, so the target of 1e-5 holds at depths 2..4.
-# BF16X3 keeps 16; its error doubles per level from about 4.4e-6 at depth 0,
-# which passes 1e-5 only up to depth 1 (the oracle's arithmetic model gives
-# the same figures), so at depths 2..4 it is held to twice that estimate.
-SPLIT_BOUND = {"fp16x3": lambda d: 1e-5, "bf16x3": lambda d: 2 * 4.4e-6 * 2 ** d}
+# Split-precision paths at n = 16384, normal(0, 1) inputs, relative Frobenius
+# error against the FP64 oracle on 256 sampled rows.
+HEADLINE_TOL = 1e-5
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
-def test_n16384_split_precision_autotuned(S, ctx, precision):
-    n = 16384
-    prec = S.PRECISIONS[precision]
-    A, B = inputs.normal(n, 0), inputs.normal(n, 1)
-    dA, dB = dev(A), dev(B)
-    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
-    st = torch.cuda.Stream()
-    pts = S.stark_tune(ctx, dA, dB, C, n, prec, 2, 4, 1e-5, st)
-    assert sorted(set(p[0] for p in pts)) == [2, 3, 4]
-    for d in (2, 3, 4):      # the planner's tile class is always measured; every class divides the leaf
-        assert S.stark_plan_info(n, d, prec).gemm_tile in [p[3] for p in pts if p[0] == d]
-    assert all((n >> p[0]) % p[3] == 0 for p in pts)
-    ok = [p for p in pts if p[2] <= 1e-5]
-    tuned = min(ok, key=lambda p: p[1]) if ok else min(pts, key=lambda p: p[2])
-    depth = tuned[0]
-    outs = []
-    for _ in range(3):                 # eager, capture, replay of what the autotuner recorded
-        C.fill_(float("nan"))
-        torch.cuda.synchronize()
-        S.stark_gemm(ctx, dA, dB, C, n, S.STARK_DEPTH_AUTO, prec, st)
-        st.synchronize()
-        outs.append(C.clone())
-    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+def row_and_freivalds_errors(S, st, dA, dB, C, A, B, n):
     rows = inputs.sample_rows(n, 256, 2)
     ref = oracle.rows_f64(A, B, rows)
     err, mabs = rel_rows(C, ref, rows)
@@ -143,14 +126,78 @@ def test_n16384_split_precision_autotuned(S, ctx, precision):
     S.stark_matvec_f64(C, x, y[2], n, st)
     st.synchronize()
     freiv = float(torch.linalg.norm(y[2] - y[1]) / torch.linalg.norm(y[1]))
-    print(f"n=16384 {precision}: tune {[(d, t, round(m, 3), f'{e:.2e}') for d, m, e, t in pts]}; "
-          f"depth {depth} tile {tuned[3]}: "
+    return err, mabs, freiv
+
+
+@pytest.fixture(scope="module")
+def big_inputs():
+    n = 16384
+    A, B = inputs.normal(n, 0), inputs.normal(n, 1)
+    return n, A, B, dev(A), dev(B)
+
+
+def test_n16384_headline_path_within_tolerance(S, ctx, big_inputs):
+    """The benchmark's headline: among the three-product split paths on the
+    16-bit matrix cores (FP16X3, BF16X3), depths 2..4 autotuned, the fastest
+    whose Freivalds error is within 1e-5; its result must then be within 1e-5
+    on 256 sampled rows, eager, captured and replayed alike."""
+    n, A, B, dA, dB = big_inputs
+    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    st = torch.cuda.Stream()
+    best = None
+    for name in ("fp16x3", "bf16x3"):
+        prec = S.PRECISIONS[name]
+        pts = S.stark_tune(ctx, dA, dB, C, n, prec, 2, 4, HEADLINE_TOL, st)
+        assert sorted(set(p[0] for p in pts)) == [2, 3, 4]
+        for d in (2, 3, 4):      # the planner's tile class is always measured; every class divides the leaf
+            assert S.stark_plan_info(n, d, prec).gemm_tile in [p[3] for p in pts if p[0] == d]
+        assert all((n >> p[0]) % p[3] == 0 for p in pts)
+        print(f"n=16384 {name}: tune {[(d, t, round(m, 3), f'{e:.2e}') for d, m, e, t in pts]}", flush=True)
+        for p in pts:
+            if p[2] <= HEADLINE_TOL and (best is None or p[1] < best[2][1]):
+                best = (name, prec, p)
+    assert best is not None, "no split path within the tolerance at depths 2..4"
+    name, prec, tuned = best
+    outs = []
+    for _ in range(3):                 # eager, capture, replay of what the autotuner recorded
+        C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        S.stark_gemm(ctx, dA, dB, C, n, S.STARK_DEPTH_AUTO, prec, st)
+        st.synchronize()
+        outs.append(C.clone())
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    err, mabs, freiv = row_and_freivalds_errors(S, st, dA, dB, C, A, B, n)
+    print(f"headline {name} depth {tuned[0]} tile {tuned[3]}: "
           f"rel_frob(256 rows)={err:.3e} max_abs={mabs:.3e} freivalds={freiv:.3e}")
-    assert err <= SPLIT_BOUND[precision](depth)
+    assert err <= HEADLINE_TOL
+    assert freiv <= HEADLINE_TOL
     # Freivalds' estimate and the sampled rows measure the same error: same order
     assert 0.25 * err <= freiv <= 4 * err
     # the tuner's own Freivalds figure agrees with this one
     assert 0.25 * freiv <= tuned[2] <= 4 * freiv
+
+
+def test_n16384_bf16x3_error_grows_with_depth(S, ctx, big_inputs):
+    """Documents why BF16X3 is not the headline: a two-term bf16 split keeps
+    16 significant bits (about 4.4e-6 at depth 0) and every Strassen level
+    roughly doubles the error, so at depths 2..4 it misses 1e-5; each depth
+    stays within twice that growth, and the autotuner records nothing for a
+    depth range with no point within the tolerance."""
+    n, A, B, dA, dB = big_inputs
+    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    st = torch.cuda.Stream()
+    errs = []
+    for depth in (2, 3, 4):
+        C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        S.stark_gemm(ctx, dA, dB, C, n, depth, S.STARK_BF16X3, st)
+        st.synchronize()
+        err, mabs, freiv = row_and_freivalds_errors(S, st, dA, dB, C, A, B, n)
+        print(f"n=16384 bf16x3 depth {depth}: rel_frob(256 rows)={err:.3e} freivalds={freiv:.3e}", flush=True)
+        assert err <= 2 * 4.4e-6 * 2 ** depth
+        assert err > HEADLINE_TOL
+        errs.append(err)
+    assert all(1.5 < errs[i + 1] / errs[i] < 2.6 for i in range(2))
 
 
 # n^2 > 2^31: every element offset of A, B, C and the workspace needs 64 bits.
