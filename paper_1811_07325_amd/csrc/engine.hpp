@@ -105,14 +105,20 @@ private:
     void loop();
     bool admit(Req* q, int slot);
     void finish(int slot);
+    void publish_failure(Req* q, stark_status status);
 
     stark_ctx* ctx_;
     double* host_sums_ = nullptr; // pinned, one per slot
-    SegmentedArena mem_;          // device memory of the requests in flight
+    // Engine thread only (no lock): the requests waiting for admission, the
+    // slots, the device memory and the count of requests in flight.
+    SegmentedArena mem_;
     std::vector<Slot> slots_;
+    std::deque<Req*> waiting_;
+    int inflight_ = 0;
+    // Guarded by mu_: arrivals, the live requests' published results, stats.
     std::mutex mu_;
     std::condition_variable cv_;
-    std::deque<Req*> arrivals_, waiting_;
+    std::deque<Req*> arrivals_;
     std::map<uint64_t, Req*> live_;     // submitted, not yet polled
     uint64_t next_ticket_ = 1;
     bool stop_ = false;
@@ -122,8 +128,8 @@ private:
     size_t lat_next_ = 0;
     uint64_t completed_ = 0, failed_ = 0;
     double flops_ = 0, first_admit_ = -1, last_done_ = 0;
-    size_t max_bytes_ = 0;
-    int inflight_ = 0, max_inflight_ = 0;
+    size_t max_bytes_ = 0, used_pub_ = 0, waiting_pub_ = 0;
+    int inflight_pub_ = 0, max_inflight_ = 0;
     int64_t fault_tag_ = -1;   // STARK_FAULT_INJECT: tag of a request made to fail
 };
 

@@ -146,7 +146,7 @@ stark_status Engine::submit(const stark_request& r, uint64_t* ticket) {
         return STARK_ENOMEM;
     }
     std::lock_guard<std::mutex> lk(mu_);
-    if (arrivals_.size() + waiting_.size() >= kMaxQueue) { set_error("queue full"); return STARK_EBUSY; }
+    if (arrivals_.size() + waiting_pub_ >= kMaxQueue) { set_error("queue full"); return STARK_EBUSY; }
     q->ticket = next_ticket_++;
     q->t_submit = now_us();
     *ticket = q->ticket;
@@ -201,8 +201,21 @@ void Engine::reset_stats() {
     flops_ = 0;
     first_admit_ = -1;
     last_done_ = 0;
-    max_bytes_ = mem_.used();
-    max_inflight_ = inflight_;
+    max_bytes_ = used_pub_;
+    max_inflight_ = inflight_pub_;
+}
+
+// The engine thread alone touches waiting_, slots_, mem_ and inflight_, so
+// choosing, reserving and launching a request need no lock; mu_ is taken
+// only to publish results and statistics (and to take arrivals), so
+// stark_submit / stark_poll / stark_stats never wait behind kernel launches.
+
+void Engine::publish_failure(Req* q, stark_status status) {
+    std::lock_guard<std::mutex> lk(mu_);
+    q->status = status;
+    ++failed_;
+    inflight_pub_ = inflight_;
+    q->t_done = now_us();   // last: poll may retire the request from here on
 }
 
 bool Engine::admit(Req* q, int si) {
@@ -211,9 +224,7 @@ bool Engine::admit(Req* q, int si) {
     const SegmentedArena::Result got = mem_.alloc(q->bytes, inflight_ == 0, &seg, &off);
     if (got == SegmentedArena::kWait) return false;
     if (got == SegmentedArena::kFail) {   // nothing in flight and the device refused the memory
-        q->status = STARK_ENOMEM;
-        q->t_done = now_us();
-        ++failed_;
+        publish_failure(q, STARK_ENOMEM);
         return true;
     }
     Slot& s = slots_[si];
@@ -221,12 +232,17 @@ bool Engine::admit(Req* q, int si) {
     q->off = off;
     q->slot = si;
     q->t_admit = now_us();
-    if (first_admit_ < 0) first_admit_ = q->t_admit;
     s.busy = true;
     s.req = q;
     ++inflight_;
-    max_inflight_ = std::max(max_inflight_, inflight_);
-    max_bytes_ = std::max(max_bytes_, mem_.used());
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (first_admit_ < 0) first_admit_ = q->t_admit;
+        inflight_pub_ = inflight_;
+        max_inflight_ = std::max(max_inflight_, inflight_);
+        used_pub_ = mem_.used();
+        max_bytes_ = std::max(max_bytes_, used_pub_);
+    }
 
     const size_t nn = (size_t)q->r.n * (size_t)q->r.n * 4;
     const size_t nn_al = (nn + 255) / 256 * 256;
@@ -259,16 +275,14 @@ bool Engine::admit(Req* q, int si) {
         if (e == hipSuccess && rc == STARK_OK) e = hipEventRecord(s.ev1, s.stream);
     }
     if (e != hipSuccess || rc != STARK_OK) {
-        q->status = rc != STARK_OK ? rc : STARK_EDEVICE;
         // make sure nothing of this request is still running before its memory is reused
         (void)hipStreamSynchronize(s.stream);
         (void)hipGetLastError();
-        q->t_done = now_us();
-        ++failed_;
         mem_.free(q->seg, q->off, q->bytes);
         s.busy = false;
         s.req = nullptr;
         --inflight_;
+        publish_failure(q, rc != STARK_OK ? rc : STARK_EDEVICE);
     }
     return true;
 }
@@ -278,30 +292,42 @@ void Engine::finish(int si) {
     Req* q = s.req;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, s.ev0, s.ev1);
-    q->gpu_ms = ms;
-    q->checksum = q->own_c ? host_sums_[si] : 0.0;
-    q->t_done = now_us();
-    q->status = STARK_OK;
-    ++completed_;
-    const double lat = (q->t_done - q->t_submit) * 1e-3;
-    if (lat_ms_.size() < kLatWindow) lat_ms_.push_back(lat);
-    else lat_ms_[lat_next_] = lat;
-    lat_next_ = (lat_next_ + 1) % kLatWindow;
-    flops_ += 2.0 * (double)q->r.n * (double)q->r.n * (double)q->r.n;
-    last_done_ = q->t_done;
+    const double checksum = q->own_c ? host_sums_[si] : 0.0;
     mem_.free(q->seg, q->off, q->bytes);
     s.busy = false;
     s.req = nullptr;
     --inflight_;
+    std::lock_guard<std::mutex> lk(mu_);
+    q->gpu_ms = ms;
+    q->checksum = checksum;
+    q->status = STARK_OK;
+    ++completed_;
+    const double t = now_us();
+    const double lat = (t - q->t_submit) * 1e-3;
+    if (lat_ms_.size() < kLatWindow) lat_ms_.push_back(lat);
+    else lat_ms_[lat_next_] = lat;
+    lat_next_ = (lat_next_ + 1) % kLatWindow;
+    flops_ += 2.0 * (double)q->r.n * (double)q->r.n * (double)q->r.n;
+    last_done_ = t;
+    inflight_pub_ = inflight_;
+    used_pub_ = mem_.used();
+    q->t_done = t;   // last: poll may retire the request from here on
 }
 
 void Engine::loop() {
     (void)hipSetDevice(ctx_->device);
-    std::unique_lock<std::mutex> lk(mu_);
     while (true) {
-        while (!arrivals_.empty()) {
-            waiting_.push_back(arrivals_.front());
-            arrivals_.pop_front();
+        bool stopping;
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            if (arrivals_.empty() && waiting_.empty() && inflight_ == 0 && !stop_)
+                cv_.wait_for(lk, std::chrono::milliseconds(5));
+            while (!arrivals_.empty()) {
+                waiting_.push_back(arrivals_.front());
+                arrivals_.pop_front();
+            }
+            waiting_pub_ = waiting_.size();   // at most one pass stale: only bounds the queue
+            stopping = stop_;
         }
         bool progress = false;
         // completions
@@ -313,14 +339,12 @@ void Engine::loop() {
                 progress = true;
             } else if (e != hipErrorNotReady) {
                 Req* q = slots_[si].req;
-                q->status = STARK_EDEVICE;
-                q->t_done = now_us();
-                ++failed_;
                 mem_.free(q->seg, q->off, q->bytes);
                 slots_[si].busy = false;
                 slots_[si].req = nullptr;
                 --inflight_;
                 (void)hipGetLastError();
+                publish_failure(q, STARK_EDEVICE);
                 progress = true;
             }
         }
@@ -336,16 +360,8 @@ void Engine::loop() {
         if (admission_pass(waiting_, slot_free, [&](Req* q) { return admit(q, free_slot); }, kMaxBypass,
                            kMaxHeadPasses) > 0)
             progress = true;
-        if (stop_ && waiting_.empty() && inflight_ == 0) break;
-        if (!progress) {
-            if (inflight_ > 0) {
-                lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
-                lk.lock();
-            } else {
-                cv_.wait_for(lk, std::chrono::milliseconds(5));
-            }
-        }
+        if (stopping && waiting_.empty() && inflight_ == 0) break;
+        if (!progress && inflight_ > 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
 

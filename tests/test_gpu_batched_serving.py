@@ -183,12 +183,16 @@ def test_serving_alone_vs_mix_bitwise(S):
             A, B = inputs.normal(n, 50 + i), inputs.normal(n, 90 + i)
             reqs.append((n, prec, dev(A), dev(B), A, B))
         alone = []
+        torch.cuda.synchronize()       # caller-owned operands must be complete before stark_submit
         for n, prec, dA, dB, _, _ in reqs:
             C = torch.empty((n, n), dtype=torch.float32, device="cuda")
             t = S.stark_submit(c, n, prec, S.STARK_DEPTH_AUTO, dA, dB, C, tag=n)
             wait(S, c, [t])
             alone.append(C.cpu().numpy())
         mixC = [torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda") for n, *_ in reqs]
+        # the NaN fills run on torch's stream; the engine's slot streams do not
+        # wait for it, so the fills must be complete before the requests go in
+        torch.cuda.synchronize()
         tickets = [S.stark_submit(c, n, prec, S.STARK_DEPTH_AUTO, dA, dB, C, tag=i)
                    for i, ((n, prec, dA, dB, _, _), C) in enumerate(zip(reqs, mixC))]
         res = wait(S, c, tickets)
@@ -229,6 +233,32 @@ def test_serving_generated_operands_and_checksums(S):
             ref = A.sum(axis=0) @ B.sum(axis=1)
             bound = 1e-4 * n * np.sqrt(n) * n   # n * ||E||_F with ||E||_F <= 1e-4 ||C||_F
             assert abs(alone[seed] - ref) <= bound, (n, alone[seed], ref)
+    finally:
+        S.stark_destroy(c)
+
+
+@pytest.mark.parametrize("n,prec,seed", [(300, 1, 21), (1024, 0, 22), (2000, 3, 23), (777, 17, 24)])
+def test_serving_generated_operands_match_oracle_rows(S, n, prec, seed):
+    """Operands generated on the device from a seed, result into a
+    caller-owned C: sampled rows against the FP64 oracle on the host twin of
+    the generator (Philox4x32-10, bit-identical operands), element by element
+    through the relative Frobenius error of the rows."""
+    c = S.stark_create(0, hbm_budget_bytes=8 << 30, max_slots=2)
+    try:
+        C = torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t = S.stark_submit(c, n, prec, S.STARK_DEPTH_AUTO, C=C, seed=seed, tag=seed)
+        r = wait(S, c, [t])[t]
+        A = inputs.philox_normal(n, 2 * seed)
+        B = inputs.philox_normal(n, 2 * seed + 1)
+        rows = inputs.sample_rows(n, 64, seed)
+        ref = oracle.rows_f64(A, B, rows)
+        got = C.cpu().numpy()[rows].astype(np.float64)
+        d = got - ref
+        err = float(np.sqrt(np.sum(d * d) / np.sum(ref * ref)))
+        print(f"served n={n} prec={prec} depth {r.depth}: rel_frob(64 rows)={err:.3e}")
+        bound = 1.5 * 4.4e-6 * 2 ** r.depth * (2 if prec & 16 else 1) if (prec & 15) == 1 else 1e-5
+        assert np.all(np.isfinite(got)) and err <= bound
     finally:
         S.stark_destroy(c)
 
