@@ -8,12 +8,10 @@ load lazily so the generators can be used without the GPU library.
 """
 import importlib
 
-__all__ = ["stark", "inputs", "Stark"]
+__all__ = ["stark", "inputs"]
 
 
 def __getattr__(name):
     if name in ("stark", "inputs", "build"):
         return importlib.import_module(f"{__name__}.{name}")
-    if name == "Stark":
-        return importlib.import_module(f"{__name__}.api").Stark
     raise AttributeError(name)

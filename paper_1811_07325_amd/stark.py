@@ -13,8 +13,10 @@ import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # STARK_LIBRARY selects another build of the same library (e.g. a different
-# leaf-GEMM configuration); by default the in-tree libstark.so.
-LIB_PATH = os.environ.get("STARK_LIBRARY") or os.path.join(_HERE, "libstark.so")
+# leaf-GEMM configuration); by default the in-tree libstark.so.  The tests
+# refuse to run with it set, and the benchmark reports the path it loaded.
+DEFAULT_LIB_PATH = os.path.join(_HERE, "libstark.so")
+LIB_PATH = os.environ.get("STARK_LIBRARY") or DEFAULT_LIB_PATH
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "stark.h")
 
 STARK_OK = 0
