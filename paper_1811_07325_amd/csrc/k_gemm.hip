@@ -20,6 +20,8 @@
 // loop is remapped so that the blocks of one XCD (blockIdx mod 8) work on
 // consecutive tiles, and tiles inside a leaf are visited in groups of 8 tile
 // rows so the A and B panels in flight are shared through that XCD's L2.
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -265,9 +267,201 @@ __device__ __forceinline__ void gemm16_lds(Src src, int64_t total_tiles) {
 }
 
 
+// ---------------------------------------------------------------------------
+// Two-plane, 256 x 256 leaf GEMM with the eight waves in two groups that
+// take turns on the matrix cores ("ping-pong").  Group g = w / 4 owns output
+// rows 128 g .. 128 g + 127 and holds one wave on each SIMD (waves w and
+// w + 4 share a SIMD).  A K step of a group is two phases separated by
+// workgroup barriers: a read phase (all operand fragments of the step from
+// LDS into registers) and a compute phase (its 96 MFMAs from registers).
+// Group 1 runs one phase behind group 0, so while one wave of a SIMD issues
+// MFMAs the other reads LDS and issues the global->LDS copies: the matrix
+// core does not wait for LDS reads at step boundaries.  LDS holds two
+// stages; stage s of step k is read in phases 2k (group 0) and 2k + 1
+// (group 1), so the copies of step k + 1 are issued in phase 2k, when its
+// stage (that of step k - 1) is free, and waited for before phase 2k + 2;
+// group 0 issues all of them, so both groups run the same loop.
+// Each output accumulates the same MFMAs in the same order as gemm16_lds, so
+// both give identical results.
+// ---------------------------------------------------------------------------
+// A wave-uniform address held in scalar registers: readfirstlane is opaque
+// to the compiler, so a per-lane offset added afterwards stays a 32-bit
+// vector offset (the load's scalar-base form) instead of the compiler
+// hoisting (uniform part + lane part) of every load into vector registers.
+__device__ __forceinline__ const char* scalar_ptr(const void* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<const char*>(((uint64_t)hi << 32) | lo);
+}
+
+#ifndef STK_PINGPONG
+#define STK_PINGPONG 1
+#endif
+
+template <class Src, bool F16>
+__device__ __forceinline__ void gemm16_pingpong(Src src, int64_t total_tiles) {
+    using VT = typename Op16<F16>::T;
+    using Cfg = BigCfg<2>;
+    constexpr int P = 2;
+    constexpr int BM = Cfg::BM, BN = Cfg::BN, NW = Cfg::NW, WAVES_N = Cfg::WAVES_N;
+    static_assert(Cfg::STAGES == 2 && BM == 256 && BN == 256 && NW == 8 && Cfg::WAVES_M == 2,
+                  "two groups of four waves, two stages");
+    constexpr int BK = 32, KC = BK / 8;
+    constexpr int ROWS = BM + BN;
+    constexpr int UNITS = P * ROWS * KC;
+    constexpr int GA = BM / 16, GB = BN / 16;
+    static_assert(kBlkRows == 16 && kBlkK == BK, "operand layout must match the K step");
+    constexpr int WM = BM / Cfg::WAVES_M, WN = BN / WAVES_N, TM = WM / 16, TN = WN / 16;
+    __shared__ __attribute__((aligned(16))) uint4 lds[2][UNITS];
+
+    // the wave index is uniform across a wave: readfirstlane lets the
+    // compiler keep it, and the copies' base addresses, in scalar registers
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int grp = w / WAVES_N, wn = w % WAVES_N;     // group = wave row of the tile
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t G = gridDim.x;
+    const int64_t slot = xcd_slot(blockIdx.x, G);
+
+    for (int64_t t = slot; t < total_tiles; t += G) {
+        int64_t local;
+        const ProbDesc& d = src.get(src.locate(t, local));
+        const int64_t L = d.leaf, LL = L * L;
+        const int64_t tm_cnt = L / BM, tn_cnt = L / BN, tpl = tm_cnt * tn_cnt;
+        const int64_t leaf = local / tpl;
+        int64_t tm, tn;
+        tile_coords(local - leaf * tpl, tm_cnt, tn_cnt, tm, tn);
+        const uint16_t* Ah = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_a + leaf * P * LL;
+        const uint16_t* Bh = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_b + leaf * P * LL;
+        float* Cp;
+        int64_t ldc;
+        if (d.depth == 0) { Cp = d.C; ldc = d.n; }
+        else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
+        const bool crop = d.depth == 0 && d.bounded0;
+        const Unscale unscale = unscale_of(d);
+        const int64_t m0 = tm * BM, n0 = tn * BN;
+
+        // direct copies, as in gemm16_lds, by the four waves of group 0:
+        // block row g of a side of plane p (one contiguous 1 KB block per K
+        // step) is moved by wave g % 4
+        constexpr int NL = NW / 2;
+        const int64_t blocks_k = L >> 5;
+        const uint16_t* a_blk = Ah + ((m0 >> 4) * blocks_k << 9);
+        const uint16_t* b_blk = Bh + ((n0 >> 4) * blocks_k << 9);
+        const uint32_t lane_bytes = 16 * lane;
+        auto issue = [&](int stage, int64_t k0) {
+            const int64_t kb = (k0 >> 5) << 9;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int r = 0; r < GA / NL; ++r) {
+                    const int g = w + NL * r;
+                    __builtin_amdgcn_global_load_lds(
+                        scalar_ptr(a_blk + p * LL + ((int64_t)g * blocks_k << 9) + kb) + lane_bytes,
+                        (lds_void_t*)&lds[stage][(p * ROWS + 16 * g) * KC], 16, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < GB / NL; ++r) {
+                    const int g = w + NL * r;
+                    __builtin_amdgcn_global_load_lds(
+                        scalar_ptr(b_blk + p * LL + ((int64_t)g * blocks_k << 9) + kb) + lane_bytes,
+                        (lds_void_t*)&lds[stage][(p * ROWS + BM + 16 * g) * KC], 16, 0, 0);
+                }
+            }
+        };
+
+
+        f32x4 acc[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        VT a[TM][P], b[TN][P];
+
+        // read phase: every fragment of step kt into registers
+        auto read_frags = [&](int64_t kt) {
+            const uint4* sl = lds[kt & 1];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int row = BM + wn * WN + 16 * j + li;
+                    b[j][p] = __builtin_bit_cast(VT, sl[(p * ROWS + row) * KC + (lg ^ blk_swz(row))]);
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int row = grp * WM + 16 * i + li;
+                    a[i][p] = __builtin_bit_cast(VT, sl[(p * ROWS + row) * KC + (lg ^ blk_swz(row))]);
+                }
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // the stage may be refilled two phases on
+        };
+        // compute phase: the step's MFMAs, in the order of gemm16_lds
+        auto compute = [&] {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int q = 0; q < SplitProducts<P>::count; ++q)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = Op16<F16>::mfma(a[i][SplitProducts<P>::a(q)], b[j][SplitProducts<P>::b(q)],
+                                                    acc[i][j]);
+        };
+        // Phase boundary: a bare workgroup barrier (no memory fence, which
+        // would wait for the copies in flight), nothing scheduled across it.
+        // Every LDS read before it has completed (read_frags waits), and a
+        // stage's copies are waited for explicitly before the barrier that
+        // precedes its first read.
+        auto boundary = [] {
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+        };
+
+        const int64_t KT = L / BK;
+        // Group 0 moves every operand block (16 copies per wave and step),
+        // group 1 none, so the two groups run the same loop; group 1 enters
+        // it one phase later (one extra barrier before, one fewer after).
+        if (grp == 0) {
+            issue(0, 0);
+            wait_vmcnt<0>();
+        }
+        boundary();
+        if (grp == 1) boundary();
+        for (int64_t kt = 0; kt < KT; ++kt) {
+            // group 0: phase 2 kt (group 1 computes step kt - 1 meanwhile)
+            if (grp == 0 && kt + 1 < KT) issue((int)((kt + 1) & 1), (kt + 1) * BK);
+            read_frags(kt);
+            boundary();
+            // group 0: phase 2 kt + 1 (group 1 reads step kt meanwhile)
+            compute();
+            if (grp == 0) wait_vmcnt<0>();                     // step kt + 1 is in LDS
+            boundary();
+        }
+        if (grp == 0) boundary();                               // phase 2 KT: group 1 computes step KT - 1
+
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = m0 + grp * WM + 16 * i + 4 * lg + r;
+                    const int64_t col = n0 + wn * WN + 16 * j + li;
+                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = unscale(acc[i][j][r]);
+                }
+    }
+}
+
+
 template <class Src, int P, bool F16>
 __global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_t total_tiles) {
-    gemm16_lds<BigCfg<P>, Src, P, F16>(src, total_tiles);
+    // the ping-pong kernel for single problems (with a device problem table
+    // its extra descriptor registers would spill)
+    if constexpr (P == 2 && STK_PINGPONG && std::is_same<Src, OneProb>::value)
+        gemm16_pingpong<Src, F16>(src, total_tiles);
+    else
+        gemm16_lds<BigCfg<P>, Src, P, F16>(src, total_tiles);
 }
 template <class Src, int P, bool F16>
 __global__ __launch_bounds__(MidCfg<P>::NT) void k_gemm_bf16_mid(Src src, int64_t total_tiles) {
