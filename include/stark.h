@@ -139,6 +139,25 @@ int stark_model_depth(int64_t n, stark_precision p);
 stark_status stark_gemm(stark_ctx* ctx, const float* A, const float* B, float* C, int64_t n,
                         int depth, stark_precision p, void* stream);
 
+/* For callers that cannot allocate device memory (work under stream capture,
+ * serving loops or harnesses that forbid the allocator): stark_gemm without a
+ * context.  Same arguments, layout, arithmetic and result as stark_gemm at
+ * the same depth; depth = STARK_DEPTH_AUTO takes stark_model_depth(n, p).  It
+ * calls no allocator: the intermediates of the multiply live in a fixed
+ * device array of STARK_NOALLOC_SCRATCH_BYTES per GPU, part of the library's
+ * device code (held by every GPU the library runs on until the process ends).
+ * A plan needing more (see stark_workspace_size: e.g. n <= 1024 fits up to
+ * depth 2, n = 2048 at depth 0) is refused with ENOMEM before anything is
+ * enqueued.  Runs on the current device and enqueues on `stream`.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on the device
+ * (other streams, other threads) race and corrupt each other's results --
+ * order them (one stream, or events).  Nothing in the array needs clearing
+ * between calls; it keeps the last call's intermediates.  Errors: EINVAL,
+ * ENOMEM, EUNSUPPORTED, EDEVICE. */
+#define STARK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+stark_status stark_gemm_noalloc(const float* A, const float* B, float* C, int64_t n, int depth,
+                                stark_precision p, void* stream);
+
 /* Rectangular product C (m x n) = A (m x k) B (k x n): row-major binary32
  * with leading dimensions k, n and n, 16-byte aligned base pointers (rows
  * need not be aligned).  depth = STARK_DEPTH_AUTO takes

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstark.so")
 
 SOURCES = ["k_stream.hip", "k_gemm.hip", "k_check.hip", "plan.cpp", "stark_api.cpp",
-           "batched.cpp", "tuner.cpp", "serving.cpp", "rect.cpp"]
+           "batched.cpp", "tuner.cpp", "serving.cpp", "rect.cpp", "noalloc.cpp"]
 
 ARCH = os.environ.get("STARK_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdarg>
 #include <list>
@@ -89,6 +90,8 @@ namespace stk {
 
 // Enqueue one multiply (all phases in `mask`) eagerly on `st`.
 stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st);
+// The same without a context: num_cu compute units on the current device.
+stark_status run_plan_cu(int num_cu, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st);
 
 // Enqueue one multiply through the graph cache (eager on first sight).
 stark_status run_cached(stark_ctx* ctx, const Plan& p, const float* A, const float* B, float* C,
@@ -121,6 +124,7 @@ stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C
 
 // Leaf-GEMM grid for `tiles` tiles: resident blocks per CU x CUs, capped.
 int gemm_grid(stark_ctx* ctx, int planes, int tile, int64_t tiles);
+int gemm_grid_cu(int num_cu, int planes, int tile, int64_t tiles);
 
 // Batched (batched.cpp).
 stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, const float* const* B,

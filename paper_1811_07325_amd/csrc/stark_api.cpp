@@ -36,6 +36,10 @@ void set_error(const char* fmt, ...) {
 const char* get_error() { return t_err.c_str(); }
 
 int gemm_grid(stark_ctx* ctx, int planes, int tile, int64_t tiles) {
+    return gemm_grid_cu(ctx->num_cu, planes, tile, tiles);
+}
+
+int gemm_grid_cu(int num_cu, int planes, int tile, int64_t tiles) {
     // resident blocks per CU of every (planes, tile) variant, queried once
     // (thread-safe static initialisation; the serving thread calls this too)
     struct Occ {
@@ -49,11 +53,15 @@ int gemm_grid(stark_ctx* ctx, int planes, int tile, int64_t tiles) {
     static const Occ occ;
     const int pi = planes == 0 ? 0 : planes == 2 ? 1 : 2;
     const int ti = tile == 128 ? 0 : tile == 64 ? 1 : 2;
-    const int64_t g = (int64_t)ctx->num_cu * occ.v[pi][ti];
+    const int64_t g = (int64_t)num_cu * occ.v[pi][ti];
     return (int)std::min<int64_t>(g, tiles);
 }
 
 stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st) {
+    return run_plan_cu(ctx->num_cu, p, d, mask, st);
+}
+
+stark_status run_plan_cu(int num_cu, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st) {
     const OneProb src{d};
     if (mask & STARK_PHASE_DIVIDE) {
         if (p.pad_a >= 0) STK_HIP(launch_pad(src, blocks_pad(d), st));
@@ -67,7 +75,7 @@ stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned
     }
     if (mask & STARK_PHASE_LEAF) {
         const int64_t tiles = pow7(p.depth) * gemm_tiles_per_leaf(p.planes, p.tile, p.leaf);
-        STK_HIP(launch_gemm(src, p.planes, p.tile, d.fp16 != 0, tiles, gemm_grid(ctx, p.planes, p.tile, tiles), st));
+        STK_HIP(launch_gemm(src, p.planes, p.tile, d.fp16 != 0, tiles, gemm_grid_cu(num_cu, p.planes, p.tile, tiles), st));
     }
     if (mask & STARK_PHASE_COMBINE) {
         int l = p.depth - 1;

@@ -122,6 +122,7 @@ def _load() -> ctypes.CDLL:
                         ctypes.POINTER(I), P], I),
         "stark_gemm_rect": ([P, P, P, P, I64, I64, I64, I, I, P], I),
         "stark_rect_block_edge": ([I64, I64, I64, I], I64),
+        "stark_gemm_noalloc": ([P, P, P, I64, I, I, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -226,6 +227,19 @@ def stark_submit(ctx, n: int, precision: int, depth: int = STARK_DEPTH_AUTO, A=N
     t = ctypes.c_uint64()
     _check("stark_submit", _lib.stark_submit(ctx, ctypes.byref(r), ctypes.byref(t)))
     return t.value
+
+
+STARK_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def stark_gemm_noalloc(A, B, C, n: int, depth: int, precision: int, stream=None) -> None:
+    _check("stark_gemm_noalloc", _lib.stark_gemm_noalloc(_ptr(A), _ptr(B), _ptr(C), n, depth, precision,
+                                                         _stream(stream)))
+
+
+def stark_gemm_noalloc_status(A, B, C, n: int, depth: int, precision: int, stream=None) -> int:
+    """Status of stark_gemm_noalloc without raising."""
+    return _lib.stark_gemm_noalloc(_ptr(A), _ptr(B), _ptr(C), n, depth, precision, _stream(stream))
 
 
 def stark_poll(ctx, ticket: int):
