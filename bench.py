@@ -70,6 +70,8 @@ def parse():
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--batched-only", action="store_true",
                    help="only run the batched workload, print its JSON object and exit")
+    p.add_argument("--serving-only", action="store_true",
+                   help="only run the serving workload, print its JSON object and exit")
     p.add_argument("--serving-requests", type=int, default=2000)
     p.add_argument("--rows", type=int, default=256, help="sampled rows for the error check")
     p.add_argument("--cpu-rows", type=int, default=1024,
@@ -297,6 +299,9 @@ def main() -> int:
     st = torch.cuda.Stream(device=dev)
     if args.batched_only:
         print(json.dumps(run_batched(S, torch, st)), flush=True)
+        return 0
+    if args.serving_only:
+        print(json.dumps(run_serving(S, count=args.serving_requests)), flush=True)
         return 0
 
     log(f"generating inputs n={n}")

@@ -89,9 +89,14 @@ struct stark_ctx {
 namespace stk {
 
 // Enqueue one multiply (all phases in `mask`) eagerly on `st`.
-stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st);
+// persistent = false launches the leaf GEMM with one workgroup per tile
+// instead of one resident wave of workgroups (served requests: the GPU is
+// shared with other streams).  Results are the same either way.
+stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st,
+                      bool persistent = true);
 // The same without a context: num_cu compute units on the current device.
-stark_status run_plan_cu(int num_cu, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st);
+stark_status run_plan_cu(int num_cu, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st,
+                         bool persistent = true);
 
 // Enqueue one multiply through the graph cache (eager on first sight).
 stark_status run_cached(stark_ctx* ctx, const Plan& p, const float* A, const float* B, float* C,

@@ -131,6 +131,10 @@ private:
     size_t max_bytes_ = 0, used_pub_ = 0, waiting_pub_ = 0;
     int inflight_pub_ = 0, max_inflight_ = 0;
     int64_t fault_tag_ = -1;   // STARK_FAULT_INJECT: tag of a request made to fail
+    // leaf GEMMs of served requests launch one workgroup per tile, so that a
+    // large request's GEMM does not hold every CU until it ends
+    // (STARK_SERVE_PERSISTENT=1: the persistent grid of stark_gemm)
+    bool persistent_ = false;
 };
 
 double now_us();

@@ -82,6 +82,8 @@ Engine::Engine(stark_ctx* ctx, size_t budget, int slots, hipError_t* err) : ctx_
         if ((*err = hipMalloc(reinterpret_cast<void**>(&s.partials), 257 * sizeof(double))) != hipSuccess) return;
     }
     if (const char* f = std::getenv("STARK_FAULT_INJECT")) fault_tag_ = std::atoll(f);
+    if (const char* f = std::getenv("STARK_SERVE_PERSISTENT")) persistent_ = std::atoi(f) != 0;
+
     thread_ = std::thread([this] { loop(); });
 }
 
@@ -266,7 +268,8 @@ bool Engine::admit(Req* q, int si) {
         e = hipEventRecord(s.ev0, s.stream);
         if (e == hipSuccess && q->gen) e = launch_generate_normal(const_cast<float*>(A), q->r.n * q->r.n, 2 * q->r.seed, s.stream);
         if (e == hipSuccess && q->gen) e = launch_generate_normal(const_cast<float*>(B), q->r.n * q->r.n, 2 * q->r.seed + 1, s.stream);
-        if (e == hipSuccess) rc = run_plan(ctx_, q->plan, make_desc(q->plan, A, B, C, ws), STARK_PHASE_ALL, s.stream);
+        if (e == hipSuccess)
+            rc = run_plan(ctx_, q->plan, make_desc(q->plan, A, B, C, ws), STARK_PHASE_ALL, s.stream, persistent_);
         if (e == hipSuccess && rc == STARK_OK && q->own_c) {
             e = launch_sum_f64(C, q->r.n * q->r.n, s.partials, s.partials + 256, s.stream);
             if (e == hipSuccess)

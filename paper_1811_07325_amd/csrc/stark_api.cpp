@@ -57,11 +57,13 @@ int gemm_grid_cu(int num_cu, int planes, int tile, int64_t tiles) {
     return (int)std::min<int64_t>(g, tiles);
 }
 
-stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st) {
-    return run_plan_cu(ctx->num_cu, p, d, mask, st);
+stark_status run_plan(stark_ctx* ctx, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st,
+                      bool persistent) {
+    return run_plan_cu(ctx->num_cu, p, d, mask, st, persistent);
 }
 
-stark_status run_plan_cu(int num_cu, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st) {
+stark_status run_plan_cu(int num_cu, const Plan& p, const ProbDesc& d, unsigned mask, hipStream_t st,
+                         bool persistent) {
     const OneProb src{d};
     if (mask & STARK_PHASE_DIVIDE) {
         if (p.pad_a >= 0) STK_HIP(launch_pad(src, blocks_pad(d), st));
@@ -75,7 +77,12 @@ stark_status run_plan_cu(int num_cu, const Plan& p, const ProbDesc& d, unsigned 
     }
     if (mask & STARK_PHASE_LEAF) {
         const int64_t tiles = pow7(p.depth) * gemm_tiles_per_leaf(p.planes, p.tile, p.leaf);
-        STK_HIP(launch_gemm(src, p.planes, p.tile, d.fp16 != 0, tiles, gemm_grid_cu(num_cu, p.planes, p.tile, tiles), st));
+        // persistent: one resident wave of workgroups loops over the tiles;
+        // otherwise one workgroup per tile (capped), so that workgroups
+        // retire throughout the launch and kernels of other streams get CUs
+        const int grid = persistent ? gemm_grid_cu(num_cu, p.planes, p.tile, tiles)
+                                    : (int)std::min<int64_t>(tiles, int64_t(1) << 30);
+        STK_HIP(launch_gemm(src, p.planes, p.tile, d.fp16 != 0, tiles, grid, st));
     }
     if (mask & STARK_PHASE_COMBINE) {
         int l = p.depth - 1;

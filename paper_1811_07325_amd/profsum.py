@@ -9,6 +9,8 @@
   runs, each scaled by what the same counter reads for a plain copy of known
   size (the counters report KiB per dispatch);
 * `mfma_md`: matrix-core busy fraction, hardware flops and clock of a kernel;
+* `stream_overlap` / `overlap_md`: the share of GPU-busy time during which
+  kernels of two or more streams run at once (served requests);
 * `source_digest`: SHA-256 of the kernel source the counters were taken on,
   so a reader can tell when they are stale.
 
@@ -19,6 +21,7 @@ Command line:
   python -m paper_1811_07325_amd.profsum mfma <counters.csv> <kernel substring> <title> <command lines...>
   python -m paper_1811_07325_amd.profsum table <copy_fetch.csv> <copy_write.csv> <copy_bytes>
       <run_fetch.csv> <run_write.csv> <kernel,substrings> <title> <command lines...>
+  python -m paper_1811_07325_amd.profsum overlap <kernel_trace.csv> <title> <command lines...>
 """
 from __future__ import annotations
 
@@ -130,6 +133,48 @@ def mfma_md(path: str, name_part: str, simds: int, xccs: int, title: str, comman
     return "\n".join(out) + "\n"
 
 
+def stream_overlap(path: str) -> dict:
+    """Concurrency of kernels from different streams in a --kernel-trace
+    csv: sweeping the dispatch start / end times, the share of the time with
+    at least one kernel running during which kernels of k or more distinct
+    streams run at once (k = 2, 3, 4), and the busy time itself."""
+    ev = []
+    for r in csv.DictReader(open(path)):
+        s, e, sid = int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Stream_Id"]
+        if e > s:
+            ev.append((s, 1, sid))
+            ev.append((e, -1, sid))
+    ev.sort(key=lambda x: (x[0], x[1]))
+    active: dict[str, int] = {}
+    busy = 0
+    at_least = {2: 0, 3: 0, 4: 0}
+    last = None
+    for t, d, sid in ev:
+        if last is not None and active:
+            span = t - last
+            busy += span
+            for k in at_least:
+                if len(active) >= k:
+                    at_least[k] += span
+        last = t
+        active[sid] = active.get(sid, 0) + d
+        if active[sid] == 0:
+            del active[sid]
+    return {"busy_ms": busy / 1e6, **{f"frac_ge{k}_streams": (v / busy if busy else 0.0) for k, v in at_least.items()},
+            "streams": len({x[2] for x in ev}), "dispatches": len(ev) // 2}
+
+
+def overlap_md(path: str, title: str, commands: list[str]) -> str:
+    o = stream_overlap(path)
+    out = [f"# {title}", "", "Commands (from the repository root, on one MI355X):", "", "```"] + commands + [
+        "```", "", "| quantity | value |", "|---|---:|",
+        f"| kernel dispatches | {o['dispatches']} |", f"| streams with kernels | {o['streams']} |",
+        f"| GPU busy time (at least one kernel running) | {o['busy_ms']:.1f} ms |"]
+    for k in (2, 3, 4):
+        out.append(f"| share of busy time with kernels of >= {k} streams running | {o[f'frac_ge{k}_streams']:.3f} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv: list[str]) -> int:
     if argv[0] == "stats":
         sys.stdout.write(kernel_stats_md(argv[1], argv[2], argv[3]))
@@ -145,6 +190,9 @@ def main(argv: list[str]) -> int:
     if argv[0] == "mfma":
         path, part, title = argv[1:4]
         sys.stdout.write(mfma_md(path, part, 1024, 8, title, argv[4:]))
+        return 0
+    if argv[0] == "overlap":
+        sys.stdout.write(overlap_md(argv[1], argv[2], argv[3:]))
         return 0
     if argv[0] == "table":
         cfe, cwr, cb, rfe, rwr, kernels, title = argv[1:8]
