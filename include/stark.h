@@ -84,7 +84,19 @@ typedef enum {
      * T2 = B22-T1, T3 = B22-B12, T4 = T2-B21; M1..M7 = A11 B11, A12 B21,
      * S4 B22, A22 T4, S1 T1, S2 T2, S3 T3; C11 = M1+M2, U2 = M1+M6,
      * U3 = U2+M7, C12 = (U2+M5)+M3, C21 = U3-M4, C22 = U3+M5). */
-    STARK_WINOGRAD = 16
+    STARK_WINOGRAD = 16,
+    /* Flag: binary32 leaves formed inside the leaf GEMM.  With Algorithm 1,
+     * binary32 leaves on the 256-wide leaf-GEMM tiles, depth >= 1 (and not
+     * depth 1 of a padded size) the leaf GEMM forms the last level's operand
+     * sums itself from the quadrants of the level above while it copies its
+     * tiles into LDS (the fusion of "Strassen's Algorithm Reloaded", Huang et
+     * al., SC'16), so the divide stops one level early and the workspace
+     * shrinks by the last level's operand blocks; the result is the same bit
+     * for bit.  Elsewhere the flag is ignored (stark_plan_info reports
+     * whether it applies).  Off by default: the leaf GEMM then moves twice
+     * the operand bytes for five of the seven products and runs slower than
+     * the stored-operand path plus the divide it saves. */
+    STARK_FUSED = 32
 } stark_precision;
 #define STARK_PRECISION_MASK 15
 
@@ -328,6 +340,8 @@ typedef struct {
      * (times 1, 3, 6 or 3 products for FP32, BF16X3, BF16X6, FP16X3). */
     double divide_bytes, split_bytes, combine_bytes, leaf_flops, mfma_flops;
     int variant;              /* 0: Algorithm 1, 1: Winograd's variant           */
+    int fused;                /* 1: the leaf GEMM forms the last level's operands
+                                 (binary32; see STARK_FUSED)                       */
 } stark_plan_desc;
 
 stark_status stark_plan_info(int64_t n, int depth, stark_precision p, stark_plan_desc* out);

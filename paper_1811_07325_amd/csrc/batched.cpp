@@ -28,6 +28,7 @@ struct BatchLaunch {
     LaunchKind kind;
     int level;      // divide / combine level
     int tile;       // gemm tile class
+    bool fused;     // gemm: binary32 leaves formed in the GEMM (plans with fuse)
     int64_t total;  // blocks (or tiles for the gemm)
     size_t prefix;  // index of the prefix array in the device buffer (in int64 units)
 };
@@ -101,7 +102,7 @@ stark_status enqueue(stark_ctx* ctx, const BatchEntry& e, hipStream_t st) {
             case kSplit: STK_HIP(launch_split(src, e.planes, e.variant, l.total, st)); break;
             case kGemm:
                 STK_HIP(launch_gemm(src, e.planes, l.tile, e.fp16, l.total,
-                                    gemm_grid(ctx, e.planes, l.tile, l.total), st));
+                                    gemm_grid(ctx, e.planes, l.tile, l.total), st, l.fused));
                 break;
             case kCombine: STK_HIP(launch_combine(src, l.level, e.variant, l.total, st)); break;
             case kCombine2: STK_HIP(launch_combine2(src, l.level, e.variant, l.total, st)); break;
@@ -138,6 +139,7 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
     for (const Plan& p : plans) {
         key.plans.push_back(p.depth);
         key.plans.push_back(p.tile);
+        key.plans.push_back(p.fuse ? 1 : 0);
     }
     key.precision = precision;
     key.ws = ctx->ws;
@@ -162,8 +164,8 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
         for (int i = 0; i < count; ++i)
             descs[i] = make_desc(plans[i], A[i], B[i], C[i], static_cast<char*>(ctx->ws) + off[i]);
         std::vector<int64_t> pre;
-        auto add_launch = [&](LaunchKind kind, int level, int tile, auto blocks_of) {
-            BatchLaunch l{kind, level, tile, 0, pre.size()};
+        auto add_launch = [&](LaunchKind kind, int level, int tile, auto blocks_of, bool fused = false) {
+            BatchLaunch l{kind, level, tile, fused, 0, pre.size()};
             int64_t acc = 0;
             for (int i = 0; i < count; ++i) {
                 pre.push_back(acc);
@@ -188,11 +190,15 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
             add_launch(kScaleExp, 0, 0, [&](int) { return (int64_t)1; });
         }
         if (e.planes > 0) add_launch(kSplit, 0, 0, [&](int i) { return blocks_split(descs[i]); });
+        // one launch per tile class (the 256-wide binary32 class: one for the
+        // problems whose leaf operands the GEMM forms, one for the others)
         for (int tile : {256, 128, 64})
-            add_launch(kGemm, 0, tile, [&](int i) {
-                const Plan& p = plans[i];
-                return p.tile == tile ? pow7(p.depth) * gemm_tiles_per_leaf(p.planes, tile, p.leaf) : (int64_t)0;
-            });
+            for (bool fused : {true, false})
+                add_launch(kGemm, 0, tile, [&](int i) {
+                    const Plan& p = plans[i];
+                    return p.tile == tile && p.fuse == fused
+                               ? pow7(p.depth) * gemm_tiles_per_leaf(p.planes, tile, p.leaf) : (int64_t)0;
+                }, fused);
         // per problem: the two deepest levels in one pass, then one level at a time
         for (int l = max_depth - 1; l >= 0; --l) {
             add_launch(kCombine2, l, 0, [&](int i) {

@@ -132,6 +132,39 @@ __device__ __forceinline__ void wait_vmcnt() {
     asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
+// LDS stages of step k and of step k + STAGES - 1 (the one refilled while
+// step k is read).  With two stages the indices are k & 1 and (k & 1) ^ 1,
+// a form the compiler's alias analysis can tell apart: it then does not make
+// the LDS reads of step k wait for the copies into the other stage it has
+// just issued (with k % 3 and (k + 2) % 3 it cannot, and waits for them --
+// the whole load latency, every step).
+template <int STAGES>
+__device__ __forceinline__ int stage_of(int64_t k) {
+    if constexpr (STAGES == 2) return (int)(k & 1);
+    else return (int)(k % STAGES);
+}
+template <int STAGES>
+__device__ __forceinline__ int refill_stage_of(int64_t k) {
+    if constexpr (STAGES == 2) return (int)(k & 1) ^ 1;
+    else return (int)((k + STAGES - 1) % STAGES);
+}
+
+// Workgroup barrier between LDS stages of a pipelined K loop: this wave's
+// LDS reads have completed, then a bare s_barrier.  __syncthreads() would add
+// a workgroup memory fence, which waits for every vector-memory operation of
+// the wave -- the direct copies of the later stages, still in flight, too --
+// and so shortens the pipeline to one stage of look-ahead.  The caller waits
+// for the copies of the stage about to be read (wait_vmcnt) before this.
+// The memory clobbers and scheduling barriers keep every LDS access on its
+// side of the barrier.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+}
+
 // ---------------------------------------------------------------------------
 // bf16-split leaf GEMM for large leaves.  Operand tiles go from global
 // memory straight into LDS (global_load_lds_dwordx4: each lane deposits 16
@@ -224,12 +257,15 @@ __device__ __forceinline__ void gemm16_lds(Src src, int64_t total_tiles) {
             if (kt + STAGES - 2 < KT) wait_vmcnt<LPS * (STAGES - 2)>();
             else wait_vmcnt<0>();
             __syncthreads();     // every wave's part of step kt landed; step kt-1's reads are done
-            if (kt + STAGES - 1 < KT) issue((int)((kt + STAGES - 1) % STAGES), (kt + STAGES - 1) * BK);
             // three planes: the compiler's DS / MFMA interleaving strategy 1
             // (measured 4 % faster there, 3 % slower with two planes)
             if constexpr (P == 3) __builtin_amdgcn_iglp_opt(1);
-            const uint4* sl = lds[kt % STAGES];
-            VT b[P][TN];
+            // Every fragment of the step is read before the copies of a later
+            // step are issued: the compiler cannot tell the stages apart and
+            // makes LDS reads wait for every copy issued before them, which
+            // would stall each step for the whole latency of its new copies.
+            const uint4* sl = lds[stage_of<STAGES>(kt)];
+            VT b[P][TN], a[TM][P];
 #pragma unroll
             for (int p = 0; p < P; ++p)
 #pragma unroll
@@ -240,16 +276,19 @@ __device__ __forceinline__ void gemm16_lds(Src src, int64_t total_tiles) {
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
                 const int row = wm * WM + 16 * i + li;
-                VT a[P];
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    a[p] = __builtin_bit_cast(VT, sl[(p * ROWS + row) * KC + (lg ^ blk_swz(row))]);
+                    a[i][p] = __builtin_bit_cast(VT, sl[(p * ROWS + row) * KC + (lg ^ blk_swz(row))]);
+            }
+            if (kt + STAGES - 1 < KT) issue(refill_stage_of<STAGES>(kt), (kt + STAGES - 1) * BK);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int q = 0; q < SplitProducts<P>::count; ++q)
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
-                        acc[i][j] = Op16<F16>::mfma(a[SplitProducts<P>::a(q)], b[SplitProducts<P>::b(q)][j], acc[i][j]);
-            }
+                        acc[i][j] = Op16<F16>::mfma(a[i][SplitProducts<P>::a(q)], b[SplitProducts<P>::b(q)][j],
+                                                    acc[i][j]);
         }
         __syncthreads();         // the next tile's first loads overwrite the stages
 
@@ -497,26 +536,74 @@ struct F32CfgT {
     static constexpr int BM = BM_, BN = BN_, WAVES_M = WAVES_M_, WAVES_N = WAVES_N_, STAGES = STAGES_;
     static constexpr int NW = WAVES_M * WAVES_N, NT = 64 * NW;
 };
-using F32BigCfg = F32CfgT<256, 256, 2, 4, 3>;    // 8 waves of 128 x 64, 96 KB LDS
+#ifndef STK_F32_STAGES
+#define STK_F32_STAGES 3
+#endif
+using F32BigCfg = F32CfgT<256, 256, 2, 4, STK_F32_STAGES>;   // 8 waves of 128 x 64, 32 KB LDS per stage
+using F32FusedCfg = F32CfgT<256, 256, 2, 4, 2>;  // the same with fused leaf operands, 128 KB LDS
 using F32MidCfg = F32CfgT<128, 128, 2, 2, 3>;    // 4 waves of 64 x 64, 48 KB LDS
 using F32SmallCfg = F32CfgT<64, 64, 2, 2, 3>;    // 4 waves of 32 x 32, 24 KB LDS
 static_assert(F32BigCfg::NT == kF32BigThreads, "thread count of the 256-wide kernel");
 
+// Leaf operand of leaf `leaf` formed inside the binary32 leaf GEMM (plans
+// with fused leaves): the leaf is child c = leaf mod 7 of the level-(depth-1)
+// node leaf / 7, whose operand X (edge 2L, stored by the divide or a view)
+// has quadrants X11, X12, X21, X22 at offsets 0, L, L ld, L ld + L.  The
+// operand is X_q1 (views S3, S4, T2, T5) or X_q1 + X_q2 or X_q1 - X_q2 -- the
+// sums of Algorithm 1 in the order k_divide forms them, so each element is
+// the same binary32 add and the product is bit-identical to the one of the
+// materialised operand.  p2 = nullptr for a view; neg is the sign bit to
+// flip on the second term (x + (-y) is x - y exactly).
+__device__ __forceinline__ void fused_operand(const ProbDesc& d, int side, int64_t leaf, const float*& p1,
+                                              const float*& p2, int64_t& ld, uint32_t& neg) {
+    const float* X;
+    resolve(d, side, d.depth - 1, leaf / 7, X, ld);
+    const int c = (int)(leaf % 7);
+    // per child: 4-bit fields q1 | q2 << 2 | two << 4 | minus << 5 (quadrant q: 0 X11, 1 X12, 2 X21, 3 X22)
+    //   A: S1 = X11+X22, S2 = X21+X22, S3 = X11, S4 = X22, S5 = X11+X12, S6 = X21-X11, S7 = X12-X22
+    //   B: T1 = Y11+Y22, T2 = Y11, T3 = Y12-Y22, T4 = Y21-Y11, T5 = Y22, T6 = Y11+Y12, T7 = Y21+Y22
+    constexpr uint8_t kA[7] = {0 | 3 << 2 | 16, 2 | 3 << 2 | 16, 0, 3, 0 | 1 << 2 | 16, 2 | 0 << 2 | 48,
+                               1 | 3 << 2 | 48};
+    constexpr uint8_t kB[7] = {0 | 3 << 2 | 16, 0, 1 | 3 << 2 | 48, 2 | 0 << 2 | 48, 3, 0 | 1 << 2 | 16,
+                               2 | 3 << 2 | 16};
+    const int code = side ? kB[c] : kA[c];
+    const int64_t L = d.leaf;
+    auto quad = [&](int q) { return X + (q >> 1) * L * ld + (q & 1) * L; };
+    p1 = quad(code & 3);
+    p2 = (code & 16) ? quad((code >> 2) & 3) : nullptr;
+    neg = (code & 32) ? 0x80000000u : 0u;
+}
+
+__device__ __forceinline__ float flip_add(float a, float b, uint32_t neg) {
+    return a + __uint_as_float(__float_as_uint(b) ^ neg);
+}
+__device__ __forceinline__ float4 flip_add(float4 a, float4 b, uint32_t neg) {
+    return make_float4(flip_add(a.x, b.x, neg), flip_add(a.y, b.y, neg), flip_add(a.z, b.z, neg),
+                       flip_add(a.w, b.w, neg));
+}
+
 // One B load of a wave moves 256 consecutive floats of the stage image: 256 /
 // BN k-rows (lane l: k-row l / (BN / 4), chunk l % (BN / 4)).
-template <class Cfg, class Src>
+// FUSE: the leaf operands are formed from the level above (fused_operand):
+// a stage holds both terms of each side, [A1][A2][B1][B2], both copied by
+// direct loads, and the operand reads add them -- once per fragment read, a
+// few adds per matrix-core instruction (16x16x4 binary32 MFMAs are long).
+template <class Cfg, class Src, bool FUSE>
 __device__ __forceinline__ void gemm32_lds(Src src, int64_t total_tiles) {
     constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = 16, NW = Cfg::NW, WAVES_N = Cfg::WAVES_N;
     constexpr int STAGES = Cfg::STAGES;
     constexpr int WM = BM / Cfg::WAVES_M, WN = BN / WAVES_N, TM = WM / 16, TN = WN / 16;
-    constexpr int AU = BM * BK / 4;                    // 16-byte units of A per stage
-    constexpr int UNITS = AU + BK * BN / 4;            // plus B
+    constexpr int AU = BM * BK / 4;                    // 16-byte units of one A term per stage
+    constexpr int BU = BK * BN / 4;                    // of one B term
+    constexpr int A2_OFF = AU;                         // second A term (FUSE)
+    constexpr int B1_OFF = FUSE ? 2 * AU : AU;
+    constexpr int B2_OFF = B1_OFF + BU;
+    constexpr int UNITS = FUSE ? 2 * (AU + BU) : AU + BU;
     constexpr int GA = BM / 16;                        // A blocks of 16 rows per stage
     constexpr int CPR = BN / 4;                        // 16-byte chunks per B k-row
     constexpr int RPL = 64 / CPR;                      // B k-rows per wave load
     constexpr int GB = BK / RPL;                       // B loads per stage
     static_assert(BN >= 64 && GA % NW == 0 && GB % NW == 0, "loads must split evenly over the waves");
-    constexpr int LPS = GA / NW + GB / NW;             // direct loads per lane per stage
     __shared__ __attribute__((aligned(16))) uint4 lds[STAGES][UNITS];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -533,10 +620,16 @@ __device__ __forceinline__ void gemm32_lds(Src src, int64_t total_tiles) {
         const int64_t leaf = local / tpl;
         int64_t tm, tn;
         tile_coords(local - leaf * tpl, tm_cnt, tn_cnt, tm, tn);
-        const float *Ap, *Bp;
+        const float *Ap, *Bp, *Ap2 = nullptr, *Bp2 = nullptr;
         int64_t lda, ldb;
-        resolve(d, 0, d.depth, leaf, Ap, lda);
-        resolve(d, 1, d.depth, leaf, Bp, ldb);
+        uint32_t nega = 0, negb = 0;
+        if constexpr (FUSE) {
+            fused_operand(d, 0, leaf, Ap, Ap2, lda, nega);
+            fused_operand(d, 1, leaf, Bp, Bp2, ldb, negb);
+        } else {
+            resolve(d, 0, d.depth, leaf, Ap, lda);
+            resolve(d, 1, d.depth, leaf, Bp, ldb);
+        }
         float* Cp;
         int64_t ldc;
         if (d.depth == 0) { Cp = d.C; ldc = d.n; }
@@ -550,89 +643,131 @@ __device__ __forceinline__ void gemm32_lds(Src src, int64_t total_tiles) {
         // goes to wave q % NW; lane l fills position l % CPR of k-row
         // RPL q + l / CPR, holding chunk (l % CPR) ^ f32_bswz(k-row).
         const int arow = lane >> 2;
-        const float* a_src = Ap + (m0 + arow) * lda + 4 * ((lane & 3) ^ blk_swz(arow));
+        const int64_t a_lane = (m0 + arow) * lda + 4 * ((lane & 3) ^ blk_swz(arow));
         const int bsub = lane / CPR, bpos = lane % CPR;
-        auto issue = [&](int stage, int64_t k0) {
+
+        // The K loop; TA / TB: the A / B operand has a second term.
+        auto run = [&](auto TA, auto TB) {
+            constexpr bool kTA = decltype(TA)::value, kTB = decltype(TB)::value;
+            constexpr int LPS = (kTA ? 2 : 1) * GA / NW + (kTB ? 2 : 1) * GB / NW;   // loads per lane per stage
+            auto issue = [&](int stage, int64_t k0) {
 #pragma unroll
-            for (int r = 0; r < GA / NW; ++r) {
-                const int g = w + NW * r;
-                __builtin_amdgcn_global_load_lds(a_src + (int64_t)(16 * g) * lda + k0,
-                                                 (lds_void_t*)&lds[stage][64 * g], 16, 0, 0);
-            }
+                for (int r = 0; r < GA / NW; ++r) {
+                    const int g = w + NW * r;
+                    __builtin_amdgcn_global_load_lds(Ap + a_lane + (int64_t)(16 * g) * lda + k0,
+                                                     (lds_void_t*)&lds[stage][64 * g], 16, 0, 0);
+                    if constexpr (kTA)
+                        __builtin_amdgcn_global_load_lds(Ap2 + a_lane + (int64_t)(16 * g) * lda + k0,
+                                                         (lds_void_t*)&lds[stage][A2_OFF + 64 * g], 16, 0, 0);
+                }
 #pragma unroll
-            for (int r = 0; r < GB / NW; ++r) {
-                const int q = w + NW * r, kr = RPL * q + bsub;
-                __builtin_amdgcn_global_load_lds(Bp + (k0 + kr) * ldb + n0 + 4 * (bpos ^ f32_bswz(kr)),
-                                                 (lds_void_t*)&lds[stage][AU + 64 * q], 16, 0, 0);
+                for (int r = 0; r < GB / NW; ++r) {
+                    const int q = w + NW * r, kr = RPL * q + bsub;
+                    const int64_t off = (k0 + kr) * ldb + n0 + 4 * (bpos ^ f32_bswz(kr));
+                    __builtin_amdgcn_global_load_lds(Bp + off, (lds_void_t*)&lds[stage][B1_OFF + 64 * q], 16, 0, 0);
+                    if constexpr (kTB)
+                        __builtin_amdgcn_global_load_lds(Bp2 + off, (lds_void_t*)&lds[stage][B2_OFF + 64 * q], 16,
+                                                         0, 0);
+                }
+            };
+
+            f32x4 acc[TM][TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+            const int64_t KT = L / BK;
+#pragma unroll
+            for (int s = 0; s < STAGES - 1; ++s)
+                if (s < KT) issue(s, s * BK);
+            for (int64_t kt = 0; kt < KT; ++kt) {
+                if (kt + STAGES - 2 < KT) wait_vmcnt<LPS * (STAGES - 2)>();
+                else wait_vmcnt<0>();
+                lds_barrier();       // step kt landed for every wave; step kt-1's reads are done
+                // Every fragment of the step is read before the copies of a
+                // later step are issued: the compiler cannot tell the stages
+                // apart and makes LDS reads wait for every copy issued before
+                // them, which would stall each step for the whole latency of
+                // its new copies.
+                const uint4* sl = lds[stage_of<STAGES>(kt)];
+                const float* sb = reinterpret_cast<const float*>(sl + B1_OFF);
+                const float* sb2 = reinterpret_cast<const float*>(sl + B2_OFF);
+                float b[TN][4];
+                float4 a[TM];
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int col = wn * WN + 16 * j + li;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int k = 4 * lg + s;
+                        const int e = k * BN + 4 * ((col >> 2) ^ f32_bswz(k)) + (col & 3);
+                        b[j][s] = sb[e];
+                        if constexpr (kTB) b[j][s] = flip_add(b[j][s], sb2[e], negb);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int row = wm * WM + 16 * i + li;
+                    const int e = 4 * row + (lg ^ blk_swz(row & 15));
+                    a[i] = __builtin_bit_cast(float4, sl[e]);
+                    if constexpr (kTA) a[i] = flip_add(a[i], __builtin_bit_cast(float4, sl[A2_OFF + e]), nega);
+                }
+                if (kt + STAGES - 1 < KT) issue(refill_stage_of<STAGES>(kt), (kt + STAGES - 1) * BK);
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float av = s == 0 ? a[i].x : s == 1 ? a[i].y : s == 2 ? a[i].z : a[i].w;
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[j][s], acc[i][j], 0, 0, 0);
+                    }
+                }
             }
+            __syncthreads();         // the next tile's first loads overwrite the stages
+
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
+                        const int64_t col = n0 + wn * WN + 16 * j + li;
+                        if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r];
+                    }
         };
-
-        f32x4 acc[TM][TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-        const int64_t KT = L / BK;
-#pragma unroll
-        for (int s = 0; s < STAGES - 1; ++s)
-            if (s < KT) issue(s, s * BK);
-        for (int64_t kt = 0; kt < KT; ++kt) {
-            if (kt + STAGES - 2 < KT) wait_vmcnt<LPS * (STAGES - 2)>();
-            else wait_vmcnt<0>();
-            __syncthreads();     // step kt landed for every wave; step kt-1's reads are done
-            if (kt + STAGES - 1 < KT) issue((int)((kt + STAGES - 1) % STAGES), (kt + STAGES - 1) * BK);
-            const uint4* sl = lds[kt % STAGES];
-            const float* sb = reinterpret_cast<const float*>(sl + AU);
-            float b[TN][4];
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                const int col = wn * WN + 16 * j + li;
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int k = 4 * lg + s;
-                    b[j][s] = sb[k * BN + 4 * ((col >> 2) ^ f32_bswz(k)) + (col & 3)];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const int row = wm * WM + 16 * i + li;
-                const float4 a = __builtin_bit_cast(float4, sl[4 * row + (lg ^ blk_swz(row & 15))]);
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const float av = s == 0 ? a.x : s == 1 ? a.y : s == 2 ? a.z : a.w;
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[j][s], acc[i][j], 0, 0, 0);
-                }
-            }
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        if constexpr (!FUSE) {
+            run(F_{}, F_{});
+        } else {
+            // (Algorithm 1 never has a view on both sides of one product)
+            if (Ap2 && Bp2) run(T_{}, T_{});
+            else if (Ap2) run(T_{}, F_{});
+            else if (Bp2) run(F_{}, T_{});
+            else run(F_{}, F_{});
         }
-        __syncthreads();         // the next tile's first loads overwrite the stages
-
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
-                    const int64_t col = n0 + wn * WN + 16 * j + li;
-                    if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = acc[i][j][r];
-                }
     }
 }
 
 template <class Src>
 __global__ __launch_bounds__(F32BigCfg::NT) void k_gemm_f32_big(Src src, int64_t total_tiles) {
-    gemm32_lds<F32BigCfg, Src>(src, total_tiles);
+    gemm32_lds<F32BigCfg, Src, false>(src, total_tiles);
+}
+// Fused leaves: two terms per side make a stage 64 KB, so two stages.
+template <class Src>
+__global__ __launch_bounds__(F32FusedCfg::NT) void k_gemm_f32_fused(Src src, int64_t total_tiles) {
+    gemm32_lds<F32FusedCfg, Src, true>(src, total_tiles);
 }
 template <class Src>
 __global__ __launch_bounds__(F32MidCfg::NT) void k_gemm_f32_mid(Src src, int64_t total_tiles) {
-    gemm32_lds<F32MidCfg, Src>(src, total_tiles);
+    gemm32_lds<F32MidCfg, Src, false>(src, total_tiles);
 }
 template <class Src>
 __global__ __launch_bounds__(F32SmallCfg::NT) void k_gemm_f32_small(Src src, int64_t total_tiles) {
-    gemm32_lds<F32SmallCfg, Src>(src, total_tiles);
+    gemm32_lds<F32SmallCfg, Src, false>(src, total_tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -648,8 +783,11 @@ static hipError_t launch_f32_tile_t(const Src& s, int tile, int64_t tiles, int g
     return hipGetLastError();
 }
 template <class Src>
-static hipError_t launch_f32_big_t(const Src& s, int64_t tiles, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemm_f32_big<Src>), dim3(grid), dim3(kF32BigThreads), 0, st, s, tiles);
+static hipError_t launch_f32_big_t(const Src& s, int64_t tiles, int grid, bool fused, hipStream_t st) {
+    if (fused)
+        hipLaunchKernelGGL((k_gemm_f32_fused<Src>), dim3(grid), dim3(F32FusedCfg::NT), 0, st, s, tiles);
+    else
+        hipLaunchKernelGGL((k_gemm_f32_big<Src>), dim3(grid), dim3(kF32BigThreads), 0, st, s, tiles);
     return hipGetLastError();
 }
 template <class Src, int P, bool F16>
@@ -698,8 +836,10 @@ int gemm_blocks_per_cu(int planes, int tile) {
 }
 
 template <class Src>
-hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t tiles, int grid, hipStream_t st) {
-    if (planes == 0) return tile == 256 ? launch_f32_big_t<Src>(s, tiles, grid, st)
+hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t tiles, int grid, hipStream_t st,
+                       bool fused) {
+    if (fused && (planes != 0 || tile != 256)) return hipErrorInvalidValue;
+    if (planes == 0) return tile == 256 ? launch_f32_big_t<Src>(s, tiles, grid, fused, st)
                                         : launch_f32_tile_t<Src>(s, tile, tiles, grid, st);
     if (f16) {   // FP16X3: two binary16 planes
         if (tile == 256) return launch_bf16_big_t<Src, 2, true>(s, tiles, grid, st);
@@ -711,7 +851,7 @@ hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t til
                        : launch_bf16_tile_t<Src, 3, false>(s, tile, tiles, grid, st);
 }
 
-template hipError_t launch_gemm<OneProb>(const OneProb&, int, int, bool, int64_t, int, hipStream_t);
-template hipError_t launch_gemm<TableProb>(const TableProb&, int, int, bool, int64_t, int, hipStream_t);
+template hipError_t launch_gemm<OneProb>(const OneProb&, int, int, bool, int64_t, int, hipStream_t, bool);
+template hipError_t launch_gemm<TableProb>(const TableProb&, int, int, bool, int64_t, int, hipStream_t, bool);
 
 }  // namespace stk

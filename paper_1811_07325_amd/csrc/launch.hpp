@@ -26,8 +26,11 @@ template <class Src> hipError_t launch_split(const Src& s, int planes, int varia
 template <class Src> hipError_t launch_combine(const Src& s, int level, int variant, int64_t blocks, hipStream_t st);
 // Combine levels `level` + 1 and `level` in one pass (depth >= level + 2).
 template <class Src> hipError_t launch_combine2(const Src& s, int level, int variant, int64_t blocks, hipStream_t st);
-// f16: the two planes are binary16 (FP16X3) rather than bfloat16.
-template <class Src> hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t tiles, int grid, hipStream_t st);
+// f16: the two planes are binary16 (FP16X3) rather than bfloat16.  fused:
+// binary32 leaves formed from the level above inside the GEMM (plans with
+// fused leaves; 256-wide tiles only).
+template <class Src> hipError_t launch_gemm(const Src& s, int planes, int tile, bool f16, int64_t tiles, int grid,
+                                            hipStream_t st, bool fused = false);
 
 // Tiles of one leaf of edge `leaf` for the GEMM variant (planes, tile class).
 int64_t gemm_tiles_per_leaf(int planes, int tile, int64_t leaf);

@@ -64,7 +64,7 @@ int tile_candidates(const Plan& p, int out[3]) {
 }
 
 int planes_for(int precision) {
-    if (precision & ~(STARK_PRECISION_MASK | STARK_WINOGRAD)) return -1;
+    if (precision & ~(STARK_PRECISION_MASK | STARK_WINOGRAD | STARK_FUSED)) return -1;
     switch (precision & STARK_PRECISION_MASK) {
         case STARK_FP32: return 0;
         case STARK_BF16X3: return 2;
@@ -136,14 +136,25 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p, int tile) {
         p.bytes = (size_t)(off > 0 ? off : 256);
         return "";
     }
+    // Binary32 leaves with Algorithm 1 on 256-wide tiles: the leaf GEMM forms
+    // the last level's operands from the level above while it copies its
+    // tiles (one add per element, as the divide would), so the divide stops
+    // a level early -- unless the level above is the padded user matrix
+    // (depth 1 with padding: its bounded reads cannot be direct copies).
+    p.fuse = planes == 0 && p.variant == 0 && p.tile == 256 && (precision & STARK_FUSED) &&
+             !(depth == 1 && p.padded);
+    // binary32 levels whose operands the divide stores: every level, or all
+    // but the last with fused leaves
+    const int stored = p.fuse ? depth - 1 : depth;
     // 16-bit paths: the split forms the last level (from depth 2 on, the last
     // two) on the fly, so only the levels above are stored in binary32
-    p.fp32_levels = planes == 0 ? depth : depth >= 2 ? depth - 2 : 0;
+    p.fp32_levels = planes == 0 ? stored : depth >= 2 ? depth - 2 : 0;
     for (int l = 0; l < p.fp32_levels; ++l) {
-        // binary32 path from depth 2 on: level depth-2 is formed on the fly by
-        // the divide of level depth-1, which then stores all seven operands
-        if (planes == 0 && depth >= 2 && l == depth - 2) continue;
-        const bool all7 = (l == 0 && p.padded) || (planes == 0 && depth >= 2 && l == depth - 1);
+        // binary32 path from two stored levels on: level stored-2 is formed
+        // on the fly by the divide of level stored-1, which then stores all
+        // seven operands
+        if (planes == 0 && stored >= 2 && l == stored - 2) continue;
+        const bool all7 = (l == 0 && p.padded) || (planes == 0 && stored >= 2 && l == stored - 1);
         const int slots = all7 ? 7 : p.variant ? 4 : 5;
         const int64_t h = (p.np >> l) >> 1;
         const int64_t sz = (int64_t)slots * pow7(l) * h * h * 4;

@@ -29,6 +29,9 @@ struct Plan {
     int64_t scale = -1;   // FP16X3 scale region
     size_t bytes = 0;
     int fp32_levels = 0;  // binary32 divide levels launched (0 .. depth)
+    // binary32 leaves formed inside the leaf GEMM from the level above
+    // (the divide stops one level early); see make_plan
+    bool fuse = false;
 };
 
 int64_t pow7(int l);

@@ -82,7 +82,7 @@ stark_status run_plan_cu(int num_cu, const Plan& p, const ProbDesc& d, unsigned 
         // retire throughout the launch and kernels of other streams get CUs
         const int grid = persistent ? gemm_grid_cu(num_cu, p.planes, p.tile, tiles)
                                     : (int)std::min<int64_t>(tiles, int64_t(1) << 30);
-        STK_HIP(launch_gemm(src, p.planes, p.tile, d.fp16 != 0, tiles, grid, st));
+        STK_HIP(launch_gemm(src, p.planes, p.tile, d.fp16 != 0, tiles, grid, st, p.fuse));
     }
     if (mask & STARK_PHASE_COMBINE) {
         int l = p.depth - 1;
@@ -274,6 +274,7 @@ stark_status stark_plan_info(int64_t n, int depth, stark_precision prec, stark_p
     out->leaf_flops = w.leaf_flops;
     out->mfma_flops = w.mfma_flops;
     out->variant = p.variant;
+    out->fused = p.fuse ? 1 : 0;
     return STARK_OK;
 }
 

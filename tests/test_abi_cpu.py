@@ -51,29 +51,38 @@ def _regions(d, depth):
     return sorted(regs, key=lambda r: r[1])
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 3, 16, 17, 19])
-@pytest.mark.parametrize("n,depth", [(512, 2), (4096, 3), (1000, 2), (384, 1), (16384, 4), (65, 0), (3000, 3)])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 16, 17, 19, 32, 33, 48])
+@pytest.mark.parametrize("n,depth", [(512, 2), (4096, 3), (1000, 2), (384, 1), (16384, 4), (65, 0), (3000, 3),
+                                     (4096, 1), (4032, 1), (4032, 2), (8192, 2)])
 def test_plan_layout(S, n, depth, prec):
     d = S.stark_plan_info(n, depth, prec)
     np_ = d.n_pad
     assert np_ >= n and np_ % (64 << depth) == 0 and d.leaf == np_ >> depth
     winograd = bool(prec & S.STARK_WINOGRAD)
     assert d.variant == int(winograd)
+    fused_flag = bool(prec & S.STARK_FUSED)
     prec &= 15
     planes = {0: 0, 1: 2, 2: 3, 3: 2}[prec]
     assert d.planes == planes
+    # STARK_FUSED with binary32 Algorithm 1 on 256-wide tiles: the leaf GEMM
+    # forms the last level's operands (not at depth 1 of a padded size), so
+    # the divide stores one level fewer; elsewhere the flag is ignored
+    fused = (planes == 0 and not winograd and fused_flag and d.gemm_tile == 256 and depth >= 1
+             and not (depth == 1 and np_ != n))
+    assert d.fused == int(fused)
+    stored = depth - 1 if fused else depth
     L, h = d.leaf, None
     # sizes of every region, from the layout rules
     size = {}
     # 16-bit paths: the split forms the last level (the last two from depth 2)
-    fp32_levels = depth if planes == 0 else max(depth - 2, 0)
-    # binary32 from depth 2 on: level depth-2 is formed on the fly by the
-    # divide of level depth-1, which stores all seven operands
-    unstored = depth - 2 if (planes == 0 and depth >= 2) else None
+    fp32_levels = stored if planes == 0 else max(depth - 2, 0)
+    # binary32 from two stored levels on: level stored-2 is formed on the fly
+    # by the divide of level stored-1, which stores all seven operands
+    unstored = stored - 2 if (planes == 0 and stored >= 2) else None
     for l in range(depth):
         if l < fp32_levels and l != unstored:
             h = (np_ >> l) // 2
-            slots = 7 if (l == 0 and np_ != n) or (unstored is not None and l == depth - 1) else 4 if winograd else 5
+            slots = 7 if (l == 0 and np_ != n) or (unstored is not None and l == stored - 1) else 4 if winograd else 5
             assert d.div_slots[l] == slots
             size["div_a%d" % l] = size["div_b%d" % l] = slots * 7 ** l * h * h * 4
         else:
@@ -118,14 +127,40 @@ def test_plan_layout(S, n, depth, prec):
 
 
 def test_workspace_formula_fp32(S):
-    """Unpadded binary32, depth k >= 2: levels 0..k-3 store 5 blocks per node
-    and side, (5/4)(7/4)^l N floats each; level k-2 is not stored; level k-1
-    stores 7, (7/4)^k N; plus the (7/4)^k N leaf products."""
-    for n, k in [(4096, 3), (16384, 2), (8192, 4)]:
+    """Unpadded binary32 with stored leaf operands, depth k >= 2: levels
+    0..k-3 store 5 blocks per node and side, (5/4)(7/4)^l N floats each;
+    level k-2 is not stored; level k-1 stores 7, (7/4)^k N; plus the
+    (7/4)^k N leaf products."""
+    for n, k in [(4096, 3), (16384, 2), (8192, 4), (512, 3)]:
         N = n * n
         expect = (2 * sum(1.25 * (7 / 4) ** l for l in range(k - 2)) + 2 * (7 / 4) ** k + (7 / 4) ** k) * N * 4
         got = S.stark_workspace_size(n, k, 0)
         assert abs(got - expect) <= 256 * (4 * k + 2)
+        if S.stark_plan_info(n, k, S.STARK_FUSED).gemm_tile != 256:      # the flag does not apply: the same plan
+            assert S.stark_workspace_size(n, k, S.STARK_FUSED) == got
+
+
+def test_workspace_formula_fp32_fused(S):
+    """Unpadded binary32 with fused leaf operands (256-wide tiles), depth k:
+    the divide stores the levels of depth k - 1 -- k = 1: nothing; k = 2:
+    level 0 with 5 blocks per node and side; k >= 3: levels 0..k-4 with 5,
+    level k-3 not stored, level k-2 with all 7, (7/4)^(k-1) N -- plus the
+    (7/4)^k N leaf products."""
+    for n, k in [(4096, 1), (16384, 2), (4096, 3), (16384, 3), (8192, 4)]:
+        assert S.stark_plan_info(n, k, S.STARK_FUSED).fused == 1
+        assert S.stark_plan_info(n, k, 0).fused == 0
+        N = n * n
+        j = k - 1
+        if j == 0:
+            div = 0.0
+        elif j == 1:
+            div = 2 * 1.25
+        else:
+            div = 2 * sum(1.25 * (7 / 4) ** l for l in range(j - 2)) + 2 * (7 / 4) ** j
+        expect = (div + (7 / 4) ** k) * N * 4
+        got = S.stark_workspace_size(n, k, S.STARK_FUSED)
+        assert abs(got - expect) <= 256 * (4 * k + 2)
+        assert got < S.stark_workspace_size(n, k, 0)
 
 
 def test_winograd_flag_and_unknown_bits(S):
@@ -137,7 +172,7 @@ def test_winograd_flag_and_unknown_bits(S):
     d5, d4 = S.stark_plan_info(4096, 3, 1), S.stark_plan_info(4096, 3, 1 | S.STARK_WINOGRAD)
     assert d5.div_slots[0] == 5 and d4.div_slots[0] == 4
     assert d4.divide_bytes < d5.divide_bytes and d4.split_bytes == d5.split_bytes
-    for bad in (32, 4, 15, 48 | 1):
+    for bad in (64, 4, 15, 64 | 1):
         with pytest.raises(S.StarkError):
             S.stark_workspace_size(512, 1, bad)
 
