@@ -96,7 +96,22 @@ typedef enum {
      * whether it applies).  Off by default: the leaf GEMM then moves twice
      * the operand bytes for five of the seven products and runs slower than
      * the stored-operand path plus the divide it saves. */
-    STARK_FUSED = 32
+    STARK_FUSED = 32,
+    /* Sizes that are not a multiple of 64 * 2^depth (Section III-A treats
+     * n = 2^p only and leaves other sizes to partitioning).  Either the
+     * residue r = n mod (64 * 2^depth) is peeled (possible for
+     * 1 <= r <= 64, depth >= 1 and n - r >= 64 * 2^depth): the recursion
+     * runs on the leading (n - r) x (n - r) core of A and B in place, the r
+     * border rows and columns of C are classical binary32 inner products,
+     * and every core output takes the r products through A's peeled columns
+     * and B's peeled rows when the last combine level writes it.  Or A and B
+     * are zero-padded to the next multiple (on the fly: level 0 reads them
+     * with bounds) and C is cropped.  By default the planner takes the one
+     * its time model finds faster; STARK_PEEL peels whenever possible,
+     * STARK_PAD always pads, and giving both is an error.  stark_plan_info
+     * reports the residue a plan peels. */
+    STARK_PEEL = 64,
+    STARK_PAD = 128
 } stark_precision;
 #define STARK_PRECISION_MASK 15
 
@@ -318,7 +333,8 @@ stark_status stark_generate_normal(float* X, int64_t n, uint64_t seed, void* str
 /* Introspection for tests and profiling.                                    */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int64_t n, n_pad, leaf;   /* user size, padded size, leaf size n_pad/2^depth   */
+    int64_t n, n_pad, leaf;   /* user size, padded size (a peeled plan: its core),
+                                 leaf size n_pad/2^depth                           */
     int depth, precision, planes;
     int64_t div_a[STARK_MAX_DEPTH], div_b[STARK_MAX_DEPTH]; /* byte offsets of the
                                  binary32 divide outputs of level l (-1 = none)    */
@@ -342,6 +358,9 @@ typedef struct {
     int variant;              /* 0: Algorithm 1, 1: Winograd's variant           */
     int fused;                /* 1: the leaf GEMM forms the last level's operands
                                  (binary32; see STARK_FUSED)                       */
+    int peel;                 /* residue r peeled off (n_pad = n - r is then the
+                                 core the recursion runs on; see STARK_PEEL)       */
+    double peel_flops;        /* border products plus the core's r-term fix-up     */
 } stark_plan_desc;
 
 stark_status stark_plan_info(int64_t n, int depth, stark_precision p, stark_plan_desc* out);

@@ -76,6 +76,8 @@ def _load():
     lib.oracle_strassen_model_f32.restype = ctypes.c_int
     lib.oracle_model_f32.argtypes = [P, P, P, I64, ctypes.c_int, I64, ctypes.c_int, ctypes.c_int]
     lib.oracle_model_f32.restype = ctypes.c_int
+    lib.oracle_peel_model_f32.argtypes = [P, P, P, I64, I64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle_peel_model_f32.restype = ctypes.c_int
     lib.oracle_winograd_f64.argtypes = [P, P, P, I64, ctypes.c_int, I64, ctypes.POINTER(Counts)]
     lib.oracle_winograd_f64.restype = ctypes.c_int
     lib.oracle_divide_f32_w.argtypes = [P, I64, P, I64, I64, P, P]
@@ -256,6 +258,24 @@ def strassen_model_f32(A, B, depth: int, mode: str, n_pad: int | None = None,
                                   VARIANTS.index(variant))
     if rc != 0:
         raise ValueError("oracle_strassen_model_f32: bad arguments")
+    return C
+
+
+def peel_model_f32(A, B, depth: int, mode: str, r: int, variant: str = "strassen") -> np.ndarray:
+    """Arithmetic model of a peeled multiply: the recursion on the leading
+    (n - r) x (n - r) blocks of A and B by the model of the square path
+    (unpadded), every core output plus the r products through A's last r
+    columns and B's last r rows, and the border rows and columns as whole
+    inner products, each of these sums exact in binary64 and rounded once.
+    Returns float32 n x n."""
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    n = A.shape[0]
+    C = np.empty((n, n), dtype=np.float32)
+    rc = _load().oracle_peel_model_f32(_ptr(A), _ptr(B), _ptr(C), n, n - r, depth, MODEL_MODES[mode],
+                                       VARIANTS.index(variant))
+    if rc != 0:
+        raise ValueError("oracle_peel_model_f32: bad arguments")
     return C
 
 

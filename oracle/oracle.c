@@ -682,6 +682,41 @@ int oracle_strassen_model_f32(const float* A, const float* B, float* C, int64_t 
     return oracle_model_f32(A, B, C, n, depth, n_pad, mode, 0);
 }
 
+/* Peeled sizes (not in the paper, which treats n = 2^p and leaves other
+ * sizes to partitioning schemes of other work, Section III-A): with
+ * nc = n - r, write A = [A11 A12; A21 A22] with A11 the leading nc x nc
+ * block (likewise B).  Then
+ *   C11 = A11 B11 + A12 B21        (the recursion on the core, plus r terms)
+ *   C12 = A11 B12 + A12 B22        = rows 0..nc-1 of A times columns nc..n-1 of B
+ *   C21, C22 = A21 B + A22 B2*     = rows nc..n-1 of A times all of B,
+ * so only A11 B11 goes through Strassen's recursion (unpadded, nc a multiple
+ * of 2^depth).  Arithmetic model of that scheme: the core by model_rec
+ * (binary32 divide/combine, leaf `mode`; FP16X3 scale exponents from the
+ * whole of A and B), every core output plus its r-term sum A12 B21 and every
+ * border output (an inner product of length n) exact in binary64, each
+ * rounded once to binary32.  Returns 0 or -1. */
+int oracle_peel_model_f32(const float* A, const float* B, float* C, int64_t n, int64_t nc, int depth, int mode,
+                          int variant)
+{
+    if (n <= 0 || nc <= 0 || nc > n || depth < 0 || depth > 20 || (nc % ((int64_t)1 << depth)) != 0 ||
+        (mode != 0 && mode != 2 && mode != 3 && mode != 4) || (variant != 0 && variant != 1))
+        return -1;
+    if (mode == 4) {
+        g_model_ex = oracle_f16_scale_exp(A, n * n, variant ? 2 * depth : depth);
+        g_model_ey = oracle_f16_scale_exp(B, n * n, variant ? 2 * depth : depth);
+    }
+    model_rec(A, n, B, n, C, n, nc, depth, mode, variant);   /* core, in place (leading dimension n) */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            const int core = i < nc && j < nc;
+            double acc = core ? (double)C[i * n + j] : 0.0;
+            for (int64_t t = core ? nc : 0; t < n; ++t) acc += (double)A[i * n + t] * (double)B[t * n + j];
+            C[i * n + j] = (float)acc;
+        }
+    return 0;
+}
+
 /* x * 2^e ~= hi + lo with binary16 terms (RNE), as binary32 values. */
 void oracle_split_f16(const float* x, int64_t count, int e, float* out)
 {

@@ -22,13 +22,14 @@ namespace stk {
 
 namespace {
 
-enum LaunchKind { kPad, kDivide, kAbsmax, kScaleExp, kSplit, kGemm, kCombine, kCombine2 };
+enum LaunchKind { kPad, kDivide, kAbsmax, kScaleExp, kSplit, kGemm, kCombine, kCombine2, kPeel };
 
 struct BatchLaunch {
     LaunchKind kind;
-    int level;      // divide / combine level
+    int level;      // divide / combine level; peel: the largest residue of the launch
     int tile;       // gemm tile class
-    bool fused;     // gemm: binary32 leaves formed in the GEMM (plans with fuse)
+    bool fused;     // gemm: binary32 leaves formed in the GEMM (plans with fuse);
+                    // level-0 combine: some problem peels (fix-up variant)
     int64_t total;  // blocks (or tiles for the gemm)
     size_t prefix;  // index of the prefix array in the device buffer (in int64 units)
 };
@@ -104,8 +105,9 @@ stark_status enqueue(stark_ctx* ctx, const BatchEntry& e, hipStream_t st) {
                 STK_HIP(launch_gemm(src, e.planes, l.tile, e.fp16, l.total,
                                     gemm_grid(ctx, e.planes, l.tile, l.total), st, l.fused));
                 break;
-            case kCombine: STK_HIP(launch_combine(src, l.level, e.variant, l.total, st)); break;
-            case kCombine2: STK_HIP(launch_combine2(src, l.level, e.variant, l.total, st)); break;
+            case kCombine: STK_HIP(launch_combine(src, l.level, e.variant, l.total, st, l.fused)); break;
+            case kCombine2: STK_HIP(launch_combine2(src, l.level, e.variant, l.total, st, l.fused)); break;
+            case kPeel: STK_HIP(launch_peel(src, l.level, l.total, st)); break;
         }
     }
     return STARK_OK;
@@ -199,16 +201,20 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
                     return p.tile == tile && p.fuse == fused
                                ? pow7(p.depth) * gemm_tiles_per_leaf(p.planes, tile, p.leaf) : (int64_t)0;
                 }, fused);
+        int max_peel = 0;
+        for (const Plan& p : plans) max_peel = std::max(max_peel, p.peel);
         // per problem: the two deepest levels in one pass, then one level at a time
         for (int l = max_depth - 1; l >= 0; --l) {
             add_launch(kCombine2, l, 0, [&](int i) {
                 return plans[i].depth >= 2 && plans[i].depth - 2 == l ? blocks_combine2(descs[i], l) : 0;
-            });
+            }, l == 0 && max_peel > 0);
             add_launch(kCombine, l, 0, [&](int i) {
                 const int d = plans[i].depth;
                 return (d == 1 && l == 0) || l <= d - 3 ? blocks_combine(descs[i], l) : 0;
-            });
+            }, l == 0 && max_peel > 0);
         }
+        // border rows and columns of the peeled problems
+        if (max_peel > 0) add_launch(kPeel, max_peel, 0, [&](int i) { return blocks_peel(descs[i]); });
         const size_t bytes = sizeof(ProbDesc) * count + sizeof(int64_t) * pre.size();
         STK_HIP(hipMalloc(&e.dev, bytes));
         std::vector<char> host(bytes);

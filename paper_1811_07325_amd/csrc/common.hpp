@@ -19,12 +19,17 @@ struct ProbDesc {
     const float* B;
     float* C;
     char* ws;           // workspace base
-    int64_t n;          // user size
+    int64_t n;          // edge of the recursion's input: the user size, or
+                        // the core of a peeled plan (n - peel)
+    int64_t ldu;        // leading dimension of A, B and C (the user size)
+    int peel;           // rows and columns peeled off the core (0: none)
     int64_t np;         // padded size (multiple of 2^depth * 64)
     int64_t leaf;       // np >> depth
     int depth;
     int planes;         // 0: binary32 leaves; 2 or 3: bf16 split planes
-    int bounded0;       // level 0 reads A/B with bounds (n != np)
+    int bounded0;       // level 0 reads A/B element by element with bounds
+                        // (n != np, or a peeled plan: rows need not be
+                        // 16-byte aligned)
     int gemm_tile;      // leaf tile edge (64 or 128)
     int64_t div_a[STK_MAXD], div_b[STK_MAXD];  // float offsets of divide outputs
     int div_slots[STK_MAXD];                   // 5 (views kept) or 7
@@ -38,6 +43,7 @@ struct ProbDesc {
 };
 
 constexpr int kScaleParts = 256;               // partial maxima per matrix (FP16X3)
+constexpr int kPeelMaxResidue = 64;            // largest residue a plan peels
 
 // Where the operand blocks of the seven products live after one divide step:
 // a materialised slot index, or a view of the parent's quadrant X11 (-1),
@@ -69,7 +75,7 @@ __device__ __forceinline__ void resolve(const ProbDesc& d, int side, int level, 
         ld = d.np;
     } else {
         ptr = side ? d.B : d.A;
-        ld = d.n;
+        ld = d.ldu;
     }
     int64_t pw = 1;
     for (int j = 1; j < level; ++j) pw *= 7;

@@ -208,7 +208,7 @@ __device__ __forceinline__ void gemm16_lds(Src src, int64_t total_tiles) {
         const uint16_t* Bh = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_b + leaf * P * LL;
         float* Cp;
         int64_t ldc;
-        if (d.depth == 0) { Cp = d.C; ldc = d.n; }
+        if (d.depth == 0) { Cp = d.C; ldc = d.ldu; }
         else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
         const bool crop = d.depth == 0 && d.bounded0;
         const Unscale unscale = unscale_of(d);
@@ -374,7 +374,7 @@ __device__ __forceinline__ void gemm16_pingpong(Src src, int64_t total_tiles) {
         const uint16_t* Bh = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_b + leaf * P * LL;
         float* Cp;
         int64_t ldc;
-        if (d.depth == 0) { Cp = d.C; ldc = d.n; }
+        if (d.depth == 0) { Cp = d.C; ldc = d.ldu; }
         else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
         const bool crop = d.depth == 0 && d.bounded0;
         const Unscale unscale = unscale_of(d);
@@ -632,7 +632,7 @@ __device__ __forceinline__ void gemm32_lds(Src src, int64_t total_tiles) {
         }
         float* Cp;
         int64_t ldc;
-        if (d.depth == 0) { Cp = d.C; ldc = d.n; }
+        if (d.depth == 0) { Cp = d.C; ldc = d.ldu; }
         else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * L * L; ldc = L; }
         const bool crop = d.depth == 0 && d.bounded0;
         const int64_t m0 = tm * BM, n0 = tn * BN;

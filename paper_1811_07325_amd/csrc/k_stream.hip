@@ -33,18 +33,38 @@ __device__ __forceinline__ float4 f4sub(float4 a, float4 b) {
     return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
 }
 
-// Four consecutive elements of row r, columns c..c+3 of an n x n row-major
-// matrix, zero outside (used only where the source is the unpadded user
-// matrix, whose rows need not be 16-byte aligned).
-__device__ __forceinline__ float4 load4_bounded(const float* X, int64_t n, int64_t r, int64_t c) {
+// Four consecutive elements of row r, columns c..c+3 of the leading n x n
+// block of a row-major matrix with leading dimension ld, zero outside (used
+// only where the source is the user matrix, whose rows need not be 16-byte
+// aligned).
+__device__ __forceinline__ float4 load4_bounded(const float* X, int64_t ld, int64_t n, int64_t r, int64_t c) {
+    const float* p = X + r * ld + c;
+    // all four inside: four adjacent loads, which the compiler issues as one
+    // 16-byte load (the target accepts 4-byte-aligned vector accesses)
+    if (r < n && c + 3 < n) return make_float4(p[0], p[1], p[2], p[3]);
     float v[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = (r < n && c + e < n) ? X[r * n + c + e] : 0.0f;
+    for (int e = 0; e < 4; ++e) v[e] = (r < n && c + e < n) ? p[e] : 0.0f;
     return make_float4(v[0], v[1], v[2], v[3]);
 }
 
+// Store the four elements (r, c..c+3) of the leading n x n block of a
+// row-major matrix with leading dimension ld, dropping those outside.
+__device__ __forceinline__ void store4_bounded(float* X, int64_t ld, int64_t n, int64_t r, int64_t c, float4 v) {
+    if (r >= n) return;
+    float* p = X + r * ld + c;
+    if (c + 3 < n) {   // adjacent stores: one 16-byte store
+        p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
+        return;
+    }
+    const float* e = &v.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (c + k < n) p[k] = e[k];
+}
+
 __device__ __forceinline__ float4 load4(const float* X, int64_t ld, int64_t n, int64_t r, int64_t c, bool bounded) {
-    if (bounded) return load4_bounded(X, n, r, c);
+    if (bounded) return load4_bounded(X, ld, n, r, c);
     return *reinterpret_cast<const float4*>(X + r * ld + c);
 }
 
@@ -126,7 +146,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_pad(Src src) {
         const int64_t f = local * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
         if (f < total) {
             const int64_t r = f / rq, c = (f - r * rq) * 4;
-            out[f] = load4_bounded(X, d.n, r, c);
+            out[f] = load4_bounded(X, d.ldu, d.n, r, c);
         }
     }
 }
@@ -265,10 +285,10 @@ __global__ __launch_bounds__(kStreamThreads) void k_divide(Src src, int level) {
         if (f < q4) {
             const int64_t r = f / hq, c = (f - r * hq) * 4;
             if (bounded) {
-                q11[u] = load4_bounded(X, d.n, r, c);
-                q12[u] = load4_bounded(X, d.n, r, c + h);
-                q21[u] = load4_bounded(X, d.n, r + h, c);
-                q22[u] = load4_bounded(X, d.n, r + h, c + h);
+                q11[u] = load4_bounded(X, ld, d.n, r, c);
+                q12[u] = load4_bounded(X, ld, d.n, r, c + h);
+                q21[u] = load4_bounded(X, ld, d.n, r + h, c);
+                q22[u] = load4_bounded(X, ld, d.n, r + h, c + h);
             } else {
                 const float* p = X + r * ld + c;
                 q11[u] = *reinterpret_cast<const float4*>(p);
@@ -544,7 +564,9 @@ __global__ __launch_bounds__(kAbsThreads) void k_absmax(Src src) {
     const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
     const int side = blockIdx.y;
     const float* X = side ? d.B : d.A;
-    const int64_t count = d.n * d.n;
+    // the whole user matrix (for a peeled plan a superset of the core, so
+    // the exponent still keeps every leaf operand in range)
+    const int64_t count = d.ldu * d.ldu;
     // chunks of a multiple of 4 elements, so every chunk starts 16-byte aligned
     const int64_t chunk = ((count + kScaleParts - 1) / kScaleParts + 3) & ~int64_t(3);
     const int64_t lo = local * chunk < count ? local * chunk : count;
@@ -628,7 +650,39 @@ __device__ __forceinline__ void combine_quads(float4 m1, float4 m2, float4 m3, f
     }
 }
 
-template <class Src, int W>
+// Peeled plans (d.peel = r > 0): the recursion covers the leading d.n x d.n
+// core of A, B and C (leading dimension d.ldu = d.n + r); each core output
+// also takes the products through the r peeled columns of A and rows of B,
+// C[i][j] += A[i][d.n + t] B[d.n + t][j] for t = 0 .. r-1 in order, one
+// fused multiply-add per term, added when level 0 writes C.  v[a][b] holds
+// the four outputs C[rows[a]][cols[b] .. cols[b] + 3].
+template <int NR, int NC>
+__device__ __forceinline__ void peel_fix(const ProbDesc& d, const int64_t (&rows)[NR], const int64_t (&cols)[NC],
+                                         float4 (&v)[NR][NC]) {
+    const int64_t ld = d.ldu, nc = d.n;
+#pragma unroll 4
+    for (int t = 0; t < d.peel; ++t) {
+        float a[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) a[i] = d.A[rows[i] * ld + nc + t];
+        const float* brow = d.B + (nc + t) * ld;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const float b0 = brow[cols[j]], b1 = brow[cols[j] + 1], b2 = brow[cols[j] + 2], b3 = brow[cols[j] + 3];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                v[i][j].x = fmaf(a[i], b0, v[i][j].x);
+                v[i][j].y = fmaf(a[i], b1, v[i][j].y);
+                v[i][j].z = fmaf(a[i], b2, v[i][j].z);
+                v[i][j].w = fmaf(a[i], b3, v[i][j].w);
+            }
+        }
+    }
+}
+
+// PEEL: the variant launched for level 0 of peeled plans (with the fix-up;
+// the plain variant keeps its registers free of it).
+template <class Src, int W, bool PEEL>
 __global__ __launch_bounds__(kStreamThreads) void k_combine(Src src, int level) {
     int64_t local;
     const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
@@ -646,11 +700,12 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine(Src src, int level) 
     int64_t ldo;
     if (level == 0) {
         out = d.C;
-        ldo = d.n;
+        ldo = d.ldu;
     } else {
         out = reinterpret_cast<float*>(d.ws) + d.comb[level] + node * m * m;
         ldo = m;
     }
+    const bool peel = PEEL && level == 0 && d.peel > 0;
 #pragma unroll
     for (int u = 0; u < kStreamUnroll; ++u) {
         const int64_t f = chunk * kStreamPerBlock + u * kStreamThreads + threadIdx.x;
@@ -659,19 +714,19 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine(Src src, int level) 
         const float4 m5 = in[4 * q4 + f], m6 = in[5 * q4 + f], m7 = in[6 * q4 + f];
         float4 cq[4];
         combine_quads<W>(m1, m2, m3, m4, m5, m6, m7, cq);
-        const float4 c11 = cq[0], c12 = cq[1], c21 = cq[2], c22 = cq[3];
         const int64_t r = f / hq, c = (f - r * hq) * 4;
+        if (peel) {
+            const int64_t rows[2] = {r, r + h}, cols[2] = {c, c + h};
+            float4 v[2][2] = {{cq[0], cq[1]}, {cq[2], cq[3]}};
+            peel_fix<2, 2>(d, rows, cols, v);
+            cq[0] = v[0][0]; cq[1] = v[0][1]; cq[2] = v[1][0]; cq[3] = v[1][1];
+        }
+        const float4 c11 = cq[0], c12 = cq[1], c21 = cq[2], c22 = cq[3];
         if (crop) {
-            const float* v11 = &c11.x; const float* v12 = &c12.x;
-            const float* v21 = &c21.x; const float* v22 = &c22.x;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t cc = c + e;
-                if (r < d.n && cc < d.n) out[r * ldo + cc] = v11[e];
-                if (r < d.n && cc + h < d.n) out[r * ldo + cc + h] = v12[e];
-                if (r + h < d.n && cc < d.n) out[(r + h) * ldo + cc] = v21[e];
-                if (r + h < d.n && cc + h < d.n) out[(r + h) * ldo + cc + h] = v22[e];
-            }
+            store4_bounded(out, ldo, d.n, r, c, c11);
+            store4_bounded(out, ldo, d.n, r, c + h, c12);
+            store4_bounded(out, ldo, d.n, r + h, c, c21);
+            store4_bounded(out, ldo, d.n, r + h, c + h, c22);
         } else {
             float* p = out + r * ldo + c;
             *reinterpret_cast<float4*>(p) = c11;
@@ -692,7 +747,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine(Src src, int level) 
 // sums suffice; Winograd's (U2 = N1 + N6, ...) keeps N3, N4, N5 until N7.
 // Either way the additions are those of two k_combine launches, in the same
 // order, so the result equals them bit for bit.
-template <class Src, int W>
+template <class Src, int W, bool PEEL>
 __global__ __launch_bounds__(kStreamThreads) void k_combine2(Src src, int level) {
     int64_t local;
     const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
@@ -712,7 +767,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine2(Src src, int level)
     int64_t ldo;
     if (level == 0) {
         out = d.C;
-        ldo = d.n;
+        ldo = d.ldu;
     } else {
         out = reinterpret_cast<float*>(d.ws) + d.comb[level] + node * m * m;
         ldo = m;
@@ -758,6 +813,21 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine2(Src src, int level)
         }
     }
     const int64_t r = f / gq, c = (f - r * gq) * 4;
+    if (PEEL && level == 0 && d.peel > 0) {
+        // output rows r + a g and columns c + b g, a, b = 0..3: quadrant Q =
+        // 2 (a / 2) + b / 2, sub-block 2 (a % 2) + b % 2
+        const int64_t rows[4] = {r, r + g, r + 2 * g, r + 3 * g}, cols[4] = {c, c + g, c + 2 * g, c + 3 * g};
+        float4 v[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v[a][b] = acc[2 * (a >> 1) + (b >> 1)][2 * (a & 1) + (b & 1)];
+        peel_fix<4, 4>(d, rows, cols, v);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[2 * (a >> 1) + (b >> 1)][2 * (a & 1) + (b & 1)] = v[a][b];
+    }
 #pragma unroll
     for (int Q = 0; Q < 4; ++Q)
 #pragma unroll
@@ -765,10 +835,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_combine2(Src src, int level)
             const int64_t row = (Q >> 1) * 2 * g + (sb >> 1) * g + r;
             const int64_t col = (Q & 1) * 2 * g + (sb & 1) * g + c;
             if (crop) {
-                const float* v = &acc[Q][sb].x;
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (row < d.n && col + e < d.n) out[row * ldo + col + e] = v[e];
+                store4_bounded(out, ldo, d.n, row, col, acc[Q][sb]);
             } else {
                 *reinterpret_cast<float4*>(out + row * ldo + col) = acc[Q][sb];
             }
@@ -827,6 +894,143 @@ __global__ __launch_bounds__(kStreamThreads) void k_reduce_blocks(const float* P
 }
 
 // ---------------------------------------------------------------------------
+// Border of a peeled plan (n = d.ldu, core nc = d.n, r = d.peel rows and
+// columns peeled):
+//   right:  C[i][nc + y] for i < nc, y < r
+//   bottom: C[nc + y][j] for y < r, j < n
+// each the whole inner product over t = 0 .. n-1 in ascending order, one
+// fused multiply-add per term, in binary32 (exact for integers).  A block
+// owns 64 indices along the long side (right: rows i; bottom: columns j) and
+// every short-side index y < r (RB >= r of them, the rest zero).  K runs in
+// chunks of 64: the long side's 64 x 64 operand chunk and the short side's
+// RB x 64 chunk sit in LDS (rows padded to 68 floats, so 16-byte reads of 16
+// consecutive rows hit distinct banks) while the loads of the next chunk are
+// in flight in registers.  A thread owns TX long x TY short outputs
+// (RB 64: 4 x 4; 16: 1 x 4; 4: 1 x 1).
+// ---------------------------------------------------------------------------
+constexpr int kPeelStrip = 64, kPeelK = 64, kPeelLd = kPeelK + 4;
+
+template <int RB> struct PeelTile;
+template <> struct PeelTile<4> { static constexpr int TX = 1, TY = 1; };
+template <> struct PeelTile<16> { static constexpr int TX = 1, TY = 4; };
+template <> struct PeelTile<64> { static constexpr int TX = 4, TY = 4; };
+
+template <class Src, int RB>
+__global__ __launch_bounds__(kStreamThreads) void k_peel(Src src) {
+    static_assert(RB <= kPeelMaxResidue, "short-side block");
+    constexpr int TX = PeelTile<RB>::TX, TY = PeelTile<RB>::TY;
+    constexpr int XS = kPeelStrip / TX, YS = RB / TY;      // thread grid XS x YS
+    static_assert(XS * YS == kStreamThreads, "one output block per thread");
+    int64_t local;
+    const ProbDesc& d = src.get(src.locate(blockIdx.x, local));
+    const int64_t n = d.ldu, nc = d.n;
+    const int r = d.peel;
+    const int64_t right_blocks = (nc + kPeelStrip - 1) / kPeelStrip;
+    const bool right = local < right_blocks;
+    const int64_t s0 = (right ? local : local - right_blocks) * kPeelStrip;
+    const int64_t slen = right ? nc : n;
+    __shared__ __attribute__((aligned(16))) float big[2][kPeelStrip][kPeelLd];   // [long index][t]
+    __shared__ __attribute__((aligned(16))) float sm[2][RB][kPeelLd];           // [short index][t]
+    const int tid = threadIdx.x;
+    constexpr int BPT = kPeelStrip * kPeelK / kStreamThreads;   // long-side elements per thread
+    constexpr int SPT = RB * kPeelK / kStreamThreads;           // short-side elements per thread
+    float rb[BPT], rs[SPT];
+    // long-side element u of this thread: lanes run along a matrix row (A row
+    // s0 + x for the right border, B row k0 + t for the bottom one), so each
+    // wave load reads 256 contiguous bytes whatever the row alignment
+    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int NWV = kStreamThreads / 64;
+    auto big_at = [&](int u, int& x, int& t) {
+        if (right) { t = lane; x = wv + NWV * u; }
+        else { x = lane; t = wv + NWV * u; }
+    };
+    auto sm_at = [&](int u, int& y, int& t) {
+        const int e = tid + kStreamThreads * u;
+        if (right) { y = e % RB; t = e / RB; }      // B row k0 + t, column nc + y
+        else { t = e % kPeelK; y = e / kPeelK; }    // A row nc + y, column k0 + t
+    };
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            int x, t;
+            big_at(u, x, t);
+            const int64_t gx = s0 + x, gt = k0 + t;
+            rb[u] = (gx < slen && gt < n) ? (right ? d.A[gx * n + gt] : d.B[gt * n + gx]) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            int y, t;
+            sm_at(u, y, t);
+            const int64_t gt = k0 + t;
+            rs[u] = (y < r && gt < n) ? (right ? d.B[gt * n + nc + y] : d.A[(nc + y) * n + gt]) : 0.0f;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            int x, t;
+            big_at(u, x, t);
+            big[buf][x][t] = rb[u];
+        }
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            int y, t;
+            sm_at(u, y, t);
+            sm[buf][y][t] = rs[u];
+        }
+    };
+
+    // outputs of this thread: long indices xa + XS i, short indices ya + YS j
+    const int xa = tid % XS, ya = tid / XS;
+    float acc[TX][TY];
+#pragma unroll
+    for (int i = 0; i < TX; ++i)
+#pragma unroll
+        for (int j = 0; j < TY; ++j) acc[i][j] = 0.0f;
+    const int64_t KC = (n + kPeelK - 1) / kPeelK;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int64_t kc = 0; kc < KC; ++kc) {
+        const int buf = (int)(kc & 1);
+        if (kc + 1 < KC) fetch((kc + 1) * kPeelK);
+#pragma unroll 2
+        for (int t = 0; t < kPeelK; t += 4) {
+            float4 a[TX], b[TY];
+#pragma unroll
+            for (int i = 0; i < TX; ++i) a[i] = *reinterpret_cast<const float4*>(&big[buf][xa + XS * i][t]);
+#pragma unroll
+            for (int j = 0; j < TY; ++j) b[j] = *reinterpret_cast<const float4*>(&sm[buf][ya + YS * j][t]);
+#pragma unroll
+            for (int i = 0; i < TX; ++i)
+#pragma unroll
+                for (int j = 0; j < TY; ++j) {
+                    acc[i][j] = fmaf(a[i].x, b[j].x, acc[i][j]);
+                    acc[i][j] = fmaf(a[i].y, b[j].y, acc[i][j]);
+                    acc[i][j] = fmaf(a[i].z, b[j].z, acc[i][j]);
+                    acc[i][j] = fmaf(a[i].w, b[j].w, acc[i][j]);
+                }
+        }
+        // the other buffer was last read in the previous chunk, before the
+        // barrier that ended it
+        if (kc + 1 < KC) stash(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TX; ++i) {
+        const int64_t gx = s0 + xa + XS * i;
+        if (gx >= slen) continue;
+#pragma unroll
+        for (int j = 0; j < TY; ++j) {
+            const int y = ya + YS * j;
+            if (y >= r) continue;
+            if (right) d.C[gx * n + nc + y] = acc[i][j];
+            else d.C[(nc + y) * n + gx] = acc[i][j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
 static int64_t pow7(int l) {
@@ -849,6 +1053,10 @@ int64_t blocks_split(const ProbDesc& d) {
     return nodes * tiles;
 }
 int64_t blocks_combine(const ProbDesc& d, int level) { return blocks_divide(d, level); }
+int64_t blocks_peel(const ProbDesc& d) {
+    if (d.peel <= 0) return 0;
+    return (d.n + kPeelStrip - 1) / kPeelStrip + (d.ldu + kPeelStrip - 1) / kPeelStrip;
+}
 int64_t blocks_combine2(const ProbDesc& d, int level) {
     const int64_t g = (d.np >> level) >> 2;
     const int64_t q4 = g * (g / 4);
@@ -888,19 +1096,31 @@ hipError_t launch_split(const Src& s, int planes, int variant, int64_t blocks, h
     return hipGetLastError();
 }
 template <class Src>
-hipError_t launch_combine2(const Src& s, int level, int variant, int64_t blocks, hipStream_t st) {
-    if (variant)
-        hipLaunchKernelGGL((k_combine2<Src, 1>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
-    else
-        hipLaunchKernelGGL((k_combine2<Src, 0>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
+hipError_t launch_combine2(const Src& s, int level, int variant, int64_t blocks, hipStream_t st, bool peel) {
+    const dim3 grid((unsigned)blocks), block(kStreamThreads);
+    if (peel && variant) hipLaunchKernelGGL((k_combine2<Src, 1, true>), grid, block, 0, st, s, level);
+    else if (peel) hipLaunchKernelGGL((k_combine2<Src, 0, true>), grid, block, 0, st, s, level);
+    else if (variant) hipLaunchKernelGGL((k_combine2<Src, 1, false>), grid, block, 0, st, s, level);
+    else hipLaunchKernelGGL((k_combine2<Src, 0, false>), grid, block, 0, st, s, level);
     return hipGetLastError();
 }
 template <class Src>
-hipError_t launch_combine(const Src& s, int level, int variant, int64_t blocks, hipStream_t st) {
-    if (variant)
-        hipLaunchKernelGGL((k_combine<Src, 1>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
-    else
-        hipLaunchKernelGGL((k_combine<Src, 0>), dim3((unsigned)blocks), dim3(kStreamThreads), 0, st, s, level);
+hipError_t launch_combine(const Src& s, int level, int variant, int64_t blocks, hipStream_t st, bool peel) {
+    const dim3 grid((unsigned)blocks), block(kStreamThreads);
+    if (peel && variant) hipLaunchKernelGGL((k_combine<Src, 1, true>), grid, block, 0, st, s, level);
+    else if (peel) hipLaunchKernelGGL((k_combine<Src, 0, true>), grid, block, 0, st, s, level);
+    else if (variant) hipLaunchKernelGGL((k_combine<Src, 1, false>), grid, block, 0, st, s, level);
+    else hipLaunchKernelGGL((k_combine<Src, 0, false>), grid, block, 0, st, s, level);
+    return hipGetLastError();
+}
+
+template <class Src>
+hipError_t launch_peel(const Src& s, int max_peel, int64_t blocks, hipStream_t st) {
+    if (max_peel < 1 || max_peel > kPeelMaxResidue) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks), block(kStreamThreads);
+    if (max_peel <= 4) hipLaunchKernelGGL((k_peel<Src, 4>), grid, block, 0, st, s);
+    else if (max_peel <= 16) hipLaunchKernelGGL((k_peel<Src, 16>), grid, block, 0, st, s);
+    else hipLaunchKernelGGL((k_peel<Src, 64>), grid, block, 0, st, s);
     return hipGetLastError();
 }
 
@@ -929,9 +1149,11 @@ template hipError_t launch_divide<OneProb>(const OneProb&, int, int, int64_t, hi
 template hipError_t launch_divide<TableProb>(const TableProb&, int, int, int64_t, hipStream_t);
 template hipError_t launch_split<OneProb>(const OneProb&, int, int, int64_t, hipStream_t);
 template hipError_t launch_split<TableProb>(const TableProb&, int, int, int64_t, hipStream_t);
-template hipError_t launch_combine<OneProb>(const OneProb&, int, int, int64_t, hipStream_t);
-template hipError_t launch_combine<TableProb>(const TableProb&, int, int, int64_t, hipStream_t);
-template hipError_t launch_combine2<OneProb>(const OneProb&, int, int, int64_t, hipStream_t);
-template hipError_t launch_combine2<TableProb>(const TableProb&, int, int, int64_t, hipStream_t);
+template hipError_t launch_combine<OneProb>(const OneProb&, int, int, int64_t, hipStream_t, bool);
+template hipError_t launch_combine<TableProb>(const TableProb&, int, int, int64_t, hipStream_t, bool);
+template hipError_t launch_combine2<OneProb>(const OneProb&, int, int, int64_t, hipStream_t, bool);
+template hipError_t launch_combine2<TableProb>(const TableProb&, int, int, int64_t, hipStream_t, bool);
+template hipError_t launch_peel<OneProb>(const OneProb&, int, int64_t, hipStream_t);
+template hipError_t launch_peel<TableProb>(const TableProb&, int, int64_t, hipStream_t);
 
 }  // namespace stk

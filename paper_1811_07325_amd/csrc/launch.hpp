@@ -13,6 +13,7 @@ int64_t blocks_divide(const ProbDesc& d, int level);
 int64_t blocks_split(const ProbDesc& d);
 int64_t blocks_combine(const ProbDesc& d, int level);
 int64_t blocks_combine2(const ProbDesc& d, int level);
+int64_t blocks_peel(const ProbDesc& d);   // 0 unless the plan peels
 
 template <class Src> hipError_t launch_pad(const Src& s, int64_t blocks, hipStream_t st);
 // FP16X3 scaling: partial maxima (kScaleParts blocks per problem), then the
@@ -23,9 +24,15 @@ template <class Src> hipError_t launch_scale_exp(const Src& s, int64_t blocks, h
 // a launch).
 template <class Src> hipError_t launch_divide(const Src& s, int level, int variant, int64_t blocks, hipStream_t st);
 template <class Src> hipError_t launch_split(const Src& s, int planes, int variant, int64_t blocks, hipStream_t st);
-template <class Src> hipError_t launch_combine(const Src& s, int level, int variant, int64_t blocks, hipStream_t st);
+// peel: level 0 of a launch with peeled problems (adds their core fix-up).
+template <class Src> hipError_t launch_combine(const Src& s, int level, int variant, int64_t blocks, hipStream_t st,
+                                               bool peel = false);
 // Combine levels `level` + 1 and `level` in one pass (depth >= level + 2).
-template <class Src> hipError_t launch_combine2(const Src& s, int level, int variant, int64_t blocks, hipStream_t st);
+template <class Src> hipError_t launch_combine2(const Src& s, int level, int variant, int64_t blocks, hipStream_t st,
+                                                bool peel = false);
+// Border rows and columns of peeled plans (max_peel: the largest residue
+// among the launch's problems, 1 .. kPeelMaxResidue).
+template <class Src> hipError_t launch_peel(const Src& s, int max_peel, int64_t blocks, hipStream_t st);
 // f16: the two planes are binary16 (FP16X3) rather than bfloat16.  fused:
 // binary32 leaves formed from the level above inside the GEMM (plans with
 // fused leaves; 256-wide tiles only).

@@ -64,7 +64,7 @@ int tile_candidates(const Plan& p, int out[3]) {
 }
 
 int planes_for(int precision) {
-    if (precision & ~(STARK_PRECISION_MASK | STARK_WINOGRAD | STARK_FUSED)) return -1;
+    if (precision & ~(STARK_PRECISION_MASK | STARK_WINOGRAD | STARK_FUSED | STARK_PEEL | STARK_PAD)) return -1;
     switch (precision & STARK_PRECISION_MASK) {
         case STARK_FP32: return 0;
         case STARK_BF16X3: return 2;
@@ -88,9 +88,39 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p, int tile) {
     p.precision = precision;
     p.variant = (precision & STARK_WINOGRAD) ? 1 : 0;
     p.planes = planes;
-    p.np = padded_size(n, depth);
+    if ((precision & STARK_PEEL) && (precision & STARK_PAD)) return "STARK_PEEL and STARK_PAD exclude each other";
+    // Sizes off the 64 * 2^depth grid: peel the residue r (the recursion
+    // runs on the leading (n - r)^2 core in place; border and fix-up are
+    // classical) or zero-pad to the next multiple.  Peeling reads A and B
+    // once more for the border and multiplies 2 r n (2n - r) more on the
+    // vector units; padding adds about 3 (64 * 2^depth - r) / n of the
+    // recursion's work and can leave leaves whose edge no wide tile class
+    // divides.  Without STARK_PEEL or STARK_PAD the modelled faster one is
+    // taken.
+    {
+        const int64_t g = kLeafGranule << depth;
+        const int64_t r = n % g;
+        const bool can = depth >= 1 && r >= 1 && r <= kPeelMaxResidue && n - r >= g;
+        if (can && !(precision & (STARK_PEEL | STARK_PAD))) {
+            // (a forced tile class must divide the leaf of the plan taken)
+            Plan peeled, padded;
+            const std::string e1 = make_plan(n, depth, precision | STARK_PEEL, peeled, tile);
+            const std::string e2 = make_plan(n, depth, precision | STARK_PAD, padded, tile);
+            if (!e1.empty() && !e2.empty()) return e1;
+            if (e2.empty() && (!e1.empty() || model_seconds(padded) < model_seconds(peeled))) p = padded;
+            else p = peeled;
+            p.precision = precision;
+            return "";
+        }
+        if (can && (precision & STARK_PEEL)) p.peel = (int)r;
+    }
+    p.np = p.peel ? n - p.peel : padded_size(n, depth);
     p.leaf = p.np >> depth;
-    p.padded = (p.np != n);
+    // level 0 reads A, B (and writes C) element by element with bounds: the
+    // user matrices of a padded size are smaller than np, and the rows of a
+    // peeled one are not 16-byte aligned unless n is a multiple of 4 (then
+    // the core is read and written like an unpadded matrix)
+    p.padded = (p.np != n) && !(p.peel && n % 4 == 0);
     // Leaf GEMM tile class: the largest whose tiles still fill most of the
     // chip -- 256-wide tiles run one block per CU (256 CUs), 128-wide two;
     // measured, 256-wide tiles beat 128-wide ones down to about 3/4 of a
@@ -188,7 +218,9 @@ ProbDesc make_desc(const Plan& p, const float* A, const float* B, float* C, void
     d.B = B;
     d.C = C;
     d.ws = static_cast<char*>(ws);
-    d.n = p.n;
+    d.n = p.peel ? p.np : p.n;
+    d.ldu = p.n;
+    d.peel = p.peel;
     d.np = p.np;
     d.leaf = p.leaf;
     d.depth = p.depth;
@@ -248,6 +280,14 @@ Work plan_work(const Plan& p) {
         w.combine_bytes += (double)pow7(l) * (7.0 + 4.0) * h * h * E;
     }
     if (p.pad_a >= 0) w.pad_bytes = 2.0 * ((double)p.n * p.n * E + (double)p.np * p.np * E);
+    if (p.peel) {
+        // border: rows np..n-1 (all n columns) and columns np..n-1 of rows
+        // 0..np-1, each an inner product of length n; fix-up: r terms per
+        // core output.  The border kernel reads A and B once.
+        const double n = (double)p.n, nc = (double)p.np, r = (double)p.peel;
+        w.peel_flops = 2.0 * n * r * (n + nc) + 2.0 * r * nc * nc;
+        w.peel_bytes = 2.0 * n * n * E;
+    }
     return w;
 }
 
@@ -263,11 +303,14 @@ double model_seconds(const Plan& p) {
     int launches = 1 + (p.pad_a >= 0 ? 1 : 0) + (split ? 1 : 0) + (p.scale >= 0 ? 2 : 0);
     for (int l = 0; l < p.fp32_levels; ++l) launches += p.div_slots[l] > 0 ? 1 : 0;
     launches += p.depth >= 2 ? p.depth - 1 : p.depth;
-    const double bytes = w.divide_bytes + w.split_bytes + w.combine_bytes + w.pad_bytes;
+    const double bytes = w.divide_bytes + w.split_bytes + w.combine_bytes + w.pad_bytes + w.peel_bytes;
+    if (p.peel) launches += 1;
     // streaming rates fitted to measured depth choices: the 16-bit paths' split and
     // combine move their bytes faster than the binary32 divide
     const double bw = split ? 5e12 : 4e12;
-    return w.mfma_flops / (rate * fill * klen) + bytes / bw + launches * 6e-6;
+    // peeled plans: border and fix-up products on the vector units
+    const double peel_s = w.peel_flops / kPeelRate;
+    return w.mfma_flops / (rate * fill * klen) + bytes / bw + launches * 6e-6 + peel_s;
 }
 
 int model_depth(int64_t n, int precision) {

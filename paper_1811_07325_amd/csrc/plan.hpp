@@ -11,6 +11,7 @@
 namespace stk {
 
 constexpr int64_t kLeafGranule = 64;   // leaf edge is a multiple of this
+constexpr double kPeelRate = 60e12;     // border and fix-up flops per second (model)
 
 struct Plan {
     int64_t n = 0, np = 0, leaf = 0;
@@ -19,7 +20,8 @@ struct Plan {
     int variant = 0;     // 0: Algorithm 1, 1: Winograd's variant
     int planes = 0;      // 0, 2, 3
     int tile = 128;      // leaf GEMM tile edge
-    bool padded = false;
+    bool padded = false;  // level 0 reads A, B element by element (n != np,
+                          // except a peeled plan with 16-byte-aligned rows)
     // Byte offsets (-1 = region absent).
     int64_t div_a[STK_MAXD], div_b[STK_MAXD];
     int div_slots[STK_MAXD];
@@ -32,6 +34,10 @@ struct Plan {
     // binary32 leaves formed inside the leaf GEMM from the level above
     // (the divide stops one level early); see make_plan
     bool fuse = false;
+    // residue peeled off: the recursion runs on the leading np x np core
+    // (np = n - peel) in place; the border and the core's fix-up are
+    // classical (see make_plan)
+    int peel = 0;
 };
 
 int64_t pow7(int l);
@@ -57,6 +63,9 @@ ProbDesc make_desc(const Plan& p, const float* A, const float* B, float* C, void
 struct Work {
     double leaf_flops, mfma_flops;
     double divide_bytes, split_bytes, combine_bytes, pad_bytes;
+    // peeled plans: border and fix-up flops; bytes the border kernel must
+    // read (A and B once)
+    double peel_flops, peel_bytes;
 };
 Work plan_work(const Plan& p);
 

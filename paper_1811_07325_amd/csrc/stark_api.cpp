@@ -87,11 +87,15 @@ stark_status run_plan_cu(int num_cu, const Plan& p, const ProbDesc& d, unsigned 
     if (mask & STARK_PHASE_COMBINE) {
         int l = p.depth - 1;
         if (p.depth >= 2) {   // the two deepest levels in one pass
-            STK_HIP(launch_combine2(src, p.depth - 2, p.variant, blocks_combine2(d, p.depth - 2), st));
+            STK_HIP(launch_combine2(src, p.depth - 2, p.variant, blocks_combine2(d, p.depth - 2), st,
+                                    p.depth == 2 && p.peel > 0));
             l = p.depth - 3;
         }
         for (; l >= 0; --l)
-            STK_HIP(launch_combine(src, l, p.variant, blocks_combine(d, l), st));
+            STK_HIP(launch_combine(src, l, p.variant, blocks_combine(d, l), st, l == 0 && p.peel > 0));
+        // border rows and columns of a peeled plan (the core's fix-up is in
+        // the level-0 combine)
+        if (p.peel) STK_HIP(launch_peel(src, p.peel, blocks_peel(d), st));
     }
     return STARK_OK;
 }
@@ -275,6 +279,8 @@ stark_status stark_plan_info(int64_t n, int depth, stark_precision prec, stark_p
     out->mfma_flops = w.mfma_flops;
     out->variant = p.variant;
     out->fused = p.fuse ? 1 : 0;
+    out->peel = p.peel;
+    out->peel_flops = w.peel_flops;
     return STARK_OK;
 }
 

@@ -34,6 +34,8 @@ STARK_BF16X6 = 2
 STARK_FP16X3 = 3
 STARK_WINOGRAD = 16      # flag: Winograd's variant of the recursion (OR into any precision)
 STARK_FUSED = 32         # flag: binary32 leaf operands formed inside the leaf GEMM (where the plan allows it)
+STARK_PEEL = 64          # flag: peel every residue n mod (64 * 2^depth) up to 64 (default: up to 16)
+STARK_PAD = 128          # flag: never peel; zero-pad to the next multiple of 64 * 2^depth
 PRECISIONS = {"fp32": STARK_FP32, "bf16x3": STARK_BF16X3, "bf16x6": STARK_BF16X6, "fp16x3": STARK_FP16X3}
 PRECISIONS.update({k + "_winograd": v | STARK_WINOGRAD for k, v in list(PRECISIONS.items())})
 
@@ -92,7 +94,8 @@ class stark_plan_desc(ctypes.Structure):
                 ("gemm_tile", ctypes.c_int), ("scale", ctypes.c_int64),
                 ("divide_bytes", ctypes.c_double), ("split_bytes", ctypes.c_double),
                 ("combine_bytes", ctypes.c_double), ("leaf_flops", ctypes.c_double),
-                ("mfma_flops", ctypes.c_double), ("variant", ctypes.c_int), ("fused", ctypes.c_int)]
+                ("mfma_flops", ctypes.c_double), ("variant", ctypes.c_int), ("fused", ctypes.c_int),
+                ("peel", ctypes.c_int), ("peel_flops", ctypes.c_double)]
 
 
 def _load() -> ctypes.CDLL:

@@ -51,24 +51,43 @@ def _regions(d, depth):
     return sorted(regs, key=lambda r: r[1])
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 3, 16, 17, 19, 32, 33, 48])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 16, 17, 19, 32, 33, 48, 64, 65, 83, 128])
 @pytest.mark.parametrize("n,depth", [(512, 2), (4096, 3), (1000, 2), (384, 1), (16384, 4), (65, 0), (3000, 3),
-                                     (4096, 1), (4032, 1), (4032, 2), (8192, 2)])
+                                     (4096, 1), (4032, 1), (4032, 2), (8192, 2), (16385, 2), (1031, 2),
+                                     (4097, 1), (4160, 2), (8255, 3)])
 def test_plan_layout(S, n, depth, prec):
     d = S.stark_plan_info(n, depth, prec)
     np_ = d.n_pad
-    assert np_ >= n and np_ % (64 << depth) == 0 and d.leaf == np_ >> depth
+    # a peeled plan runs the recursion on the core n - peel, a padded one on
+    # the next multiple of 64 * 2^depth
+    assert np_ == n - d.peel if d.peel else np_ >= n
+    assert np_ % (64 << depth) == 0 and d.leaf == np_ >> depth
     winograd = bool(prec & S.STARK_WINOGRAD)
     assert d.variant == int(winograd)
     fused_flag = bool(prec & S.STARK_FUSED)
+    g, r = 64 << depth, n % (64 << depth)
+    can_peel = depth >= 1 and 1 <= r <= 64 and n - r >= g
+    if can_peel and prec & S.STARK_PEEL:
+        assert d.peel == r
+    elif not can_peel or prec & S.STARK_PAD:
+        assert d.peel == 0
+    else:                      # the planner's time model chooses
+        assert d.peel in (0, r)
+    if d.peel:
+        assert d.peel_flops == 2 * n * r * (n + np_) + 2 * r * np_ * np_
+    else:
+        assert d.peel_flops == 0
     prec &= 15
     planes = {0: 0, 1: 2, 2: 3, 3: 2}[prec]
     assert d.planes == planes
     # STARK_FUSED with binary32 Algorithm 1 on 256-wide tiles: the leaf GEMM
     # forms the last level's operands (not at depth 1 of a padded size), so
     # the divide stores one level fewer; elsewhere the flag is ignored
+    # level 0 read element by element: padded sizes, and peeled ones whose
+    # rows are not 16-byte aligned
+    bounded = np_ != n and not (d.peel and n % 4 == 0)
     fused = (planes == 0 and not winograd and fused_flag and d.gemm_tile == 256 and depth >= 1
-             and not (depth == 1 and np_ != n))
+             and not (depth == 1 and bounded))
     assert d.fused == int(fused)
     stored = depth - 1 if fused else depth
     L, h = d.leaf, None
@@ -82,7 +101,7 @@ def test_plan_layout(S, n, depth, prec):
     for l in range(depth):
         if l < fp32_levels and l != unstored:
             h = (np_ >> l) // 2
-            slots = 7 if (l == 0 and np_ != n) or (unstored is not None and l == stored - 1) else 4 if winograd else 5
+            slots = 7 if (l == 0 and bounded) or (unstored is not None and l == stored - 1) else 4 if winograd else 5
             assert d.div_slots[l] == slots
             size["div_a%d" % l] = size["div_b%d" % l] = slots * 7 ** l * h * h * 4
         else:
@@ -124,6 +143,38 @@ def test_plan_layout(S, n, depth, prec):
         assert a1 <= d.leaf_m
         if d.scale >= 0:       # the combine outputs never overwrite the scale region
             assert a0 >= d.scale + size["scale"]
+
+
+def test_peel_rule(S):
+    """Residues r = n mod (64 * 2^depth) up to 64 can be peeled: always with
+    STARK_PEEL, never with STARK_PAD, and by default when the planner's time
+    model finds it faster (at n = 16384 + r padding leaves leaves of edge
+    4096 + 64, which only the 64-wide tiles divide, so every r peels; at
+    n = 1087, depth 1, the 64-wide tiles run either way and padding costs
+    less); depth 0 and sizes below one granule always pad; the peeled core
+    needs the workspace of its own size (level 0 read element by element,
+    so all seven operands stored)."""
+    P = lambda n, depth, flags=0: S.stark_plan_info(n, depth, flags)
+    assert (P(16385, 2).peel, P(16385, 2).n_pad) == (1, 16384)
+    assert (P(16391, 2).peel, P(16391, 2).n_pad) == (7, 16384)
+    assert (P(16448, 2).peel, P(16448, 2).n_pad) == (64, 16384)
+    assert (P(16448, 2, S.STARK_PAD).peel, P(16448, 2, S.STARK_PAD).n_pad) == (0, 16640)
+    assert P(16448, 2, S.STARK_PAD).gemm_tile == 64 and P(16448, 2).gemm_tile == 256
+    assert (P(1087, 1).peel, P(1087, 1).n_pad) == (0, 1152)
+    assert (P(1087, 1, S.STARK_PEEL).peel, P(1087, 1, S.STARK_PEEL).n_pad) == (63, 1024)
+    assert P(16447, 2, S.STARK_PEEL).peel == 63
+    assert P(16449, 2, S.STARK_PEEL).peel == 0          # residue 65: padded
+    assert P(16385, 2, S.STARK_PAD).peel == 0 and P(16385, 2, S.STARK_PAD).n_pad == 16640
+    assert P(16385, 0).peel == 0 and P(16385, 0).n_pad == 16448
+    assert P(257, 1, S.STARK_PEEL).peel == 1 and P(257, 1, S.STARK_PEEL).n_pad == 256
+    assert P(100, 1, S.STARK_PEEL).peel == 0 and P(100, 1).n_pad == 128     # no core of 128 to recurse on
+    with pytest.raises(S.StarkError):
+        S.stark_plan_info(16385, 2, S.STARK_PEEL | S.STARK_PAD)
+    for n, depth, prec in [(16385, 2, 0), (4103, 1, 1), (8199, 3, 3)]:
+        d = P(n, depth, prec)
+        assert d.peel > 0
+        core = P(n - d.peel, depth, prec)
+        assert d.bytes >= core.bytes and d.div_slots[0] in ((0, 7) if n % 4 else (0, 4, 5))
 
 
 def test_workspace_formula_fp32(S):
@@ -172,7 +223,7 @@ def test_winograd_flag_and_unknown_bits(S):
     d5, d4 = S.stark_plan_info(4096, 3, 1), S.stark_plan_info(4096, 3, 1 | S.STARK_WINOGRAD)
     assert d5.div_slots[0] == 5 and d4.div_slots[0] == 4
     assert d4.divide_bytes < d5.divide_bytes and d4.split_bytes == d5.split_bytes
-    for bad in (64, 4, 15, 64 | 1):
+    for bad in (256, 4, 15, 256 | 1):
         with pytest.raises(S.StarkError):
             S.stark_workspace_size(512, 1, bad)
 
@@ -237,7 +288,7 @@ def test_model_depth(S):
     assert S.stark_model_depth(8192, 0) == 2
     assert S.stark_model_depth(16384, 0) == 3
     assert S.stark_model_depth(3000, 1) == 1
-    assert S.stark_model_depth(0, 0) == -1 and S.stark_model_depth(100, 99) == -1
+    assert S.stark_model_depth(0, 0) == -1 and S.stark_model_depth(100, 999) == -1
 
 
 def test_plan_work_figures(S):

@@ -138,7 +138,7 @@ def test_rect_argument_errors(S, ctx):
         S.stark_gemm_rect(ctx, shifted, dB, dC, 64, 96, 32, 0, 0, None)
     assert e.value.status == S.STARK_EINVAL
     with pytest.raises(S.StarkError) as e:
-        S.stark_gemm_rect(ctx, dA, dB, dC, 64, 96, 32, 0, 99, None)
+        S.stark_gemm_rect(ctx, dA, dB, dC, 64, 96, 32, 0, 999, None)
     assert e.value.status == S.STARK_EUNSUPPORTED
 
 

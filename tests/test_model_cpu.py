@@ -17,6 +17,38 @@ def test_model_exact_on_small_integers(mode, n, depth):
     assert np.array_equal(C.astype(np.int64), A.astype(np.int64) @ B.astype(np.int64))
 
 
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3", "bf16x6", "fp16x3"])
+@pytest.mark.parametrize("n,depth,r", [(17, 2, 1), (23, 1, 7), (71, 3, 7), (127, 2, 63), (9, 0, 1), (50, 1, 2)])
+def test_peel_model_exact_on_small_integers(mode, n, depth, r):
+    """Core by the recursion, border and fix-up classical: on integers the
+    peeled model is the exact product (a dropped fix-up term, a border
+    computed over the core only or a wrong core offset would not be)."""
+    A = inputs.integers(n, 3)
+    B = inputs.integers(n, 4)
+    C = oracle.peel_model_f32(A, B, depth, mode, r)
+    assert np.array_equal(C.astype(np.int64), A.astype(np.int64) @ B.astype(np.int64))
+
+
+def test_peel_model_without_residue_is_the_square_model():
+    A = inputs.uniform(64, 5)
+    B = inputs.uniform(64, 6)
+    for mode in ("fp32", "bf16x3", "fp16x3"):
+        assert np.array_equal(oracle.peel_model_f32(A, B, 2, mode, 0), oracle.strassen_model_f32(A, B, 2, mode, 64))
+
+
+def test_peel_model_float_error_is_the_cores():
+    """On floats the peeled model sits within binary32 rounding of the exact
+    product: its border is exact rounded once, its core the square model's."""
+    A = inputs.uniform(131, 7)
+    B = inputs.uniform(131, 8)
+    exact = oracle.gemm_f64(A, B)
+    C = oracle.peel_model_f32(A, B, 2, "fp32", 3)
+    assert oracle.rel_frobenius(C, exact) < 1e-6
+    # border entries: each the rounded exact inner product
+    assert np.array_equal(C[128:, :], exact[128:, :].astype(np.float32))
+    assert np.array_equal(C[:128, 128:], exact[:128, 128:].astype(np.float32))
+
+
 def test_model_fp32_depth0_is_rounded_classical():
     A = inputs.uniform(48, 3)
     B = inputs.uniform(48, 4)
