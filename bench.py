@@ -68,6 +68,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-serving", action="store_true")
     p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-peeling", action="store_true", help="skip the peeled-against-padded leg")
     p.add_argument("--batched-only", action="store_true",
                    help="only run the batched workload, print its JSON object and exit")
     p.add_argument("--serving-only", action="store_true",
@@ -532,6 +533,48 @@ def main() -> int:
         compare["torch_matmul_fp32_external"] = {"ms": m_, "tflops": 2.0 * n ** 3 / (m_ * 1e-3) * 1e-12,
                                                  "freivalds": freivalds()}
 
+    # -- sizes off the 64 * 2^depth grid: peeled against zero-padded ----------------
+    # n + 1 and n + 64 at the headline's precision and depth; the operands hold
+    # the headline A and B in their leading n x n block and normal(0,1) values
+    # from torch's seeded device generator in the border
+    peeling = {}
+    if not args.no_peeling:
+        gen = torch.Generator(device=dev)
+        for m in (n + 1, n + 64):
+            gen.manual_seed(m)
+            Am = torch.randn(m, m, generator=gen, device=dev)
+            Bm = torch.randn(m, m, generator=gen, device=dev)
+            Am[:n, :n] = A
+            Bm[:n, :n] = B
+            Cm = torch.empty((m, m), dtype=torch.float32, device=dev)
+            xm = torch.randn(m, generator=gen, device=dev, dtype=torch.float64)
+            ym = [torch.empty(m, dtype=torch.float64, device=dev) for _ in range(3)]
+            S.stark_matvec_f64(Bm, xm, ym[0], m, st)
+            S.stark_matvec_f64(Am, ym[0], ym[1], m, st)
+            row = {"n": m, "depth": depth, "precision": hname}
+            for mode, flag in (("peeled", S.STARK_PEEL), ("padded", S.STARK_PAD)):
+                pm = prec | flag
+                pl = S.stark_plan_info(m, depth, pm)
+                for _ in range(2):
+                    S.stark_gemm(ctx, Am, Bm, Cm, m, depth, pm, st)
+                te = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                te[0].record(st)
+                for _ in range(3):
+                    S.stark_gemm(ctx, Am, Bm, Cm, m, depth, pm, st)
+                te[1].record(st)
+                te[1].synchronize()
+                tm = te[0].elapsed_time(te[1]) / 3
+                S.stark_matvec_f64(Cm, xm, ym[2], m, st)
+                st.synchronize()
+                fv = float(torch.linalg.norm(ym[2] - ym[1]) / torch.linalg.norm(ym[1]))
+                row[mode] = {"ms": tm, "tflops": 2.0 * m ** 3 / (tm * 1e-3) * 1e-12, "peel": pl.peel,
+                             "n_pad": pl.n_pad, "gemm_tile": pl.gemm_tile, "freivalds": fv}
+                log(f"  n={m} {mode}: residue {pl.peel}, core/padded edge {pl.n_pad}, tile {pl.gemm_tile}: "
+                    f"{tm:.3f} ms, {row[mode]['tflops']:.1f} TF/s, freivalds {fv:.2e}")
+            row["default"] = "peeled" if S.stark_plan_info(m, depth, prec).peel else "padded"
+            peeling[str(m)] = row
+            del Am, Bm, Cm
+
     # -- CPU baseline: the oracle on a bounded sample of rows -----------------------
     # (the error-check rows plus more rows, about 10 s of host work in total),
     # and the Table V analog (full FP64 products at smaller n)
@@ -585,7 +628,7 @@ def main() -> int:
                                          "tune": None if bf is None else bf["tune"]})},
         "tune": {k: [{"depth": a, "ms": b, "err": c, "tile": t} for a, b, c, t in v] for k, v in tuned.items()},
         "phases": phases, "phase_table": phase_table, "roofline": roofline, "cpu_baseline": cpu,
-        "compare": compare, "batched": batched,
+        "compare": compare, "peeling": peeling, "batched": batched,
         # the paper's own figure for this size (distributed Spark, FP64; another machine): context only
         "paper_context": {"n": 16384, "stark_wall_clock_s": 161.0, "effective_tflops": 2.0 * 16384 ** 3 / 161.0 * 1e-12,
                           "source": "Fig. 6 and Table V (fastest partition, b = 16)",

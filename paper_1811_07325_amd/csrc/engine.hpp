@@ -1,10 +1,11 @@
 // Serving engine: continuous batching of independent multiply requests.
 //
 // Requests arrive through stark_submit (any thread) into a queue.  An engine
-// thread admits them in arrival order whenever a slot (a HIP stream of its
-// own) is free and the request's device footprint fits the remaining HBM
-// budget; a request that does not fit lets at most kMaxBypass later, smaller
-// requests go first, so nothing starves.  Admitted requests run concurrently
+// thread admits them whenever a slot (a HIP stream of its own) is free and
+// the request's device footprint fits the remaining HBM budget: smallest
+// modelled time first (requests that have waited long first of all), at most
+// one large request in flight; a request that does not fit lets at most
+// kMaxBypass others go first, so nothing starves.  Admitted requests run concurrently
 // on their slot streams; completion is observed with HIP events and frees the
 // slot and the memory for the next arrivals.  Each request's kernels and
 // their order are fixed by its plan, so its result does not depend on what
@@ -90,6 +91,7 @@ private:
         bool gen = false, own_c = false;
         int slot = -1;
         double t_submit = 0, t_admit = 0, t_done = 0;
+        double cost_s = 0;            // modelled time on an idle device (model_seconds)
         stark_status status = STARK_OK;
         double checksum = 0;
         float gpu_ms = 0;
@@ -135,6 +137,14 @@ private:
     // large request's GEMM does not hold every CU until it ends
     // (STARK_SERVE_PERSISTENT=1: the persistent grid of stark_gemm)
     bool persistent_ = false;
+    // Admission (sched.hpp): by default the size-aware order (requests that
+    // waited longer than aging_ms first, then by modelled time) and at most
+    // one large request (modelled time >= 2 ms) in flight; STARK_SERVE_FIFO=1
+    // admits in arrival order with no cap.  STARK_SERVE_AGING_MS,
+    // STARK_SERVE_LARGE_MS and STARK_SERVE_LARGE_CAP override the defaults.
+    bool fifo_ = false;
+    double aging_ms_ = 25.0;
+    LargeCap large_{2e-3, 1};
 };
 
 double now_us();

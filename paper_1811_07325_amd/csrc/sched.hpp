@@ -1,7 +1,8 @@
 // Host-only parts of the serving engine, free of device calls so that they
 // can be tested on any machine: the first-fit arena that places requests in
-// device memory, the percentile rule of the latency statistics, and one
-// admission pass of the scheduler.
+// device memory, the percentile rule of the latency statistics, one
+// admission pass of the scheduler, and the size-aware order and large-request
+// cap it runs with by default.
 #pragma once
 #include <stddef.h>
 
@@ -118,5 +119,31 @@ int admission_pass(std::deque<Req*>& waiting, SlotFree slot_free, Take take, int
     }
     return removed;
 }
+
+// Size-aware admission order (applied before each admission pass):
+// requests that have waited longer than `aging` first, oldest first, so none
+// waits for ever; the others by ascending modelled cost, ties in arrival
+// order.  Small requests then no longer queue behind large ones.
+template <class Req, class Arrival, class Cost>
+void order_waiting(std::deque<Req*>& waiting, double now, double aging, Arrival arrival, Cost cost) {
+    std::stable_sort(waiting.begin(), waiting.end(), [&](const Req* a, const Req* b) {
+        const bool oa = now - arrival(a) > aging, ob = now - arrival(b) > aging;
+        if (oa != ob) return oa;
+        if (oa) return arrival(a) < arrival(b);
+        return cost(a) < cost(b);
+    });
+}
+
+// At most `cap` requests whose modelled cost reaches `threshold` in flight:
+// a large request's kernels then share the device with small ones only, and
+// large requests queue for each other instead of stretching each other's
+// service time.
+struct LargeCap {
+    double threshold = 0;
+    int cap = 1;
+    int inflight = 0;
+    bool large(double cost) const { return cost >= threshold; }
+    bool admits(double cost) const { return !large(cost) || inflight < cap; }
+};
 
 }  // namespace stk

@@ -83,6 +83,10 @@ Engine::Engine(stark_ctx* ctx, size_t budget, int slots, hipError_t* err) : ctx_
     }
     if (const char* f = std::getenv("STARK_FAULT_INJECT")) fault_tag_ = std::atoll(f);
     if (const char* f = std::getenv("STARK_SERVE_PERSISTENT")) persistent_ = std::atoi(f) != 0;
+    if (const char* f = std::getenv("STARK_SERVE_FIFO")) fifo_ = std::atoi(f) != 0;
+    if (const char* f = std::getenv("STARK_SERVE_AGING_MS")) aging_ms_ = std::atof(f);
+    if (const char* f = std::getenv("STARK_SERVE_LARGE_MS")) large_.threshold = std::atof(f) * 1e-3;
+    if (const char* f = std::getenv("STARK_SERVE_LARGE_CAP")) large_.cap = std::max(1, std::atoi(f));
 
     thread_ = std::thread([this] { loop(); });
 }
@@ -143,6 +147,7 @@ stark_status Engine::submit(const stark_request& r, uint64_t* ticket) {
     const std::string why = make_plan(r.n, depth, (int)r.precision, q->plan, tile);
     if (!why.empty()) { set_error("%s", why.c_str()); return STARK_EINVAL; }
     q->bytes = request_footprint(q->plan, q->gen, q->own_c);
+    q->cost_s = model_seconds(q->plan);
     if (q->bytes > mem_.budget()) {
         set_error("request needs %zu bytes, budget is %zu", q->bytes, mem_.budget());
         return STARK_ENOMEM;
@@ -221,6 +226,8 @@ void Engine::publish_failure(Req* q, stark_status status) {
 }
 
 bool Engine::admit(Req* q, int si) {
+    const bool big = large_.large(q->cost_s);
+    if (!fifo_ && !large_.admits(q->cost_s)) return false;
     size_t off;
     int seg;
     const SegmentedArena::Result got = mem_.alloc(q->bytes, inflight_ == 0, &seg, &off);
@@ -237,6 +244,7 @@ bool Engine::admit(Req* q, int si) {
     s.busy = true;
     s.req = q;
     ++inflight_;
+    if (big) ++large_.inflight;
     {
         std::lock_guard<std::mutex> lk(mu_);
         if (first_admit_ < 0) first_admit_ = q->t_admit;
@@ -285,6 +293,7 @@ bool Engine::admit(Req* q, int si) {
         s.busy = false;
         s.req = nullptr;
         --inflight_;
+        if (big) --large_.inflight;
         publish_failure(q, rc != STARK_OK ? rc : STARK_EDEVICE);
     }
     return true;
@@ -300,6 +309,7 @@ void Engine::finish(int si) {
     s.busy = false;
     s.req = nullptr;
     --inflight_;
+    if (large_.large(q->cost_s)) --large_.inflight;
     std::lock_guard<std::mutex> lk(mu_);
     q->gpu_ms = ms;
     q->checksum = checksum;
@@ -346,13 +356,14 @@ void Engine::loop() {
                 slots_[si].busy = false;
                 slots_[si].req = nullptr;
                 --inflight_;
+                if (large_.large(q->cost_s)) --large_.inflight;
                 (void)hipGetLastError();
                 publish_failure(q, STARK_EDEVICE);
                 progress = true;
             }
         }
-        // admissions: arrival order, requests that do not fit passed over a
-        // bounded number of times (sched.hpp)
+        // admissions: size-aware order (or arrival order), requests that do
+        // not fit passed over a bounded number of times (sched.hpp)
         int free_slot = -1;
         auto slot_free = [&] {
             free_slot = -1;
@@ -360,6 +371,9 @@ void Engine::loop() {
                 if (!slots_[si].busy) { free_slot = si; break; }
             return free_slot >= 0;
         };
+        if (!fifo_ && waiting_.size() > 1)
+            order_waiting(waiting_, now_us(), aging_ms_ * 1e3, [](const Req* q) { return q->t_submit; },
+                          [](const Req* q) { return q->cost_s; });
         if (admission_pass(waiting_, slot_free, [&](Req* q) { return admit(q, free_slot); }, kMaxBypass,
                            kMaxHeadPasses) > 0)
             progress = true;

@@ -12,6 +12,13 @@
 //   starvation a large request behind a steady stream of small ones runs
 //              after a bounded wait; with the head rule disabled only once
 //              the stream has stopped
+//   sizeaware  the default order (aged requests first, oldest first, then
+//              ascending cost) with at most one large request in flight:
+//              the queue is in that order before every pass, the cap and
+//              the memory and slot limits hold, every request completes,
+//              no request waits much beyond the aging bound plus one large
+//              service, and small requests wait less than in arrival order
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -198,12 +205,124 @@ static int test_starvation() {
     return 0;
 }
 
+// Cost-aware simulation: service time doubles as the modelled cost; the
+// queue is ordered by order_waiting before every pass (fifo: not at all) and
+// large requests (cost >= large.threshold) are capped by `large`.
+struct PolicyResult {
+    bool ok = true;
+    const char* why = "";
+    int completed = 0;
+    double small_wait = 0, max_wait = 0, max_aged_wait = 0;
+};
+
+static PolicyResult simulate_policy(std::vector<Req>& reqs, size_t budget, int slots, double dt, double aging,
+                                    stk::LargeCap large, bool fifo) {
+    PolicyResult r;
+    Arena arena(budget);
+    std::deque<Req*> waiting;
+    std::vector<Req*> running;
+    size_t next = 0;
+    int nsmall = 0;
+    auto arrival = [](const Req* q) { return q->arrive; };
+    auto cost = [](const Req* q) { return q->service; };
+    for (double now = 0; now < 1e7; now += dt) {
+        for (auto it = running.begin(); it != running.end();) {
+            if ((*it)->admit + (*it)->service <= now) {
+                (*it)->done = now;
+                arena.free((*it)->off, (*it)->bytes);
+                if (large.large((*it)->service)) --large.inflight;
+                ++r.completed;
+                it = running.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        while (next < reqs.size() && reqs[next].arrive <= now) waiting.push_back(&reqs[next++]);
+        if (!fifo) {
+            stk::order_waiting(waiting, now, aging, arrival, cost);
+            for (size_t i = 1; i < waiting.size(); ++i) {   // aged first (oldest first), then by cost
+                const Req *a = waiting[i - 1], *b = waiting[i];
+                const bool oa = now - a->arrive > aging, ob = now - b->arrive > aging;
+                if ((!oa && ob) || (oa && ob && a->arrive > b->arrive) || (!oa && !ob && a->service > b->service)) {
+                    r.ok = false;
+                    r.why = "sizeaware: queue not in the size-aware order";
+                    return r;
+                }
+            }
+        }
+        auto slot_free = [&] { return (int)running.size() < slots; };
+        auto take = [&](Req* q) {
+            if (!fifo && !large.admits(q->service)) return false;
+            size_t off;
+            if (!arena.alloc(q->bytes, &off)) return false;
+            q->off = off;
+            q->admit = now;
+            if (large.large(q->service)) ++large.inflight;
+            const double w = now - q->arrive;
+            r.max_wait = std::max(r.max_wait, w);
+            if (!large.large(q->service)) { r.small_wait += w; ++nsmall; }
+            running.push_back(q);
+            return true;
+        };
+        stk::admission_pass(waiting, slot_free, take, 8, 1000);
+        if (arena.used() > budget) { r.ok = false; r.why = "sizeaware: memory budget exceeded"; }
+        if ((int)running.size() > slots) { r.ok = false; r.why = "sizeaware: more requests than slots"; }
+        if (!fifo && large.inflight > large.cap) { r.ok = false; r.why = "sizeaware: large-request cap exceeded"; }
+        if (!r.ok) return r;
+        if (next == reqs.size() && waiting.empty() && running.empty()) break;
+    }
+    if (nsmall) r.small_wait /= nsmall;
+    return r;
+}
+
+static int test_size_aware() {
+    // heavy-tailed service times: small requests log-uniform over
+    // 0.01 .. 1, about 3 % large ones over 1 .. 3; four slots about 70 %
+    // busy, the large requests alone about 55 % of one slot (their queue is
+    // stable with the cap of one)
+    auto make = [] {
+        std::mt19937_64 rng(11);
+        std::vector<Req> reqs;
+        double t = 0;
+        const size_t unit = 256 * 1024;
+        std::uniform_real_distribution<double> u(0.0, 1.0);
+        for (int i = 0; i < 3000; ++i) {
+            t += std::exponential_distribution<double>(10.8)(rng);
+            const bool large = u(rng) < 0.028;
+            const double lo = large ? 1.0 : 0.01, hi = large ? 3.0 : 1.0;
+            const double svc = std::exp(std::log(lo) + u(rng) * (std::log(hi) - std::log(lo)));
+            reqs.push_back({i, (size_t)(1 + svc * 60) * unit, t, svc});
+        }
+        return reqs;
+    };
+    stk::LargeCap cap;
+    cap.threshold = 1.0;
+    cap.cap = 1;
+    const double aging = 5.0;
+    std::vector<Req> sa = make(), ff = make();
+    PolicyResult a = simulate_policy(sa, 1000 * 256 * 1024, 4, 0.01, aging, cap, false);
+    if (!a.ok) return fail(a.why);
+    PolicyResult f = simulate_policy(ff, 1000 * 256 * 1024, 4, 0.01, aging, cap, true);
+    if (!f.ok) return fail(f.why);
+    if (a.completed != (int)sa.size() || f.completed != (int)ff.size()) return fail("sizeaware: not every request completed");
+    // a request waits at most the aging bound, then behind the older aged
+    // requests and (large ones) behind the one large request in flight
+    double longest = 0;
+    for (const Req& q : sa) longest = std::max(longest, q.service);
+    if (a.max_wait > 3 * (aging + longest)) return fail("sizeaware: a request waited far beyond the aging bound");
+    if (!(a.small_wait < f.small_wait)) return fail("sizeaware: small requests do not wait less than in arrival order");
+    std::printf("sizeaware ok: mean small-request wait %.3f (arrival order %.3f), longest wait %.2f (aging %.1f)\n",
+                a.small_wait, f.small_wait, a.max_wait, aging);
+    return 0;
+}
+
 int main() {
     int rc = 0;
     rc |= test_arena();
     rc |= test_percentile();
     rc |= test_mixed();
     rc |= test_starvation();
+    rc |= test_size_aware();
     if (rc == 0) std::printf("all ok\n");
     return rc;
 }

@@ -8,7 +8,11 @@ and slot limits hold at every step, a request only overtakes older ones that
 were offered in the same pass and did not fit, and every request completes;
 a large request behind a steady stream of small ones is admitted after a
 bounded number of passes, and with that rule switched off only once the
-stream stops.
+stream stops; the default size-aware order (aged requests first, then by
+modelled cost) with at most one large request in flight keeps its order,
+its cap and the limits, completes every request within the aging bound
+plus a few large services, and cuts the small requests' mean wait below
+that of arrival order.
 """
 import os
 import shutil
