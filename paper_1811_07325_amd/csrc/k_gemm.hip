@@ -514,9 +514,12 @@ __global__ __launch_bounds__(SmallCfg<P>::NT) void k_gemm_bf16_small(Src src, in
 // ---------------------------------------------------------------------------
 // binary32 leaf GEMM: BM x BN block tile (256 x 256 with 8 waves of 128 x 64
 // for large leaves; 128 x 128 or 64 x 64 with 4 waves otherwise), K steps of
-// 16, three LDS stages filled by direct global->LDS loads straight from the
+// 16, two LDS stages filled by direct global->LDS loads straight from the
 // binary32 operands (views included: leading dimension from the recursion),
-// no register staging.
+// no register staging.  Measured for the 256-wide tile at n = 16384: two
+// stages 43.2 ms (depth 3) and 63.0 ms (depth 0), three 45.1 / 65.7, four
+// 44.1 / 64.5; for the 128-wide tile at n = 2048, depth 1: two 0.154 ms,
+// three 0.164, four 0.153.
 //   A stage image: [BM rows][4 chunks of 4 k], chunk position c ^ blk_swz(row
 //     mod 16) (as the 16-bit blocked layout), one load = one 16-row block.
 //   B stage image: [16 k][BN/4 chunks of 4 n], chunk position c ^ f32_bswz(k),
@@ -537,12 +540,15 @@ struct F32CfgT {
     static constexpr int NW = WAVES_M * WAVES_N, NT = 64 * NW;
 };
 #ifndef STK_F32_STAGES
-#define STK_F32_STAGES 3
+#define STK_F32_STAGES 2
+#endif
+#ifndef STK_F32_SMALL_STAGES
+#define STK_F32_SMALL_STAGES 2
 #endif
 using F32BigCfg = F32CfgT<256, 256, 2, 4, STK_F32_STAGES>;   // 8 waves of 128 x 64, 32 KB LDS per stage
 using F32FusedCfg = F32CfgT<256, 256, 2, 4, 2>;  // the same with fused leaf operands, 128 KB LDS
-using F32MidCfg = F32CfgT<128, 128, 2, 2, 3>;    // 4 waves of 64 x 64, 48 KB LDS
-using F32SmallCfg = F32CfgT<64, 64, 2, 2, 3>;    // 4 waves of 32 x 32, 24 KB LDS
+using F32MidCfg = F32CfgT<128, 128, 2, 2, STK_F32_SMALL_STAGES>;    // 4 waves of 64 x 64, 16 KB per stage
+using F32SmallCfg = F32CfgT<64, 64, 2, 2, STK_F32_SMALL_STAGES>;    // 4 waves of 32 x 32, 8 KB per stage
 static_assert(F32BigCfg::NT == kF32BigThreads, "thread count of the 256-wide kernel");
 
 // Leaf operand of leaf `leaf` formed inside the binary32 leaf GEMM (plans
