@@ -549,6 +549,9 @@ def main() -> int:
             Cm = torch.empty((m, m), dtype=torch.float32, device=dev)
             xm = torch.randn(m, generator=gen, device=dev, dtype=torch.float64)
             ym = [torch.empty(m, dtype=torch.float64, device=dev) for _ in range(3)]
+            # the operands are filled on torch's stream; the library's calls
+            # below run on `st`, which does not wait for it
+            torch.cuda.synchronize()
             S.stark_matvec_f64(Bm, xm, ym[0], m, st)
             S.stark_matvec_f64(Am, ym[0], ym[1], m, st)
             row = {"n": m, "depth": depth, "precision": hname}

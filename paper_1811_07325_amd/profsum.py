@@ -111,7 +111,8 @@ def traffic_table_md(copy_fetch: str, copy_write: str, copy_bytes: float, run_fe
 
 def mfma_md(path: str, name_part: str, simds: int, xccs: int, title: str, commands: list[str]) -> str:
     """Matrix-core counters of one kernel per dispatch: hardware flops
-    (SQ_INSTS_VALU_MFMA_MOPS_BF16 + _F16, whichever were collected, x 512),
+    (SQ_INSTS_VALU_MFMA_MOPS_BF16 + _F16 + _F32, whichever were collected,
+    x 512),
     MFMA busy fraction
     (SQ_VALU_MFMA_BUSY_CYCLES summed over SIMDs / (active cycles per XCC x
     SIMDs); GRBM_GUI_ACTIVE is reported summed over the XCCs) and the average
@@ -127,7 +128,8 @@ def mfma_md(path: str, name_part: str, simds: int, xccs: int, title: str, comman
     for k in sorted(per):
         e = per[k]
         cyc = e["GRBM_GUI_ACTIVE"] / xccs
-        mops = e.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) + e.get("SQ_INSTS_VALU_MFMA_MOPS_F16", 0.0)
+        mops = (e.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) + e.get("SQ_INSTS_VALU_MFMA_MOPS_F16", 0.0) +
+                e.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0))
         out.append(f"| {k} | {e['ns'] / 1e6:.3f} | {mops * 512:.4e} | "
                    f"{e['SQ_VALU_MFMA_BUSY_CYCLES'] / (cyc * simds):.3f} | {cyc / e['ns']:.2f} |")
     return "\n".join(out) + "\n"
