@@ -214,6 +214,27 @@ def test_serving_alone_vs_mix_bitwise(S):
         S.stark_destroy(c)
 
 
+def test_serving_peeled_sizes_equal_single_calls(S):
+    """Served requests of sizes off the grid run the plan the planner gives
+    them (peeled here: residues 1, 7 and 63 with STARK_PEEL), alone and
+    together, and equal stark_gemm with that plan bit for bit."""
+    c = S.stark_create(0, hbm_budget_bytes=8 << 30, max_slots=4)
+    try:
+        cases = [(2049, 2, 0 | 64), (1031, 1, 1 | 64), (1087, 1, 3 | 64), (4097, 2, 0)]
+        assert [S.stark_plan_info(n, d, p).peel for n, d, p in cases] == [1, 7, 63, 1]
+        ops = [(dev(inputs.normal(n, 300 + i)), dev(inputs.normal(n, 400 + i))) for i, (n, _, _) in enumerate(cases)]
+        outs = [torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda") for n, _, _ in cases]
+        torch.cuda.synchronize()
+        tickets = [S.stark_submit(c, n, p, d, dA, dB, C, tag=i)
+                   for i, ((n, d, p), (dA, dB), C) in enumerate(zip(cases, ops, outs))]
+        res = wait(S, c, tickets)
+        assert all(r.status == S.STARK_OK for r in res.values())
+        for (n, d, p), (dA, dB), C in zip(cases, ops, outs):
+            assert np.array_equal(C.cpu().numpy(), single(S, c, dA, dB, n, d, p))
+    finally:
+        S.stark_destroy(c)
+
+
 def test_serving_generated_operands_and_checksums(S):
     c = S.stark_create(0, hbm_budget_bytes=8 << 30, max_slots=4)
     try:

@@ -1,8 +1,9 @@
 """stark_gemm_noalloc, the allocation-free entry point, through the C ABI:
 its results equal stark_gemm's at the same depth (same kernels and plan, its
 intermediates in the library's fixed device scratch instead of a context
-workspace), on two calls in a row with the second smaller, and a plan that
-does not fit the scratch is refused before anything runs."""
+workspace), on two calls in a row with the second smaller (peeled sizes
+included), and a plan that does not fit the scratch is refused before
+anything runs."""
 import numpy as np
 import pytest
 
@@ -23,14 +24,17 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-@pytest.mark.parametrize("first,second", [((1024, 2, "fp16x3"), (640, 1, "bf16x3")),
-                                          ((1000, 2, "fp32"), (300, 1, "fp32_winograd"))])
+# (n, depth, precision, flags): the last pair peels (STARK_PEEL: residues 7, 1)
+@pytest.mark.parametrize("first,second", [((1024, 2, "fp16x3", 0), (640, 1, "bf16x3", 0)),
+                                          ((1000, 2, "fp32", 0), (300, 1, "fp32_winograd", 0)),
+                                          ((1031, 1, "fp16x3", 64), (1025, 1, "fp32", 64))])
 def test_noalloc_equals_gemm_on_two_calls(S, first, second):
     ctx = S.stark_create(0)
     try:
-        for n, depth, prec in (first, second):
-            print(f"case n={n} depth={depth} prec={prec}", flush=True)
-            p = S.PRECISIONS[prec]
+        for n, depth, prec, flags in (first, second):
+            print(f"case n={n} depth={depth} prec={prec} flags={flags}", flush=True)
+            p = S.PRECISIONS[prec] | flags
+            assert S.stark_plan_info(n, depth, p).peel == (n % (64 << depth) if flags else 0)
             assert S.stark_workspace_size(n, depth, p) <= S.STARK_NOALLOC_SCRATCH_BYTES
             A, B = inputs.normal(n, 60 + n), inputs.normal(n, 61 + n)
             dA, dB = dev(A), dev(B)
