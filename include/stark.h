@@ -105,11 +105,12 @@ typedef enum {
      * border rows and columns of C are classical binary32 inner products,
      * and every core output takes the r products through A's peeled columns
      * and B's peeled rows when the last combine level writes it.  Or A and B
-     * are zero-padded to the next multiple (on the fly: level 0 reads them
-     * with bounds) and C is cropped.  By default the planner takes the one
-     * its time model finds faster; STARK_PEEL peels whenever possible,
-     * STARK_PAD always pads, and giving both is an error.  stark_plan_info
-     * reports the residue a plan peels. */
+     * are zero-padded to a multiple of 64, 128 or 256 times 2^depth (on the
+     * fly: level 0 reads them with bounds) and C is cropped.  By default the
+     * planner takes the candidate its time model finds fastest; STARK_PEEL
+     * peels whenever possible, STARK_PAD always pads, and giving both is an
+     * error.  stark_plan_info reports the residue a plan peels and the
+     * padded (or core) edge n_pad. */
     STARK_PEEL = 64,
     STARK_PAD = 128
 } stark_precision;

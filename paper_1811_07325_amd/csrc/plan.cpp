@@ -76,45 +76,78 @@ int planes_for(int precision) {
 
 static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
+// One candidate plan: the residue `peel` peeled off (0: none), otherwise n
+// zero-padded to a multiple of granule * 2^depth.  Arguments already checked.
+static std::string build_plan(int64_t n, int depth, int precision, Plan& p, int tile, int peel, int64_t granule);
+
 std::string make_plan(int64_t n, int depth, int precision, Plan& p, int tile) {
     p = Plan();
     if (n <= 0) return "n must be positive";
     if (n > (int64_t)1 << 20) return "n too large";
     if (depth < 0 || depth > max_depth_for(n)) return "depth out of range for n";
+    if (planes_for(precision) < 0) return "unknown precision";
+    if ((precision & STARK_PEEL) && (precision & STARK_PAD)) return "STARK_PEEL and STARK_PAD exclude each other";
+    // Sizes off the grid of the leaf GEMM's tiles.  Candidates: peel the
+    // residue r = n mod 64 * 2^depth (the recursion runs on the leading
+    // (n - r)^2 core in place; border and fix-up are classical; r <= 64), or
+    // zero-pad to a multiple of G * 2^depth for a tile edge G of 64, 128 or
+    // 256 (a wider tile class needs a leaf it divides; at most a quarter more
+    // edge than the 64-multiple).  Peeling reads A and B once more for the
+    // border and multiplies 2 r n (2n - r) more on the vector units; padding
+    // adds the padded edge's share of the recursion's work.  The candidate of
+    // least modelled time is taken (STARK_PEEL: the peeled one when there is
+    // one; STARK_PAD: only padded ones); a forced tile class must divide the
+    // leaf of the candidate.
+    const int64_t g = kLeafGranule << depth;
+    const int64_t r = n % g;
+    const bool can_peel = depth >= 1 && r >= 1 && r <= kPeelMaxResidue && n - r >= g;
+    const int64_t pad_limit = (5 * padded_size(n, depth)) / 4;   // at most a quarter more edge
+    std::string first_error;
+    bool have = false;
+    double best = 0.0;
+    auto consider = [&](int peel, int64_t granule) {
+        Plan c;
+        const std::string e = build_plan(n, depth, precision, c, tile, peel, granule);
+        if (!e.empty()) {
+            if (first_error.empty()) first_error = e;
+            return;
+        }
+        const double t = model_seconds(c);
+        if (!have || t < best) {
+            p = c;
+            best = t;
+            have = true;
+        }
+    };
+    if (can_peel && !(precision & STARK_PAD)) consider((int)r, 0);
+    if (!(can_peel && (precision & STARK_PEEL))) {
+        int64_t last = -1;
+        for (int64_t granule : {kLeafGranule, 2 * kLeafGranule, 4 * kLeafGranule}) {
+            const int64_t q = granule << depth;
+            const int64_t np = (n + q - 1) / q * q;
+            if (np == last || (granule > kLeafGranule && np > pad_limit)) continue;
+            last = np;
+            consider(0, granule);
+        }
+    }
+    return have ? "" : first_error;
+}
+
+static std::string build_plan(int64_t n, int depth, int precision, Plan& p, int tile, int peel, int64_t granule) {
+    p = Plan();
     const int planes = planes_for(precision);
-    if (planes < 0) return "unknown precision";
     p.n = n;
     p.depth = depth;
     p.precision = precision;
     p.variant = (precision & STARK_WINOGRAD) ? 1 : 0;
     p.planes = planes;
-    if ((precision & STARK_PEEL) && (precision & STARK_PAD)) return "STARK_PEEL and STARK_PAD exclude each other";
-    // Sizes off the 64 * 2^depth grid: peel the residue r (the recursion
-    // runs on the leading (n - r)^2 core in place; border and fix-up are
-    // classical) or zero-pad to the next multiple.  Peeling reads A and B
-    // once more for the border and multiplies 2 r n (2n - r) more on the
-    // vector units; padding adds about 3 (64 * 2^depth - r) / n of the
-    // recursion's work and can leave leaves whose edge no wide tile class
-    // divides.  Without STARK_PEEL or STARK_PAD the modelled faster one is
-    // taken.
-    {
-        const int64_t g = kLeafGranule << depth;
-        const int64_t r = n % g;
-        const bool can = depth >= 1 && r >= 1 && r <= kPeelMaxResidue && n - r >= g;
-        if (can && !(precision & (STARK_PEEL | STARK_PAD))) {
-            // (a forced tile class must divide the leaf of the plan taken)
-            Plan peeled, padded;
-            const std::string e1 = make_plan(n, depth, precision | STARK_PEEL, peeled, tile);
-            const std::string e2 = make_plan(n, depth, precision | STARK_PAD, padded, tile);
-            if (!e1.empty() && !e2.empty()) return e1;
-            if (e2.empty() && (!e1.empty() || model_seconds(padded) < model_seconds(peeled))) p = padded;
-            else p = peeled;
-            p.precision = precision;
-            return "";
-        }
-        if (can && (precision & STARK_PEEL)) p.peel = (int)r;
+    p.peel = peel;
+    if (peel) {
+        p.np = n - peel;
+    } else {
+        const int64_t q = granule << depth;
+        p.np = (n + q - 1) / q * q;
     }
-    p.np = p.peel ? n - p.peel : padded_size(n, depth);
     p.leaf = p.np >> depth;
     // level 0 reads A, B (and writes C) element by element with bounds: the
     // user matrices of a padded size are smaller than np, and the rows of a

@@ -148,24 +148,30 @@ def test_plan_layout(S, n, depth, prec):
 def test_peel_rule(S):
     """Residues r = n mod (64 * 2^depth) up to 64 can be peeled: always with
     STARK_PEEL, never with STARK_PAD, and by default when the planner's time
-    model finds it faster (at n = 16384 + r padding leaves leaves of edge
-    4096 + 64, which only the 64-wide tiles divide, so every r peels; at
-    n = 1087, depth 1, the 64-wide tiles run either way and padding costs
-    less); depth 0 and sizes below one granule always pad; the peeled core
-    needs the workspace of its own size (level 0 read element by element,
-    so all seven operands stored)."""
+    model finds it faster than every padded plan (padding to a multiple of
+    64, 128 or 256 times 2^depth); at n = 16384 + r the padded plans do more
+    work or run narrower tiles, so every r <= 64 peels; at n = 1087, depth 1,
+    the 64-wide tiles run either way and padding costs less; depth 0 and
+    sizes below one granule always pad; the peeled core needs the workspace
+    of its own size (level 0 read element by element, so all seven operands
+    stored)."""
     P = lambda n, depth, flags=0: S.stark_plan_info(n, depth, flags)
     assert (P(16385, 2).peel, P(16385, 2).n_pad) == (1, 16384)
     assert (P(16391, 2).peel, P(16391, 2).n_pad) == (7, 16384)
     assert (P(16448, 2).peel, P(16448, 2).n_pad) == (64, 16384)
-    assert (P(16448, 2, S.STARK_PAD).peel, P(16448, 2, S.STARK_PAD).n_pad) == (0, 16640)
-    assert P(16448, 2, S.STARK_PAD).gemm_tile == 64 and P(16448, 2).gemm_tile == 256
+    # padded, the planner takes a multiple of 256 * 2^depth: leaves the
+    # 256-wide tiles divide (a multiple of 64 * 2^depth, 16640, would leave
+    # leaves of 4160 for the 64-wide tiles)
+    assert (P(16448, 2, S.STARK_PAD).peel, P(16448, 2, S.STARK_PAD).n_pad) == (0, 17408)
+    assert P(16448, 2, S.STARK_PAD).gemm_tile == 256 and P(16448, 2).gemm_tile == 256
+    assert (P(16500, 2).peel, P(16500, 2).n_pad, P(16500, 2).gemm_tile) == (0, 17408, 256)   # r = 116
+    assert (P(4032, 0).n_pad, P(4032, 0).gemm_tile) == (4096, 256)
     assert (P(1087, 1).peel, P(1087, 1).n_pad) == (0, 1152)
     assert (P(1087, 1, S.STARK_PEEL).peel, P(1087, 1, S.STARK_PEEL).n_pad) == (63, 1024)
     assert P(16447, 2, S.STARK_PEEL).peel == 63
     assert P(16449, 2, S.STARK_PEEL).peel == 0          # residue 65: padded
-    assert P(16385, 2, S.STARK_PAD).peel == 0 and P(16385, 2, S.STARK_PAD).n_pad == 16640
-    assert P(16385, 0).peel == 0 and P(16385, 0).n_pad == 16448
+    assert P(16385, 2, S.STARK_PAD).peel == 0 and P(16385, 2, S.STARK_PAD).n_pad % 1024 == 0
+    assert P(16385, 0).peel == 0 and P(16385, 0).n_pad in (16448, 16512, 16640)
     assert P(257, 1, S.STARK_PEEL).peel == 1 and P(257, 1, S.STARK_PEEL).n_pad == 256
     assert P(100, 1, S.STARK_PEEL).peel == 0 and P(100, 1).n_pad == 128     # no core of 128 to recurse on
     with pytest.raises(S.StarkError):

@@ -74,6 +74,16 @@ def rel_f(C, ref):
     return oracle.rel_frobenius(C, ref)
 
 
+def plan_model(S, A, B, depth, prec):
+    """The oracle's arithmetic model of the plan the library takes for this
+    size (padded to its n_pad, or peeled), and that plan."""
+    mode, variant = base(prec)
+    d = S.stark_plan_info(A.shape[0], depth, PREC[prec])
+    if d.peel:
+        return oracle.peel_model_f32(A, B, depth, mode, d.peel, variant), d
+    return oracle.strassen_model_f32(A, B, depth, mode, d.n_pad, variant), d
+
+
 # ---------------------------------------------------------------------------
 # Bit-exact integer products (all precisions, padded and ragged sizes).
 # ---------------------------------------------------------------------------
@@ -155,15 +165,14 @@ def test_float_inputs_match_model(S, ctx, n, depth, prec):
     A = inputs.uniform(n, 0)
     B = inputs.uniform(n, 1)
     C = run(S, ctx, A, B, depth, prec)
-    # same zero padding as the library (multiple of 2^depth * 64)
-    mode, variant = base(prec)
-    model = oracle.strassen_model_f32(A, B, depth, mode, oracle.padded_size(n, depth, 64), variant)
+    # the same padding (or peeling) as the library's plan
+    model, plan = plan_model(S, A, B, depth, prec)
     exact = oracle.gemm_f64(A, B)
     e_gpu, e_model = rel_f(C, exact), rel_f(model, exact)
     d = rel_f(C, model)
     print(f"  rel_frob gpu={e_gpu:.3e} model={e_model:.3e} gpu-vs-model={d:.3e}", flush=True)
     # binary32 accumulation over a leaf of edge L: a few units of 2^-24 sqrt(L)
-    L = oracle.padded_size(n, depth, 64) >> depth
+    L = plan.leaf
     assert d <= 4 * 2.0 ** -24 * np.sqrt(L) * 2 ** depth
     assert e_gpu <= 1.5 * e_model + 1e-6
     assert e_gpu <= fixed_bound(prec, depth)
@@ -178,15 +187,14 @@ def test_float_large_tiles_match_model(S, ctx_big, n, depth, prec):
     A = inputs.uniform(n, 0)
     B = inputs.uniform(n, 1)
     C = run(S, ctx_big, A, B, depth, prec)
-    mode, variant = base(prec)
-    model = oracle.strassen_model_f32(A, B, depth, mode, oracle.padded_size(n, depth, 64), variant)
+    model, plan = plan_model(S, A, B, depth, prec)
     rows = inputs.sample_rows(n, 64, 2)
     ref = oracle.rows_f64(A, B, rows)
     e_gpu, e_model = rel_f(C[rows], ref), rel_f(model[rows], ref)
     d = rel_f(C, model)
     print(f"  rel_frob(rows) gpu={e_gpu:.3e} model={e_model:.3e} gpu-vs-model={d:.3e}", flush=True)
     # the model's leaves are exact: the GPU adds binary32 accumulation over L
-    L = oracle.padded_size(n, depth, 64) >> depth
+    L = plan.leaf
     bound = 4 * 2.0 ** -24 * np.sqrt(L) * 2 ** depth
     assert d <= bound
     assert e_gpu <= 1.5 * e_model + bound
@@ -334,7 +342,7 @@ def test_fp16x3_wide_range_inputs_match_model(S, ctx):
     A = (inputs.normal(n, 17) * np.float32(3e4)).astype(np.float32)
     B = (inputs.normal(n, 18) * np.float32(2e-6)).astype(np.float32)
     C = run(S, ctx, A, B, depth, "fp16x3")
-    model = oracle.strassen_model_f32(A, B, depth, "fp16x3", oracle.padded_size(n, depth, 64))
+    model, _ = plan_model(S, A, B, depth, "fp16x3")
     exact = oracle.gemm_f64(A, B)
     assert rel_f(C, model) <= 4 * 2.0 ** -24 * np.sqrt(128) * 4
     assert rel_f(C, exact) < 5e-6

@@ -74,7 +74,7 @@ def test_fp16x3_rows_and_columns_of_many_scales_classical(S, ctx):
     # s <= 20: at least 18 significant bits per operand (38 - 0 - 20)
     assert np.all(e <= 1e-5)
     # same arithmetic as the oracle's model (exact leaf sums, binary32 result)
-    model = oracle.strassen_model_f32(A, B, 0, "fp16x3", oracle.padded_size(n, 0, 64))
+    model = oracle.strassen_model_f32(A, B, 0, "fp16x3", S.stark_plan_info(n, 0, S.STARK_FP16X3).n_pad)
     assert oracle.rel_frobenius(C, model) <= 4 * 2.0 ** -24 * np.sqrt(1024)
 
 
@@ -107,7 +107,8 @@ def test_fp16x3_tiny_matrix_scale_exponent_capped(S, ctx, prec):
     assert np.all(np.isfinite(C))
     variant = "winograd" if prec.endswith("_winograd") else "strassen"
     err = oracle.rel_frobenius(C, oracle.gemm_f64(A, B))
-    model = oracle.strassen_model_f32(A, B, depth, "fp16x3", oracle.padded_size(n, depth, 64), variant)
+    model = oracle.strassen_model_f32(A, B, depth, "fp16x3", S.stark_plan_info(n, depth, S.PRECISIONS[prec]).n_pad,
+                                      variant)
     print(f"{prec} tiny A: rel_frob={err:.3e} vs model {oracle.rel_frobenius(C, model):.3e}")
     assert err <= 1e-5
     assert oracle.rel_frobenius(C, model) <= 4 * 2.0 ** -24 * np.sqrt(256) * 2 ** depth
