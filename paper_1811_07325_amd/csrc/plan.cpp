@@ -23,6 +23,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <stdexcept>
 
 #include "../../include/stark.h"
@@ -324,33 +325,54 @@ Work plan_work(const Plan& p) {
     return w;
 }
 
-double model_seconds(const Plan& p) {
+ModelParts model_parts(const Plan& p) {
     const Work w = plan_work(p);
     const bool split = p.planes > 0;
-    const double rate = split ? (p.tile == 256 ? 1.40e15 : p.tile == 128 ? 0.80e15 : 0.70e15)
-                              : (p.tile == 256 ? 117e12 : p.tile == 128 ? 103e12 : 80e12);
+    // matrix-core rate of each tile class on full waves of tiles, fitted to a
+    // sweep of sizes 700 .. 8192 at depths 0 .. 3 and n = 16384 at depths
+    // 0 .. 4 (16-bit: 1.45 / 1.0 / 0.55 PFLOP/s, binary32: 136 / 110 / 95
+    // TFLOP/s for 256 / 128 / 64-wide tiles)
+    const double rate = split ? (p.tile == 256 ? 1.45e15 : p.tile == 128 ? 1.0e15 : 0.55e15)
+                              : (p.tile == 256 ? 136e12 : p.tile == 128 ? 110e12 : 95e12);
     const double rows = (split && p.planes == 3 && p.tile == 256) ? 2.0 : 1.0;  // 256 x 128 tiles
-    const double tiles = (double)pow7(p.depth) * rows * (double)(p.leaf / p.tile) * (double)(p.leaf / p.tile);
-    const double fill = std::min(1.0, tiles / 256.0);   // share of the 256 CUs with a tile
     const double klen = (double)p.leaf / ((double)p.leaf + 128.0);   // per-tile start and store cost
-    int launches = 1 + (p.pad_a >= 0 ? 1 : 0) + (split ? 1 : 0) + (p.scale >= 0 ? 2 : 0);
-    for (int l = 0; l < p.fp32_levels; ++l) launches += p.div_slots[l] > 0 ? 1 : 0;
-    launches += p.depth >= 2 ? p.depth - 1 : p.depth;
+    ModelParts m;
+    m.tiles = (double)pow7(p.depth) * rows * (double)(p.leaf / p.tile) * (double)(p.leaf / p.tile);
+    m.gemm_s = w.mfma_flops / (rate * klen);
+    m.launches = 1 + (p.pad_a >= 0 ? 1 : 0) + (split ? 1 : 0) + (p.scale >= 0 ? 2 : 0);
+    for (int l = 0; l < p.fp32_levels; ++l) m.launches += p.div_slots[l] > 0 ? 1 : 0;
+    m.launches += p.depth >= 2 ? p.depth - 1 : p.depth;
+    if (p.peel) m.launches += 1;
     const double bytes = w.divide_bytes + w.split_bytes + w.combine_bytes + w.pad_bytes + w.peel_bytes;
-    if (p.peel) launches += 1;
-    // streaming rates fitted to measured depth choices: the 16-bit paths' split and
-    // combine move their bytes faster than the binary32 divide
-    const double bw = split ? 5e12 : 4e12;
-    // peeled plans: border and fix-up products on the vector units
-    const double peel_s = w.peel_flops / kPeelRate;
-    return w.mfma_flops / (rate * fill * klen) + bytes / bw + launches * 6e-6 + peel_s;
+    // streaming rates of the same fit (the binary32 divide and combine run
+    // near the 5 TB/s they reach alone; the split passes that write binary16
+    // planes lower); peeled plans: border and fix-up products on the vector
+    // units
+    const double bw = split ? 3e12 : 5e12;
+    m.stream_s = bytes / bw + w.peel_flops / kPeelRate;
+    return m;
 }
 
-int model_depth(int64_t n, int precision) {
+double wave_fill(double tiles) {
+    // waves of 256 tiles: the last one partly empty (576 tiles take three)
+    return tiles > 0.0 ? tiles / (256.0 * std::ceil(tiles / 256.0)) : 1.0;
+}
+
+double model_seconds(const Plan& p) {
+    const ModelParts m = model_parts(p);
+    return m.gemm_s / wave_fill(m.tiles) + m.stream_s + m.launches * 6e-6;
+}
+
+int model_max_depth(int64_t n, int precision) {
     // BF16X3 loses about a factor 2 of accuracy per level (16-bit split):
     // at most one level keeps it near 1e-5
     int dmax = std::min(max_depth_for(n), 3);
     if ((precision & STARK_PRECISION_MASK) == STARK_BF16X3) dmax = std::min(dmax, 1);
+    return dmax;
+}
+
+int model_depth(int64_t n, int precision) {
+    const int dmax = model_max_depth(n, precision);
     int best = 0;
     double best_s = 0.0;
     for (int d = 0; d <= dmax; ++d) {

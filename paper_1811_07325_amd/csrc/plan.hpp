@@ -69,12 +69,28 @@ struct Work {
 };
 Work plan_work(const Plan& p);
 
-// Rough time of a plan on one MI355X (seconds): matrix-core work at the
-// measured rate of its tile class, scaled down when its tiles leave CUs
-// idle and for short K (leaf / (leaf + 128)), streaming bytes at 5 TB/s
-// (16-bit paths) or 4 TB/s (binary32), and 6 us per launch.  Only used to
-// choose a depth where nothing has been measured.
+// Parts of the modelled time of a plan on one MI355X: the leaf GEMM on full
+// waves of tiles (matrix-core work at the measured rate of its tile class,
+// scaled for short K by leaf / (leaf + 128)), its tile count, the streaming
+// passes (bytes at 3 TB/s on the 16-bit paths, 5 TB/s on binary32, plus the
+// peeled border's vector flops) and the launch count.
+struct ModelParts {
+    double gemm_s, tiles, stream_s;
+    int launches;
+};
+ModelParts model_parts(const Plan& p);
+
+// Share of the CUs a launch of `tiles` tiles keeps busy over its waves of
+// 256 (the last wave partly empty).
+double wave_fill(double tiles);
+
+// Rough time of one plan alone (seconds): gemm_s / wave_fill(tiles) +
+// stream_s + 6 us per launch.  Only used to choose a depth where nothing
+// has been measured.
 double model_seconds(const Plan& p);
+
+// Deepest level model_depth considers for (n, precision): 3, BF16X3 1.
+int model_max_depth(int64_t n, int precision);
 
 // Depth (0..3) of least model_seconds for (n, precision); BF16X3 at most 1.
 int model_depth(int64_t n, int precision);
