@@ -150,8 +150,8 @@ def run_batched(S, torch, st, count: int = 64, seed: int = 7) -> dict:
     2048, 3000, 4096} (odd sizes padded), binary32 uniform[-1, 1] operands, in
     one stark_gemm_batched call (every leaf of every problem in one grouped
     launch, graph-captured), at depths 0..2 (clamped per problem) and with
-    STARK_DEPTH_AUTO (each problem at the model's depth for its size);
-    Freivalds' check on every product of the fastest setting."""
+    STARK_DEPTH_AUTO (the batch planner's depth, padding and tile class per
+    problem); Freivalds' check on every product of the fastest setting."""
     from paper_1811_07325_amd import inputs
     rng = np.random.default_rng(seed)
     sizes = [int(x) for x in rng.choice([256, 384, 1000, 1024, 2048, 3000, 4096], count)]

@@ -238,11 +238,15 @@ stark_status stark_tune(stark_ctx* ctx, const float* A, const float* B, float* C
  * of device pointers / sizes), all in one precision, at `depth` (clamped per
  * problem to stark_max_depth) or, with depth = STARK_DEPTH_AUTO, each problem
  * at its autotuner record (depth and tile class) if the context has one for
- * (n[i], p), else at stark_model_depth(n[i], p) -- the autotuner itself is
- * not run.  Every recursion level of every problem is one launch, and all
- * leaf products of all problems form one grouped launch per tile class; the
- * sequence is captured once into a hipGraph and replayed.
- * Errors as stark_gemm. */
+ * (n[i], p); the other problems are planned together (the autotuner itself is
+ * not run): for each, the depth (up to 3; BF16X3 up to 1) and padding of
+ * least modelled time on a tile class, where the other problems' tiles fill
+ * the waves, and the batch takes one tile class for all of them (a single
+ * leaf-GEMM launch) unless its model finds per-problem classes faster (see
+ * stark_plan_batched).  Every recursion level of every problem is one
+ * launch, and all leaf products of all problems form one grouped launch per
+ * tile class, the problems with the longest leaves first; the sequence is
+ * captured once into a hipGraph and replayed.  Errors as stark_gemm. */
 stark_status stark_gemm_batched(stark_ctx* ctx, int count, const float* const* A,
                                 const float* const* B, float* const* C, const int64_t* n,
                                 int depth, stark_precision p, void* stream);
@@ -365,6 +369,15 @@ typedef struct {
 } stark_plan_desc;
 
 stark_status stark_plan_info(int64_t n, int depth, stark_precision p, stark_plan_desc* out);
+
+/* Plans stark_gemm_batched gives `count` problems of edges n[] (host array)
+ * at `depth` (or STARK_DEPTH_AUTO) in precision p: out[i] (host array of
+ * count) receives problem i's plan as stark_plan_info describes it.  ctx
+ * supplies the autotuner records STARK_DEPTH_AUTO takes; it may be NULL (no
+ * records).  Host work only.  Errors: EINVAL (count <= 0, NULL n or out, a
+ * problem without a plan), EUNSUPPORTED (precision). */
+stark_status stark_plan_batched(stark_ctx* ctx, int count, const int64_t* n, int depth, stark_precision p,
+                                stark_plan_desc* out);
 
 /* Phases for stark_gemm_phases. */
 #define STARK_PHASE_DIVIDE 1u   /* pad, divide levels and the 16-bit split        */

@@ -1,7 +1,8 @@
 // Batched multiplies: many independent problems of uneven sizes share every
 // launch.  Level l of the divide covers the level-l nodes of every problem
 // deep enough to have them; one grouped persistent launch per leaf-tile class
-// (128- or 64-wide tiles) multiplies every leaf of every problem; the combine
+// multiplies every leaf of every problem (the batch planner puts them all on
+// one class unless its model finds mixed classes faster); the combine
 // levels mirror the divide.  The problem table and the per-launch block
 // prefixes live in a small device buffer owned by the cache entry, and the
 // launch sequence is captured into a hipGraph the second time the same batch
@@ -115,22 +116,37 @@ stark_status enqueue(stark_ctx* ctx, const BatchEntry& e, hipStream_t st) {
 
 }  // namespace
 
-stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, const float* const* B, float* const* C,
-                          const int64_t* n, int depth, int precision, hipStream_t st) {
-    std::vector<Plan> plans(count);
-    std::vector<size_t> off(count);
-    size_t total = 0;
+std::string plan_batched(stark_ctx* ctx, int count, const int64_t* n, int depth, int precision,
+                         std::vector<Plan>& plans) {
+    plans.assign(count, Plan());
+    std::vector<char> fixed(count, 0);
     for (int i = 0; i < count; ++i) {
-        int d, tile = 0;
-        if (depth == STARK_DEPTH_AUTO) {   // the problem's autotuner record, else the model's depth
+        int d = 0, tile = 0;
+        if (depth == STARK_DEPTH_AUTO) {   // the problem's autotuner record, else planned with the batch
+            if (!ctx) continue;
             auto it = ctx->tune.find({n[i], precision});
-            if (it != ctx->tune.end()) { d = it->second.depth; tile = it->second.tile; }
-            else d = model_depth(n[i], precision);
+            if (it == ctx->tune.end()) continue;
+            d = it->second.depth;
+            tile = it->second.tile;
         } else {
             d = std::min(depth, max_depth_for(n[i]));
         }
         const std::string why = make_plan(n[i], d, precision, plans[i], tile);
-        if (!why.empty()) { set_error("problem %d: %s", i, why.c_str()); return STARK_EINVAL; }
+        if (!why.empty()) return "problem " + std::to_string(i) + ": " + why;
+        fixed[i] = 1;
+    }
+    if (depth == STARK_DEPTH_AUTO) return plan_batch(count, n, precision, plans, fixed);
+    return "";
+}
+
+stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, const float* const* B, float* const* C,
+                          const int64_t* n, int depth, int precision, hipStream_t st) {
+    std::vector<Plan> plans;
+    const std::string why = plan_batched(ctx, count, n, depth, precision, plans);
+    if (!why.empty()) { set_error("%s", why.c_str()); return STARK_EINVAL; }
+    std::vector<size_t> off(count);
+    size_t total = 0;
+    for (int i = 0; i < count; ++i) {
         off[i] = total;
         total += (plans[i].bytes + 255) / 256 * 256;
     }
@@ -162,9 +178,20 @@ stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, cons
         e.planes = plans[0].planes;
         e.fp16 = plans[0].scale >= 0;
         e.variant = plans[0].variant;
+        // The table lists the problems with the longest leaves (the longest
+        // tiles) first: a grouped launch takes its tiles in table order, so
+        // the short ones fill the last waves.
+        std::vector<int> ord(count);
+        for (int i = 0; i < count; ++i) ord[i] = i;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return plans[a].leaf > plans[b].leaf; });
         std::vector<ProbDesc> descs(count);
-        for (int i = 0; i < count; ++i)
-            descs[i] = make_desc(plans[i], A[i], B[i], C[i], static_cast<char*>(ctx->ws) + off[i]);
+        std::vector<Plan> table_plans(count);
+        for (int j = 0; j < count; ++j) {
+            const int i = ord[j];
+            table_plans[j] = plans[i];
+            descs[j] = make_desc(plans[i], A[i], B[i], C[i], static_cast<char*>(ctx->ws) + off[i]);
+        }
+        plans.swap(table_plans);   // from here on, in table order
         std::vector<int64_t> pre;
         auto add_launch = [&](LaunchKind kind, int level, int tile, auto blocks_of, bool fused = false) {
             BatchLaunch l{kind, level, tile, fused, 0, pre.size()};

@@ -131,7 +131,11 @@ stark_status tune_range(stark_ctx* ctx, const float* A, const float* B, float* C
 int gemm_grid(stark_ctx* ctx, int planes, int tile, int64_t tiles);
 int gemm_grid_cu(int num_cu, int planes, int tile, int64_t tiles);
 
-// Batched (batched.cpp).
+// Batched (batched.cpp).  plan_batched: the plans of stark_gemm_batched
+// (ctx may be null: no autotuner records; lock held otherwise); "" or an
+// error naming the problem.
+std::string plan_batched(stark_ctx* ctx, int count, const int64_t* n, int depth, int precision,
+                         std::vector<Plan>& plans);
 stark_status gemm_batched(stark_ctx* ctx, int count, const float* const* A, const float* const* B,
                           float* const* C, const int64_t* n, int depth, int precision, hipStream_t st);
 void batched_release(stark_ctx* ctx);

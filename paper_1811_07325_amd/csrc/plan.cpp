@@ -23,6 +23,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <stdexcept>
 
@@ -98,7 +99,8 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p, int tile) {
     // adds the padded edge's share of the recursion's work.  The candidate of
     // least modelled time is taken (STARK_PEEL: the peeled one when there is
     // one; STARK_PAD: only padded ones); a forced tile class must divide the
-    // leaf of the candidate.
+    // leaf of the candidate, and where none does, n is padded to a multiple
+    // of the tile edge times 2^depth.
     const int64_t g = kLeafGranule << depth;
     const int64_t r = n % g;
     const bool can_peel = depth >= 1 && r >= 1 && r <= kPeelMaxResidue && n - r >= g;
@@ -130,6 +132,10 @@ std::string make_plan(int64_t n, int depth, int precision, Plan& p, int tile) {
             last = np;
             consider(0, granule);
         }
+        // a forced tile class no candidate allows: pad to its multiple even
+        // beyond the quarter (batches put small problems on the class of the
+        // rest)
+        if (!have && tile > 0) consider(0, tile);
     }
     return have ? "" : first_error;
 }
@@ -382,6 +388,88 @@ int model_depth(int64_t n, int precision) {
         if (d == 0 || s < best_s) { best = d; best_s = s; }
     }
     return best;
+}
+
+std::string plan_batch(int count, const int64_t* n, int precision, std::vector<Plan>& plans,
+                       const std::vector<char>& fixed) {
+    constexpr int kClasses[3] = {256, 128, 64};
+    struct Cand {
+        bool ok = false;
+        Plan p;
+        ModelParts m{};
+    };
+    // cand[i][c]: problem i's cheapest plan on tile class kClasses[c]
+    std::vector<std::array<Cand, 3>> cand(count);
+    for (int i = 0; i < count; ++i) {
+        if (fixed[i]) continue;
+        std::string first_error;
+        bool any = false;
+        for (int c = 0; c < 3; ++c)
+            for (int d = 0; d <= model_max_depth(n[i], precision); ++d) {
+                Plan p;
+                const std::string e = make_plan(n[i], d, precision, p, kClasses[c]);
+                if (!e.empty()) {
+                    if (first_error.empty()) first_error = e;
+                    continue;
+                }
+                const ModelParts m = model_parts(p);
+                Cand& k = cand[i][c];
+                if (!k.ok || m.gemm_s + m.stream_s < k.m.gemm_s + k.m.stream_s) {
+                    k.ok = true;
+                    k.p = p;
+                    k.m = m;
+                }
+                any = true;
+            }
+        if (!any) return "problem " + std::to_string(i) + ": " + first_error;
+    }
+    // choice[i]: class index of problem i; -1 for fixed problems
+    auto cost = [&](const std::vector<int>& choice) {
+        double gemm[3] = {0, 0, 0}, tiles[3] = {0, 0, 0}, stream = 0.0;
+        for (int i = 0; i < count; ++i) {
+            const Plan& p = choice[i] < 0 ? plans[i] : cand[i][choice[i]].p;
+            const ModelParts m = choice[i] < 0 ? model_parts(p) : cand[i][choice[i]].m;
+            const int c = p.tile == 256 ? 0 : p.tile == 128 ? 1 : 2;
+            gemm[c] += m.gemm_s;
+            tiles[c] += m.tiles;
+            stream += m.stream_s;
+        }
+        double t = stream;
+        for (int c = 0; c < 3; ++c)
+            if (tiles[c] > 0.0) t += gemm[c] / wave_fill(tiles[c]) + 6e-6;
+        return t;
+    };
+    std::vector<int> best, choice(count);
+    double best_t = 0.0;
+    auto consider = [&]() {
+        const double t = cost(choice);
+        if (best.empty() || t < best_t) {
+            best = choice;
+            best_t = t;
+        }
+    };
+    for (int c = 0; c < 3; ++c) {   // one class for the whole batch
+        bool ok = true;
+        for (int i = 0; i < count && ok; ++i) {
+            choice[i] = fixed[i] ? -1 : c;
+            ok = fixed[i] || cand[i][c].ok;
+        }
+        if (ok) consider();
+    }
+    for (int i = 0; i < count; ++i) {   // every problem on its own best class
+        choice[i] = -1;
+        if (fixed[i]) continue;
+        for (int c = 0; c < 3; ++c) {
+            const Cand& k = cand[i][c];
+            if (k.ok && (choice[i] < 0 || k.m.gemm_s + k.m.stream_s <
+                                              cand[i][choice[i]].m.gemm_s + cand[i][choice[i]].m.stream_s))
+                choice[i] = c;
+        }
+    }
+    consider();
+    for (int i = 0; i < count; ++i)
+        if (best[i] >= 0) plans[i] = cand[i][best[i]].p;
+    return "";
 }
 
 }  // namespace stk

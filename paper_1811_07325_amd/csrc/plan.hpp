@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -94,5 +95,18 @@ int model_max_depth(int64_t n, int precision);
 
 // Depth (0..3) of least model_seconds for (n, precision); BF16X3 at most 1.
 int model_depth(int64_t n, int precision);
+
+// Plans of a batch whose problems share every launch (grouped multiplies
+// at the automatic depth).  Problems with fixed[i] keep plans[i]; each of
+// the others takes, for a given tile class, its depth (0 ..
+// model_max_depth) and padding of least gemm_s + stream_s: in a batch the
+// other problems' tiles fill the waves, so a problem's own fill does not
+// count.  The batch takes the cheaper of: every problem on one tile class
+// (a single leaf GEMM launch), or each on its own best class; a choice
+// costs, per class, the summed GEMM time over its launch's wave fill, plus
+// every streaming pass, plus 6 us per GEMM launch.  Returns "" or the
+// first problem's error.
+std::string plan_batch(int count, const int64_t* n, int precision, std::vector<Plan>& plans,
+                       const std::vector<char>& fixed);
 
 }  // namespace stk

@@ -245,11 +245,7 @@ stark_status stark_workspace_size(int64_t n, int depth, stark_precision prec, si
     return STARK_OK;
 }
 
-stark_status stark_plan_info(int64_t n, int depth, stark_precision prec, stark_plan_desc* out) {
-    if (!out) { set_error("out is NULL"); return STARK_EINVAL; }
-    Plan p;
-    const std::string why = make_plan(n, depth, (int)prec, p);
-    if (!why.empty()) { set_error("%s", why.c_str()); return STARK_EINVAL; }
+static void describe_plan(const Plan& p, stark_plan_desc* out) {
     std::memset(out, 0, sizeof *out);
     out->n = p.n;
     out->n_pad = p.np;
@@ -281,6 +277,32 @@ stark_status stark_plan_info(int64_t n, int depth, stark_precision prec, stark_p
     out->fused = p.fuse ? 1 : 0;
     out->peel = p.peel;
     out->peel_flops = w.peel_flops;
+}
+
+stark_status stark_plan_info(int64_t n, int depth, stark_precision prec, stark_plan_desc* out) {
+    if (!out) { set_error("out is NULL"); return STARK_EINVAL; }
+    Plan p;
+    const std::string why = make_plan(n, depth, (int)prec, p);
+    if (!why.empty()) { set_error("%s", why.c_str()); return STARK_EINVAL; }
+    describe_plan(p, out);
+    return STARK_OK;
+}
+
+stark_status stark_plan_batched(stark_ctx* ctx, int count, const int64_t* n, int depth, stark_precision prec,
+                                stark_plan_desc* out) {
+    if (count <= 0 || !n || !out) { set_error("bad batch arguments"); return STARK_EINVAL; }
+    if (planes_for((int)prec) < 0) { set_error("unknown precision %d", (int)prec); return STARK_EUNSUPPORTED; }
+    if (depth < 0 && depth != STARK_DEPTH_AUTO) { set_error("depth must be >= 0 or STARK_DEPTH_AUTO"); return STARK_EINVAL; }
+    std::vector<Plan> plans;
+    std::string why;
+    if (ctx) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        why = plan_batched(ctx, count, n, depth, (int)prec, plans);
+    } else {
+        why = plan_batched(nullptr, count, n, depth, (int)prec, plans);
+    }
+    if (!why.empty()) { set_error("%s", why.c_str()); return STARK_EINVAL; }
+    for (int i = 0; i < count; ++i) describe_plan(plans[i], &out[i]);
     return STARK_OK;
 }
 

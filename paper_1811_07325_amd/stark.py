@@ -120,6 +120,7 @@ def _load() -> ctypes.CDLL:
         "stark_row_errors": ([P, I64, P, I64, P, P, P], I),
         "stark_generate_normal": ([P, I64, ctypes.c_uint64, P], I),
         "stark_plan_info": ([I64, I, I, ctypes.POINTER(stark_plan_desc)], I),
+        "stark_plan_batched": ([P, I, ctypes.POINTER(I64), I, I, ctypes.POINTER(stark_plan_desc)], I),
         "stark_gemm_phases": ([P, P, P, P, I64, I, I, ctypes.c_uint, P], I),
         "stark_workspace": ([P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)], I),
         "stark_tune": ([P, P, P, P, I64, I, I, I, ctypes.c_double, ctypes.POINTER(stark_tune_point), I,
@@ -290,6 +291,16 @@ def stark_plan_info(n: int, depth: int, precision: int) -> stark_plan_desc:
     d = stark_plan_desc()
     _check("stark_plan_info", _lib.stark_plan_info(n, depth, precision, ctypes.byref(d)))
     return d
+
+
+def stark_plan_batched(ctx, ns, depth: int, precision: int) -> list:
+    """Plans stark_gemm_batched gives the problems of edges `ns` (ctx may be
+    None: no autotuner records)."""
+    count = len(ns)
+    out = (stark_plan_desc * count)()
+    nn = (ctypes.c_int64 * count)(*ns)
+    _check("stark_plan_batched", _lib.stark_plan_batched(ctx, count, nn, depth, precision, out))
+    return list(out)
 
 
 def stark_gemm_phases(ctx, A, B, C, n: int, depth: int, precision: int, mask: int, stream=None) -> None:

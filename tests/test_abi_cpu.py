@@ -3,6 +3,7 @@ declares, and its pure host functions (planner, argument checks) behave."""
 import ctypes
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_1811_07325_amd import build as _build  # noqa: F401  (import check)
@@ -300,6 +301,42 @@ def test_model_depth(S):
     assert S.stark_model_depth(16384, 0) == 3
     assert S.stark_model_depth(3000, 1) == 1
     assert S.stark_model_depth(0, 0) == -1 and S.stark_model_depth(100, 999) == -1
+
+
+def test_plan_batched(S):
+    """Plans of grouped multiplies at the automatic depth (no autotuner
+    records): in a batch the other problems fill the waves, so each problem
+    takes the depth and padding of least GEMM plus streaming time on a tile
+    class, and the 64-problem workload of sizes {256, ..., 4096} runs on one
+    class -- a single leaf-GEMM launch -- n = 384 padded to 512 for it (beyond
+    the quarter a single multiply allows), 4096 recursing (binary32); a fixed
+    depth plans every problem as stark_plan_info does; a batch whose small
+    problems would pad 64 -> 256 keeps them on the 64-wide class."""
+    rng = np.random.default_rng(7)
+    sizes = [int(x) for x in rng.choice([256, 384, 1000, 1024, 2048, 3000, 4096], 64)]
+    for prec in (0, 1, 3):
+        plans = S.stark_plan_batched(None, sizes, S.STARK_DEPTH_AUTO, prec)
+        assert {p.gemm_tile for p in plans} == {256}
+        for n, p in zip(sizes, plans):
+            assert p.n == n and p.n_pad >= n and p.n_pad % (256 << p.depth) == 0
+            assert p.depth <= (1 if prec == 1 else 3)
+        by = {n: p for n, p in zip(sizes, plans)}
+        assert by[384].n_pad == 512 and S.stark_plan_info(384, 0, prec).n_pad == 384
+    fp32 = {n: p for n, p in zip(sizes, S.stark_plan_batched(None, sizes, S.STARK_DEPTH_AUTO, 0))}
+    assert fp32[4096].depth >= 1 and fp32[256].depth == 0
+    fixed = S.stark_plan_batched(None, sizes, 1, 0)
+    for n, p in zip(sizes, fixed):
+        q = S.stark_plan_info(n, min(1, S.stark_max_depth(n)), 0)
+        assert (p.depth, p.gemm_tile, p.n_pad, p.peel) == (q.depth, q.gemm_tile, q.n_pad, q.peel)
+    mixed = S.stark_plan_batched(None, [4096] + [64] * 300, S.STARK_DEPTH_AUTO, 0)
+    assert mixed[0].gemm_tile == 256 and {p.gemm_tile for p in mixed[1:]} == {64}
+    assert all(p.n_pad == 64 for p in mixed[1:])
+    with pytest.raises(S.StarkError):
+        S.stark_plan_batched(None, [], S.STARK_DEPTH_AUTO, 0)
+    with pytest.raises(S.StarkError):
+        S.stark_plan_batched(None, [256, 0], S.STARK_DEPTH_AUTO, 0)
+    with pytest.raises(S.StarkError):
+        S.stark_plan_batched(None, [256], S.STARK_DEPTH_AUTO, 999)
 
 
 def test_plan_work_figures(S):

@@ -88,22 +88,36 @@ def test_batched_float_equal_to_single_and_replays(S, ctx):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batched_auto_depth_per_problem(S, tmp_path, prec):
-    """STARK_DEPTH_AUTO in a batch: every problem runs at its own plan -- its
-    autotuner record if the context has one (here n = 2048, from the cache
-    file: depth 1, 128-wide tiles), else stark_model_depth -- and equals the
-    single call with that plan bit for bit."""
+    """STARK_DEPTH_AUTO in a batch: a problem with an autotuner record runs
+    at it (here n = 2048, from the cache file: depth 1, 128-wide tiles), the
+    others at the batch planner's plans (stark_plan_batched: one tile class
+    for all of them here); each result equals the single call with the same
+    depth and tile class (given to a second context as records) bit for
+    bit."""
     sizes = [256, 1000, 2048, 3000, 4096, 700]
-    depths = [S.stark_model_depth(n, prec) for n in sizes]
-    assert len(set(depths)) > 1                  # the batch mixes depths
     path = tmp_path / f"tune_{prec}.txt"
     path.write_text(f"# n precision depth ms freivalds_error tile\n2048 {prec} 1 1.0 0.0 128\n")
     c = S.stark_create(0, tuner_cache=str(path))
+    plans = S.stark_plan_batched(c, sizes, S.STARK_DEPTH_AUTO, prec)
+    assert (plans[2].depth, plans[2].gemm_tile) == (1, 128)
+    assert len({p.gemm_tile for i, p in enumerate(plans) if i != 2}) == 1
+    assert len({p.depth for p in plans}) > 1                  # the batch mixes depths
+    ref_path = tmp_path / f"ref_{prec}.txt"
+    ref_path.write_text("# n precision depth ms freivalds_error tile\n" + "".join(
+        f"{n} {prec} {p.depth} 1.0 0.0 {p.gemm_tile}\n" for n, p in zip(sizes, plans)))
+    cref = S.stark_create(0, tuner_cache=str(ref_path))
     try:
         As = [inputs.uniform(n, 500 + i) for i, n in enumerate(sizes)]
         Bs = [inputs.uniform(n, 600 + i) for i, n in enumerate(sizes)]
         dA = [dev(a) for a in As]
         dB = [dev(b) for b in Bs]
         dC = [torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda") for n in sizes]
+        refs = []
+        for i, n in enumerate(sizes):
+            ref = torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda")
+            S.stark_gemm(cref, dA[i], dB[i], ref, n, S.STARK_DEPTH_AUTO, prec, None)
+            refs.append(ref)
+        torch.cuda.synchronize()
         for rep in range(3):                     # eager, capture, replay
             for x in dC:
                 x.fill_(float("nan"))
@@ -111,16 +125,13 @@ def test_batched_auto_depth_per_problem(S, tmp_path, prec):
             S.stark_gemm_batched(c, dA, dB, dC, sizes, S.STARK_DEPTH_AUTO, prec, None)
             torch.cuda.synchronize()
             for i, n in enumerate(sizes):
-                ref = torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda")
-                d = S.STARK_DEPTH_AUTO if n == 2048 else depths[i]   # the record, else the model's depth
-                S.stark_gemm(c, dA[i], dB[i], ref, n, d, prec, None)
-                torch.cuda.synchronize()
-                assert torch.equal(dC[i], ref), (rep, n)
+                assert torch.equal(dC[i], refs[i]), (rep, n)
         rows = inputs.sample_rows(3000, 16, 9)
         err = oracle.rel_frobenius(dC[3].cpu().numpy()[rows], oracle.rows_f64(As[3], Bs[3], rows))
         assert err < (2e-6 if prec == 0 else 2e-5)
     finally:
         S.stark_destroy(c)
+        S.stark_destroy(cref)
 
 
 def test_batched_64_uneven_problems(S):
