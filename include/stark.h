@@ -329,9 +329,13 @@ stark_status stark_row_errors(const float* C, int64_t n, const int64_t* rows, in
                               const double* ref, double* out, void* stream);
 
 /* Fill X (n x n binary32, device) with normal(0,1) values from `seed`:
- * Philox4x32-10 (Salmon et al., SC'11) counter stream, each value the sum of
- * twelve 24-bit uniforms minus 6 (Irwin-Hall, mean 0, variance 1), exactly
- * reproducible on any host. */
+ * Philox4x32-10 (Salmon et al., SC'11) counter stream: elements 4m .. 4m+3
+ * (row-major) take one Philox call (counters m_lo, m_hi, 0, 0; key = seed);
+ * words (w0, w1) and (w2, w3) each give uniforms u1 = (w + 1) 2^-32 in
+ * (0, 1] and u2 = w' 2^-32 and the Box-Muller pair sqrt(-2 ln u1) cos(2 pi
+ * u2), sqrt(-2 ln u1) sin(2 pi u2) in binary32 (independent normal(0, 1);
+ * magnitude at most 6.7).  A host repeating the steps in binary64 agrees to
+ * a few binary32 ulps. */
 stark_status stark_generate_normal(float* X, int64_t n, uint64_t seed, void* stream);
 
 /* ------------------------------------------------------------------------ */

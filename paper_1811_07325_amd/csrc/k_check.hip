@@ -82,20 +82,38 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
     return Philox4{{c0, c1, c2, c3}};
 }
 
-// Element e: twelve 24-bit uniforms from counters (e_lo, e_hi, j, 0), j=0..2,
-// key (seed_lo, seed_hi); value = (sum - 6*2^24) * 2^-24 (Irwin-Hall, mean 0,
-// variance 1).  The integer sum is exact and its conversion rounds to nearest
-// even, so any host reproduces the value bit for bit.
+// Elements 4m .. 4m + 3: two Box-Muller pairs (Box and Muller, 1958) from
+// one Philox call, counters (m_lo, m_hi, 0, 0), key (seed_lo, seed_hi).
+// Pair j (words w_2j, w_2j+1): u1 = (w_2j + 1) 2^-32 in (0, 1] and
+// u2 = w_2j+1 2^-32 (each rounded to binary32; the scaling is exact),
+// radius sqrt(-2 ln u1), angle 2 pi u2; element 4m + 2j takes radius x
+// cos(angle), element 4m + 2j + 1 radius x sin(angle): independent normal(0,
+// 1) variates, at most 6.7 in magnitude.  Binary32 arithmetic throughout
+// (the library's logf, sincosf and sqrtf, within a few ulps): a host
+// repeating the steps in binary64 from the same binary32 u1, u2 agrees to a
+// few binary32 ulps of the radius.
+__device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, float& z0, float& z1) {
+    const float u1 = (float)((uint64_t)w1 + 1) * 0x1p-32f, u2 = (float)w2 * 0x1p-32f;
+    const float radius = sqrtf(-2.0f * logf(u1));
+    float sn, cs;
+    sincosf(6.28318530717958647692f * u2, &sn, &cs);
+    z0 = radius * cs;
+    z1 = radius * sn;
+}
+
 __global__ __launch_bounds__(256) void k_generate_normal(float* __restrict__ X, int64_t count, uint64_t seed) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= count) return;
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    int32_t s = 0;
-    for (uint32_t j = 0; j < 3; ++j) {
-        const Philox4 r = philox4x32_10((uint32_t)e, (uint32_t)((uint64_t)e >> 32), j, 0u, k0, k1);
-        s += (int32_t)(r.v[0] >> 8) + (int32_t)(r.v[1] >> 8) + (int32_t)(r.v[2] >> 8) + (int32_t)(r.v[3] >> 8);
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (4 * m >= count) return;
+    const Philox4 r = philox4x32_10((uint32_t)m, (uint32_t)((uint64_t)m >> 32), 0u, 0u, (uint32_t)seed,
+                                    (uint32_t)(seed >> 32));
+    float z[4];
+    box_muller(r.v[0], r.v[1], z[0], z[1]);
+    box_muller(r.v[2], r.v[3], z[2], z[3]);
+    if (4 * m + 4 <= count) {
+        *reinterpret_cast<float4*>(X + 4 * m) = make_float4(z[0], z[1], z[2], z[3]);
+    } else {
+        for (int j = 0; j < 4 && 4 * m + j < count; ++j) X[4 * m + j] = z[j];
     }
-    X[e] = (float)(s - 6 * (1 << 24)) * (1.0f / 16777216.0f);
 }
 
 // Deterministic binary64 sum of X: kSumBlocks blocks sum contiguous chunks
@@ -144,7 +162,7 @@ hipError_t launch_row_errors(const float* C, int64_t n, const int64_t* rows, int
     return hipGetLastError();
 }
 hipError_t launch_generate_normal(float* X, int64_t count, uint64_t seed, hipStream_t st) {
-    const int64_t blocks = (count + 255) / 256;
+    const int64_t blocks = ((count + 3) / 4 + 255) / 256;   // one thread per four elements
     hipLaunchKernelGGL(k_generate_normal, dim3((unsigned)blocks), dim3(256), 0, st, X, count, seed);
     return hipGetLastError();
 }

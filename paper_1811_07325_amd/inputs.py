@@ -68,15 +68,25 @@ def philox4x32_10(c0, c1, c2, c3, k0, k1):
 
 
 def philox_normal(n: int, seed: int) -> np.ndarray:
-    """n x n float32 with mean 0, variance 1: for element e, the sum of twelve
-    24-bit uniforms (top bits of Philox outputs for counters (e_lo, e_hi, j, 0),
-    j = 0..2, key (seed_lo, seed_hi)) minus 6, times 2^-24 (Irwin-Hall)."""
-    e = np.arange(n * n, dtype=np.uint64)
-    lo, hi = e & _M32, e >> np.uint64(32)
+    """n x n float32 normal(0, 1) variates, elements 4m .. 4m + 3 (row-major)
+    from the Philox outputs w0..w3 for counters (m_lo, m_hi, 0, 0), key
+    (seed_lo, seed_hi): pair j takes u1 = float32(w_2j + 1) 2^-32, u2 =
+    float32(w_2j+1) 2^-32, radius sqrt(-2 ln u1) (float64 here) and the
+    float32 angle float32(2 pi) u2, element 4m + 2j = radius x cos(angle), 4m + 2j + 1 = radius x
+    sin(angle), rounded to float32 -- the device generator's steps, which it
+    takes in float32 with its own log, sin, cos and sqrt: the two agree to a
+    few float32 ulps of the radius."""
+    count = n * n
+    m = np.arange((count + 3) // 4, dtype=np.uint64)
+    lo, hi = m & _M32, m >> np.uint64(32)
     k0, k1 = np.uint64(seed) & _M32, np.uint64(seed) >> np.uint64(32)
-    s = np.zeros(n * n, dtype=np.int64)
-    for j in range(3):
-        for w in philox4x32_10(lo, hi, np.uint64(j), np.uint64(0), k0, k1):
-            s += (w >> np.uint32(8)).astype(np.int64)
-    v = (s - 6 * (1 << 24)).astype(np.float32) * np.float32(1.0 / 16777216.0)
-    return v.reshape(n, n)
+    w = [x.astype(np.uint64) for x in philox4x32_10(lo, hi, np.uint64(0), np.uint64(0), k0, k1)]
+    v = np.empty(4 * m.size, dtype=np.float32)
+    for j in range(2):
+        u1 = (w[2 * j] + np.uint64(1)).astype(np.float32).astype(np.float64) * 2.0 ** -32
+        u2 = w[2 * j + 1].astype(np.float32) * np.float32(2.0 ** -32)
+        radius = np.sqrt(-2.0 * np.log(u1))
+        angle = (np.float32(6.2831855) * u2).astype(np.float64)     # the binary32 angle
+        v[2 * j::4] = (radius * np.cos(angle)).astype(np.float32)
+        v[2 * j + 1::4] = (radius * np.sin(angle)).astype(np.float32)
+    return v[:count].reshape(n, n)

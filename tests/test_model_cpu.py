@@ -96,11 +96,22 @@ def test_philox_known_answers():
 
 
 def test_philox_normal_moments():
-    x = inputs.philox_normal(512, 11).astype(np.float64)
+    """The serving generator's host twin draws normal(0, 1): moments up to
+    the fourth (a sum of twelve uniforms would show kurtosis 2.9), the tail
+    mass beyond 3 and 4 standard deviations, and Kolmogorov-Smirnov against
+    the normal CDF over 2^18 values."""
+    from scipy import stats
+    x = inputs.philox_normal(512, 11).astype(np.float64).ravel()
     assert abs(x.mean()) < 0.01 and abs(x.var() - 1.0) < 0.01
-    assert np.all(np.abs(x) <= 6.0)
-    # exactly reproducible: value * 2^24 is an integer
-    assert np.array_equal(x * 2.0 ** 24, np.round(x * 2.0 ** 24))
+    assert abs(stats.skew(x)) < 0.03 and abs(stats.kurtosis(x, fisher=False) - 3.0) < 0.05
+    for t in (3.0, 4.0):
+        expect = 2 * stats.norm.sf(t) * x.size
+        assert abs(np.sum(np.abs(x) > t) - expect) < 5 * np.sqrt(expect)
+    assert stats.kstest(x, "norm").pvalue > 1e-3
+    assert np.all(np.abs(x) <= 6.7)
+    # other seeds give other values; the same seed the same ones
+    assert not np.array_equal(inputs.philox_normal(64, 11), inputs.philox_normal(64, 12))
+    assert np.array_equal(inputs.philox_normal(64, 11), inputs.philox_normal(512, 11).ravel()[:4096].reshape(64, 64))
 
 
 def test_f16_rounding_matches_library():
