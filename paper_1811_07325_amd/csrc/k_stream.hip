@@ -356,11 +356,12 @@ __device__ __forceinline__ void seven(int side, float x11, float x12, float x21,
 //
 // A block covers a kSplitRows x 64 tile of output positions; thread t owns
 // rows kSplitRPT*(t/16).. and columns 4*(t%16)..+3 of it, read as float4
-// (16 threads cover a 256-byte row segment).  A side: each thread stores
-// 8-byte pieces; a tile fills whole 1 KB blocks per output and plane.  B
-// side: the tile of each output and plane is transposed through LDS (rows of
+// (16 threads cover a 256-byte row segment).  A side: the tile of each
+// output and plane goes through LDS (rows of 64 + 8 16-bit terms) and is
+// written back in 16-byte chunks, one whole 1 KB block of the blocked layout
+// per wave store.  B side: the tile is transposed through LDS (rows of
 // kSplitRows + 8 16-bit terms) and written back in 16-byte chunks of T^T
-// rows, kSplitRound outputs at a time.
+// rows.  Both sides take kSplitRound outputs at a time.
 #ifndef STK_SPLIT_ROWS
 #define STK_SPLIT_ROWS 32
 #endif
@@ -463,20 +464,49 @@ __device__ __forceinline__ void split_body(const ProbDesc& d, int side, int64_t 
         fp16 ? ldexpf(1.0f, reinterpret_cast<const int*>(reinterpret_cast<const float*>(d.ws) + d.scale)[2 * kScaleParts + side])
              : 1.0f;
 
+    constexpr int R = NOUT == 1 ? 1 : SplitRound<P>::R;
     if (side == 0) {
+        // staged through LDS (rows of 64 + 8 16-bit terms) so that each
+        // wave store writes one whole 1 KB block of the blocked layout:
+        // lane l of a block takes row 16 rb + l / 4 and chunk 4 kb + l % 4
+        constexpr int ROWA = kSplitTile + 8;
+        constexpr int TILE_A = kSplitRows * ROWA;
+        static_assert(TILE_A <= kSplitTile * kSplitLdsRow, "A tile fits the LDS of a B tile");
+        constexpr int BLOCKS = (kSplitRows / 16) * (kSplitTile / 32);   // 1 KB blocks per output and plane
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o)
+        for (int o0 = 0; o0 < NOUT; o0 += R) {
 #pragma unroll
-            for (int i = 0; i < kSplitRPT; ++i) {
-                uint32_t pl[P][2];
-                splitN<P, 4>(v[o][i], pl, fp16, scale);
+            for (int oo = 0; oo < R; ++oo) {
+                if (o0 + oo >= NOUT) break;
+#pragma unroll
+                for (int i = 0; i < kSplitRPT; ++i) {
+                    uint32_t pl[P][2];
+                    splitN<P, 4>(v[o0 + oo][i], pl, fp16, scale);
+#pragma unroll
+                    for (int p = 0; p < P; ++p)
+                        store_terms<4>(lds + (oo * P + p) * TILE_A + (ri + i) * ROWA + ci, pl[p]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int oo = 0; oo < R; ++oo) {
+                if (o0 + oo >= NOUT) break;
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    store_terms<4>(base + ((int64_t)o * P + p) * LL + blk_offset(R0 + ri + i, C0 + ci, L), pl[p]);
+#pragma unroll
+                    for (int h = 0; h < BLOCKS * 64 / kStreamThreads; ++h) {
+                        const int id = tid + kStreamThreads * h;
+                        const int blk = id >> 6, l = id & 63;
+                        const int row = 16 * (blk >> 1) + (l >> 2), chunk = 4 * (blk & 1) + (l & 3);
+                        const uint4 val = *reinterpret_cast<const uint4*>(lds + (oo * P + p) * TILE_A + row * ROWA + 8 * chunk);
+                        *reinterpret_cast<uint4*>(base + ((int64_t)(o0 + oo) * P + p) * LL +
+                                                  blk_offset(R0 + row, C0 + 8 * chunk, L)) = val;
+                    }
             }
+            __syncthreads();
+        }
         return;
     }
-    constexpr int R = NOUT == 1 ? 1 : SplitRound<P>::R;
     constexpr int TILE_U16 = kSplitTile * kSplitLdsRow;     // 64 rows of T^T
 #pragma unroll
     for (int o0 = 0; o0 < NOUT; o0 += R) {
