@@ -134,6 +134,32 @@ def test_batched_auto_depth_per_problem(S, tmp_path, prec):
         S.stark_destroy(cref)
 
 
+def test_batched_auto_mixed_tile_classes(S):
+    """A batch the planner splits over two tile classes (BF16X3: one 4096
+    problem on 256-wide tiles, 100 problems of 64 on 64-wide ones, where
+    padding them to 256 would cost 64 times their work): integer inputs,
+    every result exact, eager, captured and replayed."""
+    sizes = [4096] + [64] * 100
+    plans = S.stark_plan_batched(None, sizes, S.STARK_DEPTH_AUTO, 1)
+    assert plans[0].gemm_tile == 256 and {p.gemm_tile for p in plans[1:]} == {64}
+    c = S.stark_create(0)
+    try:
+        As = [inputs.integers(n, 700 + i, -8, 8) for i, n in enumerate(sizes)]
+        Bs = [inputs.integers(n, 900 + i, -8, 8) for i, n in enumerate(sizes)]
+        exact = [(a.astype(np.float64) @ b.astype(np.float64)).astype(np.float32) for a, b in zip(As, Bs)]
+        dA = [dev(a) for a in As]
+        dB = [dev(b) for b in Bs]
+        for rep in range(3):
+            dC = [torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda") for n in sizes]
+            torch.cuda.synchronize()
+            S.stark_gemm_batched(c, dA, dB, dC, sizes, S.STARK_DEPTH_AUTO, 1, None)
+            torch.cuda.synchronize()
+            for i in range(len(sizes)):
+                assert np.array_equal(dC[i].cpu().numpy(), exact[i]), (rep, i)
+    finally:
+        S.stark_destroy(c)
+
+
 def test_batched_64_uneven_problems(S):
     """64 problems, n drawn from {256, 384, 1000, 1024, 2048, 3000, 4096}, FP32,
     uniform[-1, 1]; every problem against the FP64 oracle on sampled rows."""
