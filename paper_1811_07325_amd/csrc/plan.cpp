@@ -335,11 +335,11 @@ ModelParts model_parts(const Plan& p) {
     const Work w = plan_work(p);
     const bool split = p.planes > 0;
     // matrix-core rate of each tile class on full waves of tiles, fitted to a
-    // sweep of sizes 700 .. 8192 at depths 0 .. 3 and n = 16384 at depths
-    // 0 .. 4 (16-bit: 1.45 / 1.0 / 0.55 PFLOP/s, binary32: 136 / 110 / 95
+    // sweep of sizes 700 .. 12288 at depths 0 .. 3 and n = 16384 at depths
+    // 0 .. 4 (16-bit: 1.45 / 1.0 / 0.55 PFLOP/s, binary32: 125 / 110 / 95
     // TFLOP/s for 256 / 128 / 64-wide tiles)
     const double rate = split ? (p.tile == 256 ? 1.45e15 : p.tile == 128 ? 1.0e15 : 0.55e15)
-                              : (p.tile == 256 ? 136e12 : p.tile == 128 ? 110e12 : 95e12);
+                              : (p.tile == 256 ? 125e12 : p.tile == 128 ? 110e12 : 95e12);
     const double rows = (split && p.planes == 3 && p.tile == 256) ? 2.0 : 1.0;  // 256 x 128 tiles
     const double klen = (double)p.leaf / ((double)p.leaf + 128.0);   // per-tile start and store cost
     ModelParts m;
@@ -354,7 +354,7 @@ ModelParts model_parts(const Plan& p) {
     // near the 5 TB/s they reach alone; the split passes that write binary16
     // planes lower); peeled plans: border and fix-up products on the vector
     // units
-    const double bw = split ? 3e12 : 5e12;
+    const double bw = split ? 3.5e12 : 5e12;
     m.stream_s = bytes / bw + w.peel_flops / kPeelRate;
     return m;
 }
@@ -366,7 +366,7 @@ double wave_fill(double tiles) {
 
 double model_seconds(const Plan& p) {
     const ModelParts m = model_parts(p);
-    return m.gemm_s / wave_fill(m.tiles) + m.stream_s + m.launches * 6e-6;
+    return m.gemm_s / wave_fill(m.tiles) + m.stream_s + m.launches * 10e-6;
 }
 
 int model_max_depth(int64_t n, int precision) {
@@ -436,7 +436,7 @@ std::string plan_batch(int count, const int64_t* n, int precision, std::vector<P
         }
         double t = stream;
         for (int c = 0; c < 3; ++c)
-            if (tiles[c] > 0.0) t += gemm[c] / wave_fill(tiles[c]) + 6e-6;
+            if (tiles[c] > 0.0) t += gemm[c] / wave_fill(tiles[c]) + 10e-6;
         return t;
     };
     std::vector<int> best, choice(count);

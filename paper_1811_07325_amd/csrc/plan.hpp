@@ -73,7 +73,7 @@ Work plan_work(const Plan& p);
 // Parts of the modelled time of a plan on one MI355X: the leaf GEMM on full
 // waves of tiles (matrix-core work at the measured rate of its tile class,
 // scaled for short K by leaf / (leaf + 128)), its tile count, the streaming
-// passes (bytes at 3 TB/s on the 16-bit paths, 5 TB/s on binary32, plus the
+// passes (bytes at 3.5 TB/s on the 16-bit paths, 5 TB/s on binary32, plus the
 // peeled border's vector flops) and the launch count.
 struct ModelParts {
     double gemm_s, tiles, stream_s;
@@ -86,7 +86,7 @@ ModelParts model_parts(const Plan& p);
 double wave_fill(double tiles);
 
 // Rough time of one plan alone (seconds): gemm_s / wave_fill(tiles) +
-// stream_s + 6 us per launch.  Only used to choose a depth where nothing
+// stream_s + 10 us per launch.  Only used to choose a depth where nothing
 // has been measured.
 double model_seconds(const Plan& p);
 
@@ -104,7 +104,7 @@ int model_depth(int64_t n, int precision);
 // count.  The batch takes the cheaper of: every problem on one tile class
 // (a single leaf GEMM launch), or each on its own best class; a choice
 // costs, per class, the summed GEMM time over its launch's wave fill, plus
-// every streaming pass, plus 6 us per GEMM launch.  Returns "" or the
+// every streaming pass, plus 10 us per GEMM launch.  Returns "" or the
 // first problem's error.
 std::string plan_batch(int count, const int64_t* n, int precision, std::vector<Plan>& plans,
                        const std::vector<char>& fixed);

@@ -328,7 +328,7 @@ def test_plan_batched(S):
     for n, p in zip(sizes, fixed):
         q = S.stark_plan_info(n, min(1, S.stark_max_depth(n)), 0)
         assert (p.depth, p.gemm_tile, p.n_pad, p.peel) == (q.depth, q.gemm_tile, q.n_pad, q.peel)
-    mixed = S.stark_plan_batched(None, [4096] + [64] * 300, S.STARK_DEPTH_AUTO, 0)
+    mixed = S.stark_plan_batched(None, [4096] + [64] * 300, S.STARK_DEPTH_AUTO, S.STARK_BF16X3)
     assert mixed[0].gemm_tile == 256 and {p.gemm_tile for p in mixed[1:]} == {64}
     assert all(p.n_pad == 64 for p in mixed[1:])
     with pytest.raises(S.StarkError):
