@@ -327,6 +327,12 @@ __device__ __forceinline__ void gemm16_lds(Src src, int64_t total_tiles) {
 // to the compiler, so a per-lane offset added afterwards stays a 32-bit
 // vector offset (the load's scalar-base form) instead of the compiler
 // hoisting (uniform part + lane part) of every load into vector registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ const char* scalar_ptr(const void* p) {
     const uint64_t v = reinterpret_cast<uint64_t>(p);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -363,22 +369,39 @@ __device__ __forceinline__ void gemm16_pingpong(Src src, int64_t total_tiles) {
     const int64_t slot = xcd_slot(blockIdx.x, G);
 
     for (int64_t t = slot; t < total_tiles; t += G) {
+        // Everything a tile's K loop needs is uniform across the workgroup.
+        // Read from a device problem table it would land in vector
+        // registers, beside the accumulators and fragments, so there it is
+        // moved to scalar registers first and the epilogue's values are
+        // read after the loop (a kernel-argument descriptor is scalar
+        // already).
+        constexpr bool kTable = !std::is_same<Src, OneProb>::value;
+        auto uni = [](int64_t v) { return kTable ? uniform64(v) : v; };
         int64_t local;
-        const ProbDesc& d = src.get(src.locate(t, local));
-        const int64_t L = d.leaf, LL = L * L;
+        int pi = src.locate(t, local);
+        if constexpr (kTable) pi = __builtin_amdgcn_readfirstlane(pi);
+        local = uni(local);
+        const ProbDesc& d = src.get(pi);
+        const int64_t L = uni(d.leaf), LL = L * L;
         const int64_t tm_cnt = L / BM, tn_cnt = L / BN, tpl = tm_cnt * tn_cnt;
         const int64_t leaf = local / tpl;
         int64_t tm, tn;
         tile_coords(local - leaf * tpl, tm_cnt, tn_cnt, tm, tn);
-        const uint16_t* Ah = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_a + leaf * P * LL;
-        const uint16_t* Bh = reinterpret_cast<const uint16_t*>(d.ws) + d.leaf_b + leaf * P * LL;
+        const uint16_t* ws16 = reinterpret_cast<const uint16_t*>(kTable ? scalar_ptr(d.ws) : d.ws);
+        const uint16_t* Ah = ws16 + uni(d.leaf_a) + leaf * P * LL;
+        const uint16_t* Bh = ws16 + uni(d.leaf_b) + leaf * P * LL;
+        const int64_t m0 = tm * BM, n0 = tn * BN;
         float* Cp;
         int64_t ldc;
-        if (d.depth == 0) { Cp = d.C; ldc = d.ldu; }
-        else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
-        const bool crop = d.depth == 0 && d.bounded0;
-        const Unscale unscale = unscale_of(d);
-        const int64_t m0 = tm * BM, n0 = tn * BN;
+        bool crop;
+        Unscale unscale;
+        auto epilogue_args = [&] {
+            if (d.depth == 0) { Cp = d.C; ldc = d.ldu; }
+            else { Cp = reinterpret_cast<float*>(d.ws) + d.leaf_m + leaf * LL; ldc = L; }
+            crop = d.depth == 0 && d.bounded0;
+            unscale = unscale_of(d);
+        };
+        if constexpr (!kTable) epilogue_args();
 
         // direct copies, as in gemm16_lds, by the four waves of group 0:
         // block row g of a side of plane p (one contiguous 1 KB block per K
@@ -479,6 +502,7 @@ __device__ __forceinline__ void gemm16_pingpong(Src src, int64_t total_tiles) {
         }
         if (grp == 0) boundary();                               // phase 2 KT: group 1 computes step KT - 1
 
+        if constexpr (kTable) epilogue_args();
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -495,9 +519,9 @@ __device__ __forceinline__ void gemm16_pingpong(Src src, int64_t total_tiles) {
 
 template <class Src, int P, bool F16>
 __global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_t total_tiles) {
-    // the ping-pong kernel for single problems (with a device problem table
-    // its extra descriptor registers would spill)
-    if constexpr (P == 2 && STK_PINGPONG && std::is_same<Src, OneProb>::value)
+    // the ping-pong kernel for two planes, single problems and problem
+    // tables alike (its tile set-up lives in scalar registers)
+    if constexpr (P == 2 && STK_PINGPONG)
         gemm16_pingpong<Src, F16>(src, total_tiles);
     else
         gemm16_lds<BigCfg<P>, Src, P, F16>(src, total_tiles);
