@@ -344,14 +344,12 @@ __device__ __forceinline__ const char* scalar_ptr(const void* p) {
 #define STK_PINGPONG 1
 #endif
 
-template <class Src, bool F16>
+template <class Src, int P, bool F16>
 __device__ __forceinline__ void gemm16_pingpong(Src src, int64_t total_tiles) {
     using VT = typename Op16<F16>::T;
-    using Cfg = BigCfg<2>;
-    constexpr int P = 2;
+    using Cfg = BigCfg<P>;
     constexpr int BM = Cfg::BM, BN = Cfg::BN, NW = Cfg::NW, WAVES_N = Cfg::WAVES_N;
-    static_assert(Cfg::STAGES == 2 && BM == 256 && BN == 256 && NW == 8 && Cfg::WAVES_M == 2,
-                  "two groups of four waves, two stages");
+    static_assert(Cfg::STAGES == 2 && NW == 8 && Cfg::WAVES_M % 2 == 0, "two groups of four waves, two stages");
     constexpr int BK = 32, KC = BK / 8;
     constexpr int ROWS = BM + BN;
     constexpr int UNITS = P * ROWS * KC;
@@ -363,7 +361,9 @@ __device__ __forceinline__ void gemm16_pingpong(Src src, int64_t total_tiles) {
     // the wave index is uniform across a wave: readfirstlane lets the
     // compiler keep it, and the copies' base addresses, in scalar registers
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int grp = w / WAVES_N, wn = w % WAVES_N;     // group = wave row of the tile
+    // group = upper or lower half of the tile's wave rows; waves w and
+    // w + 4 share a SIMD and sit in different groups
+    const int wm = w / WAVES_N, wn = w % WAVES_N, grp = w / (NW / 2);
     const int li = lane & 15, lg = lane >> 4;
     const int64_t G = gridDim.x;
     const int64_t slot = xcd_slot(blockIdx.x, G);
@@ -452,7 +452,7 @@ __device__ __forceinline__ void gemm16_pingpong(Src src, int64_t total_tiles) {
                 }
 #pragma unroll
                 for (int i = 0; i < TM; ++i) {
-                    const int row = grp * WM + 16 * i + li;
+                    const int row = wm * WM + 16 * i + li;
                     a[i][p] = __builtin_bit_cast(VT, sl[(p * ROWS + row) * KC + (lg ^ blk_swz(row))]);
                 }
             }
@@ -509,7 +509,7 @@ __device__ __forceinline__ void gemm16_pingpong(Src src, int64_t total_tiles) {
             for (int j = 0; j < TN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int64_t row = m0 + grp * WM + 16 * i + 4 * lg + r;
+                    const int64_t row = m0 + wm * WM + 16 * i + 4 * lg + r;
                     const int64_t col = n0 + wn * WN + 16 * j + li;
                     if (!crop || (row < d.n && col < d.n)) Cp[row * ldc + col] = unscale(acc[i][j][r]);
                 }
@@ -519,10 +519,10 @@ __device__ __forceinline__ void gemm16_pingpong(Src src, int64_t total_tiles) {
 
 template <class Src, int P, bool F16>
 __global__ __launch_bounds__(BigCfg<P>::NT) void k_gemm_bf16_big(Src src, int64_t total_tiles) {
-    // the ping-pong kernel for two planes, single problems and problem
-    // tables alike (its tile set-up lives in scalar registers)
-    if constexpr (P == 2 && STK_PINGPONG)
-        gemm16_pingpong<Src, F16>(src, total_tiles);
+    // the ping-pong kernel for single problems and problem tables alike
+    // (its tile set-up lives in scalar registers)
+    if constexpr (STK_PINGPONG)
+        gemm16_pingpong<Src, P, F16>(src, total_tiles);
     else
         gemm16_lds<BigCfg<P>, Src, P, F16>(src, total_tiles);
 }
