@@ -177,6 +177,27 @@ def test_n16384_headline_path_within_tolerance(S, ctx, big_inputs):
     assert 0.25 * freiv <= tuned[2] <= 4 * freiv
 
 
+@pytest.mark.parametrize("name,depth", [("fp32", 3), ("bf16x6", 2), ("fp16x3_winograd", 2)])
+def test_n16384_other_paths_within_tolerance(S, ctx, big_inputs, name, depth):
+    """The comparison paths the benchmark reports at n = 16384 (binary32
+    leaves at depth 3, the six-product bf16 split, Winograd's variant with
+    binary16 leaves): 256 sampled rows and Freivalds' check within 1e-5 of
+    the FP64 product."""
+    n, A, B, dA, dB = big_inputs
+    prec = S.PRECISIONS[name]
+    C = torch.full((n, n), float("nan"), dtype=torch.float32, device="cuda")
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    S.stark_gemm(ctx, dA, dB, C, n, depth, prec, st)
+    st.synchronize()
+    err, mabs, freiv = row_and_freivalds_errors(S, st, dA, dB, C, A, B, n)
+    print(f"n=16384 {name} depth {depth}: rel_frob(256 rows)={err:.3e} max_abs={mabs:.3e} freivalds={freiv:.3e}",
+          flush=True)
+    assert bool(torch.isfinite(C).all())
+    assert err <= HEADLINE_TOL and freiv <= HEADLINE_TOL
+    assert 0.25 * err <= freiv <= 4 * err
+
+
 def test_n16384_bf16x3_error_grows_with_depth(S, ctx, big_inputs):
     """Documents why BF16X3 is not the headline: a two-term bf16 split keeps
     16 significant bits (about 4.4e-6 at depth 0) and every Strassen level
