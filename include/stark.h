@@ -335,7 +335,8 @@ stark_status stark_row_errors(const float* C, int64_t n, const int64_t* rows, in
  * (0, 1] and u2 = w' 2^-32 and the Box-Muller pair sqrt(-2 ln u1) cos(2 pi
  * u2), sqrt(-2 ln u1) sin(2 pi u2) in binary32 (independent normal(0, 1);
  * magnitude at most 6.7).  A host repeating the steps in binary64 agrees to
- * a few binary32 ulps. */
+ * a few binary32 ulps.  X: n x n device binary32, 16-byte aligned (EINVAL
+ * otherwise, as for NULL X or n <= 0). */
 stark_status stark_generate_normal(float* X, int64_t n, uint64_t seed, void* stream);
 
 /* ------------------------------------------------------------------------ */

@@ -476,6 +476,7 @@ stark_status stark_row_errors(const float* C, int64_t n, const int64_t* rows, in
 
 stark_status stark_generate_normal(float* X, int64_t n, uint64_t seed, void* stream) {
     if (!X || n <= 0) { set_error("bad generator arguments"); return STARK_EINVAL; }
+    if ((uintptr_t)X & 15) { set_error("X must be 16-byte aligned"); return STARK_EINVAL; }
     STK_HIP(launch_generate_normal(X, n * n, seed, static_cast<hipStream_t>(stream)));
     return STARK_OK;
 }

@@ -303,6 +303,14 @@ def test_model_depth(S):
     assert S.stark_model_depth(0, 0) == -1 and S.stark_model_depth(100, 999) == -1
 
 
+def test_generator_argument_errors(S):
+    """The device generator refuses NULL, n <= 0 and misaligned X before
+    touching the device."""
+    for ptr, n in ((None, 4), (64, 0), (68, 4), (72, 4)):
+        with pytest.raises(S.StarkError):
+            S.stark_generate_normal(ptr, n, 1, None)
+
+
 def test_plan_batched(S):
     """Plans of grouped multiplies at the automatic depth (no autotuner
     records): in a batch the other problems fill the waves, so each problem
