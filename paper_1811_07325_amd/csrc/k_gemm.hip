@@ -538,12 +538,15 @@ __global__ __launch_bounds__(SmallCfg<P>::NT) void k_gemm_bf16_small(Src src, in
 // ---------------------------------------------------------------------------
 // binary32 leaf GEMM: BM x BN block tile (256 x 256 with 8 waves of 128 x 64
 // for large leaves; 128 x 128 or 64 x 64 with 4 waves otherwise), K steps of
-// 16, two LDS stages filled by direct global->LDS loads straight from the
+// 16, LDS stages filled by direct global->LDS loads straight from the
 // binary32 operands (views included: leading dimension from the recursion),
-// no register staging.  Measured for the 256-wide tile at n = 16384: two
-// stages 43.2 ms (depth 3) and 63.0 ms (depth 0), three 45.1 / 65.7, four
-// 44.1 / 64.5; for the 128-wide tile at n = 2048, depth 1: two 0.154 ms,
-// three 0.164, four 0.153.
+// no register staging.  The 256-wide tile meets its waves at one barrier
+// per two K steps (four stages of 32 KB, two groups of two); the smaller
+// tiles at one per step (two stages).  Measured for the 256-wide tile at
+// n = 16384: two steps per barrier 41.9 ms (depth 3) and 62.3 ms (depth 0);
+// one step per barrier with two stages 43.0 / 62.7, three 45.1 / 65.7,
+// four 44.1 / 64.5; for the 128-wide tile at n = 2048, depth 1: two stages
+// 0.154 ms, three 0.164, four 0.153.
 //   A stage image: [BM rows][4 chunks of 4 k], chunk position c ^ blk_swz(row
 //     mod 16) (as the 16-bit blocked layout), one load = one 16-row block.
 //   B stage image: [16 k][BN/4 chunks of 4 n], chunk position c ^ f32_bswz(k),
@@ -558,9 +561,10 @@ __device__ __forceinline__ int f32_bswz(int k) { return ((k >> 2) & 1) << 2; }
 
 constexpr int kF32BigThreads = 512;
 
-template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int STAGES_>
+template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int STAGES_, int SPB_ = 1>
 struct F32CfgT {
     static constexpr int BM = BM_, BN = BN_, WAVES_M = WAVES_M_, WAVES_N = WAVES_N_, STAGES = STAGES_;
+    static constexpr int SPB = SPB_;                   // K steps per barrier
     static constexpr int NW = WAVES_M * WAVES_N, NT = 64 * NW;
 };
 #ifndef STK_F32_STAGES
@@ -569,9 +573,17 @@ struct F32CfgT {
 #ifndef STK_F32_SMALL_STAGES
 #define STK_F32_SMALL_STAGES 2
 #endif
-using F32BigCfg = F32CfgT<256, 256, 2, 4, STK_F32_STAGES>;   // 8 waves of 128 x 64, 32 KB LDS per stage
+#ifndef STK_F32_SPB
+#define STK_F32_SPB 2
+#endif
+#ifndef STK_F32_MID_SPB
+#define STK_F32_MID_SPB 1
+#endif
+using F32BigCfg = F32CfgT<256, 256, 2, 4, STK_F32_SPB == 1 ? STK_F32_STAGES : 2 * STK_F32_SPB,
+                          STK_F32_SPB>;   // 8 waves of 128 x 64, 32 KB LDS per stage
 using F32FusedCfg = F32CfgT<256, 256, 2, 4, 2>;  // the same with fused leaf operands, 128 KB LDS
-using F32MidCfg = F32CfgT<128, 128, 2, 2, STK_F32_SMALL_STAGES>;    // 4 waves of 64 x 64, 16 KB per stage
+using F32MidCfg = F32CfgT<128, 128, 2, 2, STK_F32_MID_SPB == 1 ? STK_F32_SMALL_STAGES : 2 * STK_F32_MID_SPB,
+                          STK_F32_MID_SPB>;    // 4 waves of 64 x 64, 16 KB per stage
 using F32SmallCfg = F32CfgT<64, 64, 2, 2, STK_F32_SMALL_STAGES>;    // 4 waves of 32 x 32, 8 KB per stage
 static_assert(F32BigCfg::NT == kF32BigThreads, "thread count of the 256-wide kernel");
 
@@ -621,7 +633,7 @@ __device__ __forceinline__ float4 flip_add(float4 a, float4 b, uint32_t neg) {
 template <class Cfg, class Src, bool FUSE>
 __device__ __forceinline__ void gemm32_lds(Src src, int64_t total_tiles) {
     constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = 16, NW = Cfg::NW, WAVES_N = Cfg::WAVES_N;
-    constexpr int STAGES = Cfg::STAGES;
+    constexpr int STAGES = Cfg::STAGES, SPB = Cfg::SPB;
     constexpr int WM = BM / Cfg::WAVES_M, WN = BN / WAVES_N, TM = WM / 16, TN = WN / 16;
     constexpr int AU = BM * BK / 4;                    // 16-byte units of one A term per stage
     constexpr int BU = BK * BN / 4;                    // of one B term
@@ -708,23 +720,10 @@ __device__ __forceinline__ void gemm32_lds(Src src, int64_t total_tiles) {
                 for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
             const int64_t KT = L / BK;
-#pragma unroll
-            for (int s = 0; s < STAGES - 1; ++s)
-                if (s < KT) issue(s, s * BK);
-            for (int64_t kt = 0; kt < KT; ++kt) {
-                if (kt + STAGES - 2 < KT) wait_vmcnt<LPS * (STAGES - 2)>();
-                else wait_vmcnt<0>();
-                lds_barrier();       // step kt landed for every wave; step kt-1's reads are done
-                // Every fragment of the step is read before the copies of a
-                // later step are issued: the compiler cannot tell the stages
-                // apart and makes LDS reads wait for every copy issued before
-                // them, which would stall each step for the whole latency of
-                // its new copies.
-                const uint4* sl = lds[stage_of<STAGES>(kt)];
+            // Fragments of one K step from a stage image, and its MFMAs.
+            auto read_step = [&](const uint4* sl, float (&b)[TN][4], float4 (&a)[TM]) {
                 const float* sb = reinterpret_cast<const float*>(sl + B1_OFF);
                 const float* sb2 = reinterpret_cast<const float*>(sl + B2_OFF);
-                float b[TN][4];
-                float4 a[TM];
 #pragma unroll
                 for (int j = 0; j < TN; ++j) {
                     const int col = wn * WN + 16 * j + li;
@@ -743,7 +742,8 @@ __device__ __forceinline__ void gemm32_lds(Src src, int64_t total_tiles) {
                     a[i] = __builtin_bit_cast(float4, sl[e]);
                     if constexpr (kTA) a[i] = flip_add(a[i], __builtin_bit_cast(float4, sl[A2_OFF + e]), nega);
                 }
-                if (kt + STAGES - 1 < KT) issue(refill_stage_of<STAGES>(kt), (kt + STAGES - 1) * BK);
+            };
+            auto mfma_step = [&](const float (&b)[TN][4], const float4 (&a)[TM]) {
 #pragma unroll
                 for (int i = 0; i < TM; ++i) {
 #pragma unroll
@@ -753,6 +753,56 @@ __device__ __forceinline__ void gemm32_lds(Src src, int64_t total_tiles) {
                         for (int j = 0; j < TN; ++j)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[j][s], acc[i][j], 0, 0, 0);
                     }
+                }
+            };
+            if constexpr (SPB == 1) {
+#pragma unroll
+                for (int s = 0; s < STAGES - 1; ++s)
+                    if (s < KT) issue(s, s * BK);
+                for (int64_t kt = 0; kt < KT; ++kt) {
+                    if (kt + STAGES - 2 < KT) wait_vmcnt<LPS * (STAGES - 2)>();
+                    else wait_vmcnt<0>();
+                    lds_barrier();       // step kt landed for every wave; step kt-1's reads are done
+                    // Every fragment of the step is read before the copies of a
+                    // later step are issued: the compiler cannot tell the stages
+                    // apart and makes LDS reads wait for every copy issued before
+                    // them, which would stall each step for the whole latency of
+                    // its new copies.
+                    float b[TN][4];
+                    float4 a[TM];
+                    read_step(lds[stage_of<STAGES>(kt)], b, a);
+                    if (kt + STAGES - 1 < KT) issue(refill_stage_of<STAGES>(kt), (kt + STAGES - 1) * BK);
+                    mfma_step(b, a);
+                }
+            } else {
+                // SPB K steps per barrier over a ring of 2 SPB stages: the
+                // steps of group g sit in stages SPB (g & 1) .. SPB (g & 1) +
+                // SPB - 1; after the barrier every wave runs the group's
+                // steps (the fragments of a step read during the MFMAs of the
+                // one before), issuing the copies of group g + 1 into the
+                // stages of group g - 1 (read by every wave before this
+                // barrier) once its last step's fragments are read.  KT is a
+                // multiple of SPB (the leaf edge is a multiple of BM).
+                static_assert(STAGES == 2 * SPB, "a ring of two groups");
+#pragma unroll
+                for (int h = 0; h < SPB; ++h) issue(h, h * BK);
+                for (int64_t kt = 0; kt < KT; kt += SPB) {
+                    wait_vmcnt<0>();
+                    lds_barrier();
+                    const int g0 = (int)((kt / SPB) & 1) * SPB;
+                    float b[TN][4];
+                    float4 a[TM];
+                    read_step(lds[g0], b, a);
+#pragma unroll
+                    for (int h = 1; h < SPB; ++h) {
+                        mfma_step(b, a);
+                        read_step(lds[g0 + h], b, a);
+                    }
+                    if (kt + SPB < KT) {
+#pragma unroll
+                        for (int h = 0; h < SPB; ++h) issue(SPB - g0 + h, (kt + SPB + h) * BK);
+                    }
+                    mfma_step(b, a);
                 }
             }
             __syncthreads();         // the next tile's first loads overwrite the stages
