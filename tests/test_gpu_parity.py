@@ -121,9 +121,11 @@ def test_integer_inputs_bit_exact(S, ctx, n, depth, prec):
 @pytest.mark.parametrize("n,depth,prec", [(4096, 1, "bf16x3"), (4096, 0, "bf16x6"), (4096, 1, "bf16x6"),
                                           (4032, 1, "bf16x3"), (4096, 1, "fp16x3"), (4096, 0, "fp32"),
                                           (4096, 1, "fp32"), (4032, 1, "fp32"), (4096, 1, "bf16x3_winograd"),
-                                          (4032, 1, "fp32_winograd")])
+                                          (4032, 1, "fp32_winograd"), (2048, 3, "fp32"), (2048, 2, "fp32")])
 def test_integer_inputs_bit_exact_large_tiles(S, ctx_big, n, depth, prec):
-    """Leaves wide enough for the 256-wide tile class."""
+    """Leaves wide enough for the 256-wide tile class (n = 2048 at depth 3:
+    leaves of 256, the shortest K loop of the binary32 kernel, whose steps
+    go two to a barrier)."""
     print(f"case n={n} depth={depth} prec={prec}", flush=True)
     assert S.stark_plan_info(n, depth, PREC[prec]).gemm_tile == 256
     A = inputs.integers(n, 0)
@@ -178,7 +180,8 @@ def test_float_inputs_match_model(S, ctx, n, depth, prec):
     assert e_gpu <= fixed_bound(prec, depth)
 
 
-@pytest.mark.parametrize("n,depth,prec", [(4096, 1, "fp32"), (4096, 1, "bf16x3"), (4096, 1, "fp32_winograd")])
+@pytest.mark.parametrize("n,depth,prec", [(4096, 1, "fp32"), (4096, 1, "bf16x3"), (4096, 1, "fp32_winograd"),
+                                          (2048, 3, "fp32")])
 def test_float_large_tiles_match_model(S, ctx_big, n, depth, prec):
     """The 256-wide tile kernels on float inputs: against the arithmetic
     model on every element, against the FP64 product on sampled rows."""
