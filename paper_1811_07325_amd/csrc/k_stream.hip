@@ -928,22 +928,28 @@ __global__ __launch_bounds__(kStreamThreads) void k_reduce_blocks(const float* P
 // columns peeled):
 //   right:  C[i][nc + y] for i < nc, y < r
 //   bottom: C[nc + y][j] for y < r, j < n
-// each the whole inner product over t = 0 .. n-1 in ascending order, one
-// fused multiply-add per term, in binary32 (exact for integers).  A block
+// each the whole inner product over t = 0 .. n-1 in binary32 (exact for
+// integers): for r <= 4 in ascending order, one fused multiply-add per term;
+// for larger r on the matrix cores (16 x 16 x 4 binary32 MFMAs, K ascending
+// in steps of four).  A block
 // owns 64 indices along the long side (right: rows i; bottom: columns j) and
 // every short-side index y < r (RB >= r of them, the rest zero).  K runs in
 // chunks of 64: the long side's 64 x 64 operand chunk and the short side's
 // RB x 64 chunk sit in LDS (rows padded to 68 floats, so 16-byte reads of 16
 // consecutive rows hit distinct banks) while the loads of the next chunk are
-// in flight in registers.  A thread owns TX long x TY short outputs
-// (RB 64: 4 x 4; 16: 1 x 4; 4: 1 x 1).
+// in flight in registers.  With RB = 4 a thread owns one output (vector
+// fused multiply-adds); with RB = 16 or 64 a wave owns 16 long x RB short
+// outputs on the matrix cores (the vector path read 2 LDS bytes per
+// multiply-add and was bound by LDS bandwidth: 2.6 ms for r = 64 at
+// n = 16448).
 // ---------------------------------------------------------------------------
 constexpr int kPeelStrip = 64, kPeelK = 64, kPeelLd = kPeelK + 4;
 
-template <int RB> struct PeelTile;
+template <int RB> struct PeelTile;   // thread tile of the vector path
 template <> struct PeelTile<4> { static constexpr int TX = 1, TY = 1; };
 template <> struct PeelTile<16> { static constexpr int TX = 1, TY = 4; };
 template <> struct PeelTile<64> { static constexpr int TX = 4, TY = 4; };
+typedef float peel_f32x4 __attribute__((ext_vector_type(4)));
 
 template <class Src, int RB>
 __global__ __launch_bounds__(kStreamThreads) void k_peel(Src src) {
@@ -1010,52 +1016,93 @@ __global__ __launch_bounds__(kStreamThreads) void k_peel(Src src) {
         }
     };
 
-    // outputs of this thread: long indices xa + XS i, short indices ya + YS j
-    const int xa = tid % XS, ya = tid / XS;
-    float acc[TX][TY];
-#pragma unroll
-    for (int i = 0; i < TX; ++i)
-#pragma unroll
-        for (int j = 0; j < TY; ++j) acc[i][j] = 0.0f;
     const int64_t KC = (n + kPeelK - 1) / kPeelK;
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    for (int64_t kc = 0; kc < KC; ++kc) {
-        const int buf = (int)(kc & 1);
-        if (kc + 1 < KC) fetch((kc + 1) * kPeelK);
-#pragma unroll 2
-        for (int t = 0; t < kPeelK; t += 4) {
-            float4 a[TX], b[TY];
+    if constexpr (RB >= 16) {
+        // Matrix cores: out[x][y] = sum_t big[x][t] sm[y][t] as 16 x 16 x 4
+        // binary32 MFMAs; wave wv owns long indices 16 wv .. 16 wv + 15 and
+        // every short index (RB / 16 tiles).  Lane (li, lg) supplies k = t +
+        // lg of row li of each operand (conflict-free: row stride 68 words).
+        constexpr int NTY = RB / 16;
+        const int li = lane & 15, lg = lane >> 4;
+        peel_f32x4 acc[NTY];
 #pragma unroll
-            for (int i = 0; i < TX; ++i) a[i] = *reinterpret_cast<const float4*>(&big[buf][xa + XS * i][t]);
-#pragma unroll
-            for (int j = 0; j < TY; ++j) b[j] = *reinterpret_cast<const float4*>(&sm[buf][ya + YS * j][t]);
-#pragma unroll
-            for (int i = 0; i < TX; ++i)
-#pragma unroll
-                for (int j = 0; j < TY; ++j) {
-                    acc[i][j] = fmaf(a[i].x, b[j].x, acc[i][j]);
-                    acc[i][j] = fmaf(a[i].y, b[j].y, acc[i][j]);
-                    acc[i][j] = fmaf(a[i].z, b[j].z, acc[i][j]);
-                    acc[i][j] = fmaf(a[i].w, b[j].w, acc[i][j]);
-                }
-        }
-        // the other buffer was last read in the previous chunk, before the
-        // barrier that ended it
-        if (kc + 1 < KC) stash(buf ^ 1);
+        for (int j = 0; j < NTY; ++j) acc[j] = peel_f32x4{0.f, 0.f, 0.f, 0.f};
+        fetch(0);
+        stash(0);
         __syncthreads();
-    }
+        for (int64_t kc = 0; kc < KC; ++kc) {
+            const int buf = (int)(kc & 1);
+            if (kc + 1 < KC) fetch((kc + 1) * kPeelK);
+#pragma unroll 4
+            for (int t = 0; t < kPeelK; t += 4) {
+                const float av = big[buf][16 * wv + li][t + lg];
 #pragma unroll
-    for (int i = 0; i < TX; ++i) {
-        const int64_t gx = s0 + xa + XS * i;
-        if (gx >= slen) continue;
+                for (int j = 0; j < NTY; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sm[buf][16 * j + li][t + lg], acc[j], 0, 0, 0);
+            }
+            // the other buffer was last read in the previous chunk, before the
+            // barrier that ended it
+            if (kc + 1 < KC) stash(buf ^ 1);
+            __syncthreads();
+        }
+        // lane (li, lg) holds out[16 wv + 4 lg + v][16 j + li], v = 0..3
 #pragma unroll
-        for (int j = 0; j < TY; ++j) {
-            const int y = ya + YS * j;
+        for (int j = 0; j < NTY; ++j) {
+            const int y = 16 * j + li;
             if (y >= r) continue;
-            if (right) d.C[gx * n + nc + y] = acc[i][j];
-            else d.C[(nc + y) * n + gx] = acc[i][j];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gx = s0 + 16 * wv + 4 * lg + v;
+                if (gx >= slen) continue;
+                if (right) d.C[gx * n + nc + y] = acc[j][v];
+                else d.C[(nc + y) * n + gx] = acc[j][v];
+            }
+        }
+    } else {
+        // outputs of this thread: long indices xa + XS i, short indices ya + YS j
+        const int xa = tid % XS, ya = tid / XS;
+        float acc[TX][TY];
+#pragma unroll
+        for (int i = 0; i < TX; ++i)
+#pragma unroll
+            for (int j = 0; j < TY; ++j) acc[i][j] = 0.0f;
+        fetch(0);
+        stash(0);
+        __syncthreads();
+        for (int64_t kc = 0; kc < KC; ++kc) {
+            const int buf = (int)(kc & 1);
+            if (kc + 1 < KC) fetch((kc + 1) * kPeelK);
+#pragma unroll 2
+            for (int t = 0; t < kPeelK; t += 4) {
+                float4 a[TX], b[TY];
+#pragma unroll
+                for (int i = 0; i < TX; ++i) a[i] = *reinterpret_cast<const float4*>(&big[buf][xa + XS * i][t]);
+#pragma unroll
+                for (int j = 0; j < TY; ++j) b[j] = *reinterpret_cast<const float4*>(&sm[buf][ya + YS * j][t]);
+#pragma unroll
+                for (int i = 0; i < TX; ++i)
+#pragma unroll
+                    for (int j = 0; j < TY; ++j) {
+                        acc[i][j] = fmaf(a[i].x, b[j].x, acc[i][j]);
+                        acc[i][j] = fmaf(a[i].y, b[j].y, acc[i][j]);
+                        acc[i][j] = fmaf(a[i].z, b[j].z, acc[i][j]);
+                        acc[i][j] = fmaf(a[i].w, b[j].w, acc[i][j]);
+                    }
+            }
+            if (kc + 1 < KC) stash(buf ^ 1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < TX; ++i) {
+            const int64_t gx = s0 + xa + XS * i;
+            if (gx >= slen) continue;
+#pragma unroll
+            for (int j = 0; j < TY; ++j) {
+                const int y = ya + YS * j;
+                if (y >= r) continue;
+                if (right) d.C[gx * n + nc + y] = acc[i][j];
+                else d.C[(nc + y) * n + gx] = acc[i][j];
+            }
         }
     }
 }
