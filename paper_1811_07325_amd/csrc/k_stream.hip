@@ -985,7 +985,77 @@ __global__ __launch_bounds__(kStreamThreads) void k_peel(Src src) {
         if (right) { y = e % RB; t = e / RB; }      // B row k0 + t, column nc + y
         else { t = e % kPeelK; y = e / kPeelK; }    // A row nc + y, column k0 + t
     };
+    // 16-byte loads where every row start and the border column nc are
+    // 16-byte aligned (n and r multiples of 4, A and B 16-byte aligned): a
+    // thread moves BPT / 4 and SPT / 4 float4, a wave four 256-byte row
+    // segments (or 16 rows of the 64-float column strip) per load
+    const bool vec = RB >= 16 && (n & 3) == 0 && (r & 3) == 0 && ((uintptr_t)d.A & 15) == 0 &&
+                     ((uintptr_t)d.B & 15) == 0;
+    constexpr int SQ = (SPT >= 4) ? RB / 4 : 1;     // float4 per short-side k-row
+    auto fetch4 = [&](int64_t k0) {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < BPT / 4; ++u) {
+            const int e = tid + kStreamThreads * u, c4 = e & 15, ln = e >> 4;
+            float4 v = z;
+            if (right) {   // A row s0 + ln, columns k0 + 4 c4 ..
+                const int64_t gx = s0 + ln, gt = k0 + 4 * c4;
+                if (gx < slen && gt < n) v = *reinterpret_cast<const float4*>(d.A + gx * n + gt);
+            } else {       // B row k0 + ln, columns s0 + 4 c4 ..
+                const int64_t gt = k0 + ln, gx = s0 + 4 * c4;
+                if (gx < slen && gt < n) v = *reinterpret_cast<const float4*>(d.B + gt * n + gx);
+            }
+            rb[4 * u] = v.x; rb[4 * u + 1] = v.y; rb[4 * u + 2] = v.z; rb[4 * u + 3] = v.w;
+        }
+#pragma unroll
+        for (int u = 0; u < SPT / 4; ++u) {
+            const int e = tid + kStreamThreads * u;
+            float4 v = z;
+            if (right) {   // B row k0 + t, columns nc + 4 y4 ..
+                const int y4 = e % SQ, t = e / SQ;
+                const int64_t gt = k0 + t;
+                if (4 * y4 < r && gt < n) v = *reinterpret_cast<const float4*>(d.B + gt * n + nc + 4 * y4);
+            } else {       // A row nc + y, columns k0 + 4 c4 ..
+                const int c4 = e & 15, y = e >> 4;
+                const int64_t gt = k0 + 4 * c4;
+                if (y < r && gt < n) v = *reinterpret_cast<const float4*>(d.A + (nc + y) * n + gt);
+            }
+            rs[4 * u] = v.x; rs[4 * u + 1] = v.y; rs[4 * u + 2] = v.z; rs[4 * u + 3] = v.w;
+        }
+    };
+    auto stash4 = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < BPT / 4; ++u) {
+            const int e = tid + kStreamThreads * u, c4 = e & 15, ln = e >> 4;
+            if (right) {
+                *reinterpret_cast<float4*>(&big[buf][ln][4 * c4]) =
+                    make_float4(rb[4 * u], rb[4 * u + 1], rb[4 * u + 2], rb[4 * u + 3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) big[buf][4 * c4 + q][ln] = rb[4 * u + q];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SPT / 4; ++u) {
+            const int e = tid + kStreamThreads * u;
+            if (right) {
+                const int y4 = e % SQ, t = e / SQ;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sm[buf][4 * y4 + q][t] = rs[4 * u + q];
+            } else {
+                const int c4 = e & 15, y = e >> 4;
+                *reinterpret_cast<float4*>(&sm[buf][y][4 * c4]) =
+                    make_float4(rs[4 * u], rs[4 * u + 1], rs[4 * u + 2], rs[4 * u + 3]);
+            }
+        }
+    };
     auto fetch = [&](int64_t k0) {
+        if constexpr (RB >= 16) {
+            if (vec) {
+                fetch4(k0);
+                return;
+            }
+        }
 #pragma unroll
         for (int u = 0; u < BPT; ++u) {
             int x, t;
@@ -1002,6 +1072,12 @@ __global__ __launch_bounds__(kStreamThreads) void k_peel(Src src) {
         }
     };
     auto stash = [&](int buf) {
+        if constexpr (RB >= 16) {
+            if (vec) {
+                stash4(buf);
+                return;
+            }
+        }
 #pragma unroll
         for (int u = 0; u < BPT; ++u) {
             int x, t;
